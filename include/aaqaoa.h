@@ -1,0 +1,200 @@
+/*
+ * aaqaoa.h -- C ABI of the MI355X (gfx950) MaxCut-QAOA statevector estimator.
+ *
+ * The library evaluates the p-layer QAOA state
+ *     |psi(gamma, beta)> = prod_{l=1..p} e^{-i beta_l H_M} e^{-i gamma_l H_C} |+>^n
+ * (QAOA section, eq. for |psi>_p; layer 1 is applied first and the cost unitary
+ * precedes the mixer in every layer, as written out in eq. A2), with the unweighted
+ * MaxCut Hamiltonian H_C = 1/2 sum_{(i,j) in E} (1 - Z_i Z_j) and the mixer
+ * H_M = sum_i X_i, and returns the expectation of either
+ *     H_C                                                      (AAQ_OBS_HC), or
+ *     H_red = 1/2 sum_m |S_m| (1 - Z_{i_m} Z_{j_m})            (AAQ_OBS_HRED)
+ * where (i_m, j_m) is a representative edge of Aut(G) edge orbit S_m ("Reducing
+ * the Hamiltonian" section).  On the Aut(G)-invariant QAOA state both are equal
+ * (Eq. exact); the library does not check that the supplied orbits are real
+ * Aut(G) orbits -- a wrong orbit list silently breaks that identity.  Use
+ * AAQ_AGG_PER_TERM with AAQ_OBS_HC to inspect per-edge <Z_i Z_j> within orbits.
+ *
+ * Conventions
+ *   - vertex v = qubit v = bit v of the amplitude index z (little-endian);
+ *   - gamma[l], beta[l] in radians, l = 0..p-1, l = 0 applied first;
+ *   - energies are <H> including the constant (the expected cut value, >= 0);
+ *   - the cost layer multiplies amplitude z by exp(-i gamma C(z)), C(z) = number
+ *     of cut edges (an exact integer), with gamma*C(z) reduced in FP64;
+ *   - amplitudes are complex64 (interleaved float re/im, 8 bytes) unless the call
+ *     asks for AAQ_PREC_C128 (complex128, 16 bytes); expectation and gradient
+ *     accumulations are FP64.
+ *
+ * Memory ownership
+ *   - Host arrays passed in are only read during the call.
+ *   - Device buffers (state, lambda, workspace, device outputs) are owned by the
+ *     caller.  The library never allocates device memory.
+ *   - Calls that return results through host pointers synchronise the stream.
+ *   - aaq_plan objects are host objects owned by the library (aaq_plan_destroy).
+ *
+ * Errors
+ *   Every entry point returns an aaq_status.  Arguments are validated on the host
+ *   before any HIP call; on error the outputs are left untouched and
+ *   aaq_last_error_message() (thread-local) explains the failure.  Nothing aborts.
+ */
+#ifndef AAQAOA_H
+#define AAQAOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AAQ_OK = 0,
+  AAQ_ERR_INVALID_ARG = 1, /* null pointer, bad enum, bad p or n               */
+  AAQ_ERR_GRAPH = 2,       /* vertex out of range, self-loop, duplicate edge   */
+  AAQ_ERR_ORBITS = 3,      /* orbit sizes do not sum to |E|, bad representative */
+  AAQ_ERR_PARAMS = 4,      /* non-finite gamma or beta                         */
+  AAQ_ERR_BUFFER = 5,      /* state / lambda / workspace buffer too small      */
+  AAQ_ERR_UNSUPPORTED = 6, /* valid request this build does not support        */
+  AAQ_ERR_HIP = 7          /* a HIP runtime call failed                        */
+} aaq_status;
+
+typedef enum { AAQ_OBS_HC = 0, AAQ_OBS_HRED = 1 } aaq_observable;
+
+/* How the expectation is aggregated (estimator cost section):
+ *   FUSED          -- one integer h(z) per amplitude, one pass (default);
+ *   PER_TERM       -- one <Z_i Z_j> accumulator per observable term in the same pass,
+ *                     energy = sum_t (w_t/2)(1 - <ZZ>_t); fills zz_out;
+ *   PASS_PER_TERM  -- the final state is written and every term's <Z_i Z_j> is a
+ *                     separate O(2^n) pass over it (the per-term estimator structure
+ *                     the paper describes; its cost grows with the number of terms). */
+typedef enum { AAQ_AGG_FUSED = 0, AAQ_AGG_PER_TERM = 1, AAQ_AGG_PASS_PER_TERM = 2 } aaq_aggregation;
+
+typedef enum { AAQ_PREC_C64 = 0, AAQ_PREC_C128 = 1 } aaq_precision;
+
+/* A MaxCut instance with its Aut(G) edge orbits (Algorithm 1 output).
+ *   n           qubits = vertices, 1 <= n <= 34
+ *   num_edges   |E| >= 0 (n = 1 requires 0)
+ *   edges       [2*|E|] pairs (u, v), 0 <= u, v < n, u != v, no duplicate edge
+ *   num_orbits  |O_E| (0 iff |E| = 0)
+ *   orbit_rep   [|O_E|] edge index of each orbit's representative (0 <= . < |E|)
+ *   orbit_size  [|O_E|] |S_m| >= 1, summing to |E|
+ *   edge_orbit  [|E|] orbit id of every edge, or NULL; when given, the library
+ *               checks that sizes and representatives agree with it. */
+typedef struct {
+  int32_t n;
+  int32_t num_edges;
+  const int32_t *edges;
+  int32_t num_orbits;
+  const int32_t *orbit_rep;
+  const int32_t *orbit_size;
+  const int32_t *edge_orbit;
+} aaq_problem;
+
+/* Host-side validation of a problem and depth p (1 <= p <= AAQ_MAX_P). No HIP calls. */
+#define AAQ_MAX_P 64
+#define AAQ_MAX_N 34
+aaq_status aaq_validate(const aaq_problem *prob, int p);
+
+/* Bytes of one state buffer (2^n amplitudes) at the given precision. */
+aaq_status aaq_state_bytes(const aaq_problem *prob, aaq_precision prec, size_t *bytes);
+
+/* Workspace bytes needed by aaq_energy / aaq_energy_grad for this problem, depth,
+ * gradient flag, observable, aggregation and precision. */
+aaq_status aaq_workspace_size(const aaq_problem *prob, int p, int with_grad, aaq_observable obs,
+                              aaq_aggregation agg, aaq_precision prec, size_t *bytes);
+
+/* <H> of the QAOA state (F_p, QAOA section; aggregation eq. of the estimator-cost
+ * section; H_red as in "Reducing the Hamiltonian").
+ *   d_state      device buffer of >= aaq_state_bytes; overwritten (for n > 14 it holds
+ *                intermediate states; its final contents are unspecified)
+ *   d_ws         device workspace of >= aaq_workspace_size bytes
+ *   stream       hipStream_t (NULL = default stream)
+ *   energy_out   host double
+ *   zz_out       host double[T] (T = |E| for H_C, |O_E| for H_red) or NULL; filled
+ *                only for PER_TERM and PASS_PER_TERM aggregation
+ *   norm_out     host double <psi|psi> (diagnostic) or NULL */
+aaq_status aaq_energy(const aaq_problem *prob, int p, const double *gamma, const double *beta,
+                      aaq_observable obs, aaq_aggregation agg, aaq_precision prec, void *d_state,
+                      size_t state_bytes, void *d_ws, size_t ws_bytes, void *stream, double *energy_out,
+                      double *zz_out, double *norm_out);
+
+/* <H> and its gradient by the adjoint method: dE/dtheta = 2 Im <lambda|G|psi> for each
+ * gate e^{-i theta G} (G = H_C for gamma_l, G = sum_q X_q for beta_l), with lambda the
+ * observable applied to the final state and swept backwards with psi; the gates are
+ * unitary, so psi is uncomputed on the way back and no checkpoints are kept.
+ *   d_lambda     second device buffer of >= aaq_state_bytes
+ *   dgamma_out, dbeta_out  host double[p] */
+aaq_status aaq_energy_grad(const aaq_problem *prob, int p, const double *gamma, const double *beta,
+                           aaq_observable obs, aaq_precision prec, void *d_state, size_t state_bytes,
+                           void *d_lambda, size_t lambda_bytes, void *d_ws, size_t ws_bytes, void *stream,
+                           double *energy_out, double *dgamma_out, double *dbeta_out, double *norm_out);
+
+/* Exact integer values of the observable's diagonal for every z in [0, 2^n):
+ * C(z) for AAQ_OBS_HC, h_red(z) = sum_m |S_m| [z_{i_m} != z_{j_m}] for AAQ_OBS_HRED
+ * (the diagonal of H_C and H_red without the 1/2 (1 - ZZ) rewriting), computed by the
+ * same device code that the cost layer and the expectation use.
+ *   d_ws   device workspace of >= 512 + 16 * (number of terms) bytes
+ *   d_out  device int32[2^n]; n <= 30.  Synchronises the stream. */
+aaq_status aaq_cut_values(const aaq_problem *prob, aaq_observable obs, void *d_ws, size_t ws_bytes, int32_t *d_out,
+                          void *stream);
+
+/* Diagnostic variant: the values as computed inside tile set `set_index`
+ * (0 .. aaq_num_sets(n, prec) - 1) at register arrangement 0 (the load/store layout)
+ * or 1 (the layout where the cost phase is applied).  Every variant must equal
+ * aaq_cut_values bit for bit. */
+aaq_status aaq_cut_values_layout(const aaq_problem *prob, aaq_observable obs, int set_index, int arrangement,
+                                 aaq_precision prec, void *d_ws, size_t ws_bytes, int32_t *d_out, void *stream);
+
+/* Number of tile sets the sweep schedule uses for n qubits (1 when the whole state is
+ * one tile: n <= 14 for complex64, n <= 13 for complex128). */
+int aaq_num_sets(int n, aaq_precision prec);
+
+/* ---------------------------------------------------------------- batched plans
+ * Many (instance, parameter point) units evaluated by one persistent kernel: each
+ * workgroup takes the next unit from a device work counter (largest n first) and
+ * runs that unit's whole forward (and backward) sweep sequence.  Replays are
+ * captured once in a HIP graph.
+ *   probs[count]  the instance of every unit (the same instance may repeat)
+ *   d_params      device double[count][2p]: gamma_0..gamma_{p-1}, beta_0..beta_{p-1}
+ *   d_out         device double[count][2 + 2p]: energy, norm, dE/dgamma[p], dE/dbeta[p]
+ *                 (gradients only when with_grad) */
+typedef struct aaq_plan aaq_plan;
+
+typedef struct {
+  int use_graph;      /* capture the launches in a HIP graph and replay it (default 1) */
+  int workgroups;     /* persistent workgroups; 0 = one per compute unit x occupancy */
+  int sort_units;     /* 1 = largest n first (default) */
+  aaq_precision prec; /* amplitude precision (default AAQ_PREC_C64) */
+} aaq_plan_opts;
+
+/* Fills opts with the defaults above. */
+void aaq_plan_default_opts(aaq_plan_opts *opts);
+
+aaq_status aaq_plan_workspace_size(const aaq_problem *probs, int count, int p, aaq_observable obs, int with_grad,
+                                   const aaq_plan_opts *opts, size_t *bytes);
+
+/* Validates every unit, lays out the workspace (descriptors, phase tables, per-unit
+ * state buffers for n > 14) and uploads descriptors on `stream`. */
+aaq_status aaq_plan_create(const aaq_problem *probs, int count, int p, aaq_observable obs, int with_grad,
+                           const aaq_plan_opts *opts, void *d_ws, size_t ws_bytes, void *stream,
+                           aaq_plan **out);
+
+/* Asynchronous on `stream`: reads parameters from d_params, writes d_out.  With
+ * use_graph the first call (or a call with new buffer addresses) captures a graph
+ * and later calls replay it. */
+aaq_status aaq_plan_execute(aaq_plan *plan, const double *d_params, double *d_out, void *stream);
+
+void aaq_plan_destroy(aaq_plan *plan);
+
+/* ---------------------------------------------------------------- diagnostics */
+const char *aaq_status_string(aaq_status s);
+const char *aaq_last_error_message(void);
+
+/* Library version string, e.g. "aaqaoa 0.1 gfx950". */
+const char *aaq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAQAOA_H */

@@ -1,0 +1,13 @@
+"""MI355X (gfx950) MaxCut-QAOA statevector estimator with orbit-reduced observables.
+
+The compute path is the HIP C-ABI library ``libaaqaoa.so`` (declared in
+``include/aaqaoa.h``); this package only marshals arguments to it.  PyTorch
+provides device memory and streams.  Importing the package does not load the
+library; the first call does, and fails loudly if it has not been built.
+"""
+from .api import (  # noqa: F401
+    AAQ_AGG_FUSED, AAQ_AGG_PASS_PER_TERM, AAQ_AGG_PER_TERM, AAQ_OBS_HC, AAQ_OBS_HRED, AAQ_PREC_C64, AAQ_PREC_C128,
+    AAQError, Problem, aaq_cut_values, aaq_cut_values_layout, aaq_energy, aaq_energy_grad, aaq_num_sets,
+    aaq_plan_create, aaq_plan_destroy, aaq_plan_execute, aaq_plan_workspace_size, aaq_state_bytes, aaq_validate,
+    aaq_version, aaq_workspace_size, Estimator, Plan,
+)

@@ -1,0 +1,75 @@
+"""ctypes loader for libaaqaoa.so (built in-tree by paper_2410_22247_amd/build.py)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaaqaoa.so")
+
+_lib = None
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("num_edges", ctypes.c_int32),
+        ("edges", ctypes.POINTER(ctypes.c_int32)),
+        ("num_orbits", ctypes.c_int32),
+        ("orbit_rep", ctypes.POINTER(ctypes.c_int32)),
+        ("orbit_size", ctypes.POINTER(ctypes.c_int32)),
+        ("edge_orbit", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class CPlanOpts(ctypes.Structure):
+    _fields_ = [
+        ("use_graph", ctypes.c_int),
+        ("workgroups", ctypes.c_int),
+        ("sort_units", ctypes.c_int),
+        ("prec", ctypes.c_int),
+    ]
+
+
+EXPORTS = (
+    "aaq_validate", "aaq_state_bytes", "aaq_workspace_size", "aaq_energy", "aaq_energy_grad", "aaq_cut_values",
+    "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
+    "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
+)
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                           "or `python paper_2410_22247_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(CProblem)
+    vp, sz, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "aaq_validate": (i, [P, i]),
+        "aaq_state_bytes": (i, [P, i, szp]),
+        "aaq_workspace_size": (i, [P, i, i, i, i, i, szp]),
+        "aaq_energy": (i, [P, i, dp, dp, i, i, i, vp, sz, vp, sz, vp, dp, dp, dp]),
+        "aaq_energy_grad": (i, [P, i, dp, dp, i, i, vp, sz, vp, sz, vp, sz, vp, dp, dp, dp, dp]),
+        "aaq_cut_values": (i, [P, i, vp, sz, vp, vp]),
+        "aaq_cut_values_layout": (i, [P, i, i, i, i, vp, sz, vp, vp]),
+        "aaq_num_sets": (i, [i, i]),
+        "aaq_plan_default_opts": (None, [ctypes.POINTER(CPlanOpts)]),
+        "aaq_plan_workspace_size": (i, [P, i, i, i, i, ctypes.POINTER(CPlanOpts), szp]),
+        "aaq_plan_create": (i, [P, i, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, ctypes.POINTER(vp)]),
+        "aaq_plan_execute": (i, [vp, vp, vp, vp]),
+        "aaq_plan_destroy": (None, [vp]),
+        "aaq_status_string": (ctypes.c_char_p, [i]),
+        "aaq_last_error_message": (ctypes.c_char_p, []),
+        "aaq_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return _lib

@@ -1,0 +1,282 @@
+"""Python binding of the C ABI in include/aaqaoa.h.
+
+Functions named ``aaq_*`` mirror the C entry points one to one and only marshal
+arguments (device buffers are torch tensors, streams are torch streams).  Every
+step of the computation runs in the HIP library; a non-zero status raises
+``AAQError``.  ``Estimator`` and ``Plan`` are thin conveniences that allocate the
+device buffers with torch and call the same entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+
+AAQ_OBS_HC, AAQ_OBS_HRED = 0, 1
+AAQ_AGG_FUSED, AAQ_AGG_PER_TERM, AAQ_AGG_PASS_PER_TERM = 0, 1, 2
+AAQ_PREC_C64, AAQ_PREC_C128 = 0, 1
+
+
+class AAQError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"aaqaoa status {status}: {message}")
+        self.status = status
+
+
+def _check(st: int):
+    if st != 0:
+        L = _lib.lib()
+        raise AAQError(st, f"{L.aaq_status_string(st).decode()}: {L.aaq_last_error_message().decode()}")
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+
+
+def _ptr_i32(a: Optional[np.ndarray]):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_int32)()
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Problem:
+    """A MaxCut instance and its Aut(G) edge orbits, as the C struct ``aaq_problem``.
+
+    ``edges``: (m, 2) vertex pairs; ``orbit_rep``: representative edge index per
+    orbit; ``orbit_size``: orbit sizes; ``edge_orbit``: orbit id per edge or None.
+    The numpy arrays are kept alive by this object."""
+
+    def __init__(self, n: int, edges, orbit_rep=None, orbit_size=None, edge_orbit=None):
+        self.n = int(n)
+        self.edges = _i32(edges)
+        m = self.edges.size // 2
+        if orbit_rep is None:  # every edge its own orbit
+            orbit_rep, orbit_size = np.arange(m), np.ones(m)
+        self.orbit_rep = _i32(orbit_rep)
+        self.orbit_size = _i32(orbit_size)
+        self.edge_orbit = None if edge_orbit is None else _i32(edge_orbit)
+        self.c = _lib.CProblem(self.n, m, _ptr_i32(self.edges), self.orbit_rep.size, _ptr_i32(self.orbit_rep),
+                               _ptr_i32(self.orbit_size), _ptr_i32(self.edge_orbit))
+
+    @property
+    def num_edges(self) -> int:
+        return self.edges.size // 2
+
+    @property
+    def num_orbits(self) -> int:
+        return self.orbit_rep.size
+
+    def num_terms(self, obs: int) -> int:
+        return self.num_edges if obs == AAQ_OBS_HC else self.num_orbits
+
+    @classmethod
+    def from_workload(cls, prob) -> "Problem":
+        """From any object with n, edges(), orbit_rep(), orbit_size(), edge_orbit()."""
+        return cls(prob.n, prob.edges(), prob.orbit_rep(), prob.orbit_size(), prob.edge_orbit())
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _params(gamma, beta):
+    g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(-1))
+    b = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(-1))
+    if g.size != b.size:
+        raise ValueError("gamma and beta must have the same length p")
+    return g, b
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dev(t):
+    """(pointer, bytes) of a torch device tensor, or (None, 0)."""
+    if t is None:
+        return None, 0
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ mirrors of the C ABI
+def aaq_version() -> str:
+    return _lib.lib().aaq_version().decode()
+
+
+def aaq_validate(prob: Problem, p: int) -> None:
+    _check(_lib.lib().aaq_validate(prob.ref(), int(p)))
+
+
+def aaq_state_bytes(prob: Problem, prec: int = AAQ_PREC_C64) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_state_bytes(prob.ref(), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def aaq_workspace_size(prob: Problem, p: int, with_grad: bool, obs: int = AAQ_OBS_HRED, agg: int = AAQ_AGG_FUSED,
+                       prec: int = AAQ_PREC_C64) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_workspace_size(prob.ref(), int(p), int(bool(with_grad)), int(obs), int(agg), int(prec),
+                                         ctypes.byref(out)))
+    return out.value
+
+
+def aaq_energy(prob: Problem, gamma, beta, obs: int, agg: int, prec: int, d_state, d_ws, stream=None):
+    """Returns (energy, zz or None, norm)."""
+    g, b = _params(gamma, beta)
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    T = prob.num_terms(obs)
+    zz = np.zeros(max(T, 1)) if agg != AAQ_AGG_FUSED else None
+    sp, sb = _dev(d_state)
+    wp, wb = _dev(d_ws)
+    _check(_lib.lib().aaq_energy(prob.ref(), g.size, _dp(g), _dp(b), int(obs), int(agg), int(prec), sp, sb, wp, wb,
+                                 _stream(stream), ctypes.byref(e), _dp(zz) if zz is not None else None,
+                                 ctypes.byref(nrm)))
+    return e.value, (zz[:T] if zz is not None else None), nrm.value
+
+
+def aaq_energy_grad(prob: Problem, gamma, beta, obs: int, prec: int, d_state, d_lambda, d_ws, stream=None):
+    """Returns (energy, dE/dgamma[p], dE/dbeta[p], norm)."""
+    g, b = _params(gamma, beta)
+    p = g.size
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    dg, db = np.zeros(p), np.zeros(p)
+    sp, sb = _dev(d_state)
+    lp, lb = _dev(d_lambda)
+    wp, wb = _dev(d_ws)
+    _check(_lib.lib().aaq_energy_grad(prob.ref(), p, _dp(g), _dp(b), int(obs), int(prec), sp, sb, lp, lb, wp, wb,
+                                      _stream(stream), ctypes.byref(e), _dp(dg), _dp(db), ctypes.byref(nrm)))
+    return e.value, dg, db, nrm.value
+
+
+def aaq_cut_values(prob: Problem, obs: int, d_ws, d_out, stream=None) -> None:
+    wp, wb = _dev(d_ws)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_cut_values(prob.ref(), int(obs), wp, wb, op, _stream(stream)))
+
+
+def aaq_cut_values_layout(prob: Problem, obs: int, set_index: int, arrangement: int, prec: int, d_ws, d_out,
+                          stream=None) -> None:
+    wp, wb = _dev(d_ws)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_cut_values_layout(prob.ref(), int(obs), int(set_index), int(arrangement), int(prec), wp, wb,
+                                            op, _stream(stream)))
+
+
+def aaq_num_sets(n: int, prec: int = AAQ_PREC_C64) -> int:
+    return int(_lib.lib().aaq_num_sets(int(n), int(prec)))
+
+
+def _opts(use_graph=True, workgroups=0, sort_units=True, prec=AAQ_PREC_C64):
+    o = _lib.CPlanOpts()
+    _lib.lib().aaq_plan_default_opts(ctypes.byref(o))
+    o.use_graph, o.workgroups, o.sort_units, o.prec = int(use_graph), int(workgroups), int(sort_units), int(prec)
+    return o
+
+
+def _problem_array(probs: Sequence[Problem]):
+    arr = (_lib.CProblem * len(probs))()
+    for i, pr in enumerate(probs):
+        arr[i] = pr.c
+    return arr
+
+
+def aaq_plan_workspace_size(probs: Sequence[Problem], p: int, obs: int, with_grad: bool, **opts) -> int:
+    arr = _problem_array(probs)
+    o = _opts(**opts)
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_plan_workspace_size(arr, len(probs), int(p), int(obs), int(bool(with_grad)), ctypes.byref(o),
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def aaq_plan_create(probs: Sequence[Problem], p: int, obs: int, with_grad: bool, d_ws, stream=None, **opts):
+    arr = _problem_array(probs)
+    o = _opts(**opts)
+    wp, wb = _dev(d_ws)
+    h = ctypes.c_void_p()
+    _check(_lib.lib().aaq_plan_create(arr, len(probs), int(p), int(obs), int(bool(with_grad)), ctypes.byref(o), wp, wb,
+                                      _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def aaq_plan_execute(plan, d_params, d_out, stream=None) -> None:
+    pp, _ = _dev(d_params)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_plan_execute(plan, pp, op, _stream(stream)))
+
+
+def aaq_plan_destroy(plan) -> None:
+    if plan:
+        _lib.lib().aaq_plan_destroy(plan)
+
+
+# ------------------------------------------------------------------ conveniences
+class Estimator:
+    """Owns the device buffers (torch) for repeated evaluations of one instance."""
+
+    def __init__(self, prob: Problem, p: int, obs: int = AAQ_OBS_HRED, prec: int = AAQ_PREC_C64, grad: bool = True,
+                 agg: int = AAQ_AGG_FUSED, device: str = "cuda"):
+        import torch
+
+        self.prob, self.p, self.obs, self.prec, self.agg = prob, int(p), obs, prec, agg
+        sb = aaq_state_bytes(prob, prec)
+        wb = max(aaq_workspace_size(prob, p, grad, obs, AAQ_AGG_FUSED, prec),
+                 aaq_workspace_size(prob, p, False, obs, agg, prec))
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        self.lam = torch.empty(sb, dtype=torch.uint8, device=device) if grad else None
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=device)
+
+    def energy(self, gamma, beta, obs: Optional[int] = None, agg: Optional[int] = None, stream=None):
+        return aaq_energy(self.prob, gamma, beta, self.obs if obs is None else obs, self.agg if agg is None else agg,
+                          self.prec, self.state, self.ws, stream)
+
+    def energy_grad(self, gamma, beta, obs: Optional[int] = None, stream=None):
+        if self.lam is None:
+            raise ValueError("Estimator was built without gradient buffers")
+        return aaq_energy_grad(self.prob, gamma, beta, self.obs if obs is None else obs, self.prec, self.state,
+                               self.lam, self.ws, stream)
+
+
+class Plan:
+    """Batched evaluation of many (instance, parameter point) units."""
+
+    def __init__(self, probs: Sequence[Problem], p: int, obs: int = AAQ_OBS_HRED, with_grad: bool = True,
+                 device: str = "cuda", stream=None, **opts):
+        import torch
+
+        self.count, self.p, self.with_grad = len(probs), int(p), with_grad
+        self._probs = list(probs)
+        wb = aaq_plan_workspace_size(self._probs, p, obs, with_grad, **opts)
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.handle = aaq_plan_create(self._probs, p, obs, with_grad, self.ws, stream, **opts)
+        self.params = torch.zeros(self.count, 2 * self.p, dtype=torch.float64, device=device)
+        self.out = torch.zeros(self.count, 2 + 2 * self.p, dtype=torch.float64, device=device)
+
+    def execute(self, stream=None, params=None, out=None):
+        aaq_plan_execute(self.handle, self.params if params is None else params, self.out if out is None else out,
+                         stream)
+        return self.out if out is None else out
+
+    def close(self):
+        if self.handle:
+            aaq_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

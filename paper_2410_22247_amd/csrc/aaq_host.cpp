@@ -1,0 +1,891 @@
+// Host side of the C ABI: validation, the sweep planner, workspace layout and the
+// entry points declared in include/aaqaoa.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "aaq_launch.h"
+#include "aaqaoa.h"
+
+using namespace aaq;
+
+namespace {
+
+thread_local std::string g_err;
+
+aaq_status fail(aaq_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(AAQ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ validation
+aaq_status validate_problem(const aaq_problem* pr) {
+  if (!pr) return fail(AAQ_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->n < 1 || pr->n > AAQ_MAX_N) return fail(AAQ_ERR_INVALID_ARG, "n must be in [1, 34]");
+  const int n = pr->n, m = pr->num_edges;
+  if (m < 0) return fail(AAQ_ERR_GRAPH, "num_edges < 0");
+  if (m > 0 && !pr->edges) return fail(AAQ_ERR_INVALID_ARG, "edges is NULL");
+  std::set<std::pair<int, int>> seen;
+  for (int e = 0; e < m; ++e) {
+    int u = pr->edges[2 * e], v = pr->edges[2 * e + 1];
+    if (u < 0 || u >= n || v < 0 || v >= n) return fail(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " has a vertex out of range");
+    if (u == v) return fail(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a self-loop");
+    if (!seen.insert({std::min(u, v), std::max(u, v)}).second)
+      return fail(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a duplicate");
+  }
+  const int k = pr->num_orbits;
+  if (m == 0) {
+    if (k != 0) return fail(AAQ_ERR_ORBITS, "a graph without edges has no edge orbits");
+    return AAQ_OK;
+  }
+  if (k < 1 || k > m) return fail(AAQ_ERR_ORBITS, "num_orbits must be in [1, |E|]");
+  if (!pr->orbit_rep || !pr->orbit_size) return fail(AAQ_ERR_INVALID_ARG, "orbit_rep / orbit_size is NULL");
+  long long tot = 0;
+  std::set<int> reps;
+  for (int o = 0; o < k; ++o) {
+    if (pr->orbit_rep[o] < 0 || pr->orbit_rep[o] >= m) return fail(AAQ_ERR_ORBITS, "orbit representative is not an edge index");
+    if (!reps.insert(pr->orbit_rep[o]).second) return fail(AAQ_ERR_ORBITS, "two orbits share a representative");
+    if (pr->orbit_size[o] < 1) return fail(AAQ_ERR_ORBITS, "orbit size < 1");
+    tot += pr->orbit_size[o];
+  }
+  if (tot != m) return fail(AAQ_ERR_ORBITS, "orbit sizes do not sum to |E|");
+  if (pr->edge_orbit) {
+    std::vector<int> cnt(k, 0);
+    for (int e = 0; e < m; ++e) {
+      int o = pr->edge_orbit[e];
+      if (o < 0 || o >= k) return fail(AAQ_ERR_ORBITS, "edge_orbit entry out of range");
+      cnt[o]++;
+    }
+    for (int o = 0; o < k; ++o) {
+      if (cnt[o] != pr->orbit_size[o]) return fail(AAQ_ERR_ORBITS, "orbit size disagrees with edge_orbit");
+      if (pr->edge_orbit[pr->orbit_rep[o]] != o) return fail(AAQ_ERR_ORBITS, "representative is not in its orbit");
+    }
+  }
+  return AAQ_OK;
+}
+
+aaq_status validate_p(int p) {
+  if (p < 1 || p > AAQ_MAX_P) return fail(AAQ_ERR_INVALID_ARG, "p must be in [1, 64]");
+  return AAQ_OK;
+}
+
+aaq_status validate_params(int p, const double* g, const double* b) {
+  if (!g || !b) return fail(AAQ_ERR_INVALID_ARG, "gamma / beta is NULL");
+  for (int l = 0; l < p; ++l)
+    if (!std::isfinite(g[l]) || !std::isfinite(b[l])) return fail(AAQ_ERR_PARAMS, "non-finite gamma or beta");
+  return AAQ_OK;
+}
+
+// ------------------------------------------------------------------ graph block
+GraphDev make_graph(const aaq_problem* pr) {
+  GraphDev g;
+  std::memset(&g, 0, sizeof(g));
+  g.n = pr->n;
+  g.m = pr->num_edges;
+  g.cmax = pr->num_edges;
+  for (int e = 0; e < pr->num_edges; ++e) {
+    int u = pr->edges[2 * e], v = pr->edges[2 * e + 1];
+    g.adj[u] |= 1ull << v;
+    g.adj[v] |= 1ull << u;
+    g.deg[u]++;
+    g.deg[v]++;
+  }
+  return g;
+}
+
+std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
+  std::vector<int4> t;
+  if (obs == AAQ_OBS_HC) {
+    for (int e = 0; e < pr->num_edges; ++e) t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], 1, 0));
+  } else {
+    for (int o = 0; o < pr->num_orbits; ++o) {
+      int e = pr->orbit_rep[o];
+      t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], pr->orbit_size[o], 0));
+    }
+  }
+  return t;
+}
+
+// ------------------------------------------------------------------ sweep planner
+// Split the n qubits into k tile sets.  Set 0 is a contiguous block of L global bits
+// (its low a_0 bits mixed); every later set mixes a_s <= L - 5 qubits and fills its
+// tile with the lowest remaining global bits, so that every tile holds global bits
+// 0..4 (>= 256 contiguous bytes per access).  k is the smallest possible, sizes as
+// even as the caps allow.
+std::vector<SetSpec> make_sets(int n, int L) {
+  std::vector<SetSpec> sets;
+  if (n <= L) {
+    SetSpec s;
+    std::memset(&s, 0, sizeof(s));
+    for (int j = 0; j < 16; ++j) s.pos[j] = (j < n) ? (uint8_t)j : kDummy;
+    s.act = (1u << n) - 1u;
+    s.dummy = ((1u << L) - 1u) & ~s.act;
+    s.fixmask = 0;
+    s.ntiles = 1;
+    sets.push_back(s);
+    return sets;
+  }
+  const int cap_rest = L - kMinContig;
+  int k = 1 + (n - L + cap_rest - 1) / cap_rest;
+  std::vector<int> a(k);
+  a[0] = L;
+  for (int s = 1; s < k; ++s) a[s] = cap_rest;
+  int tot = L + (k - 1) * cap_rest;
+  while (tot > n) {  // shave the largest set (set 0 first on ties) keeping a_0 >= 5
+    int best = -1;
+    for (int s = 0; s < k; ++s) {
+      if (s == 0 && a[0] <= kMinContig) continue;
+      if (a[s] <= 1) continue;
+      if (best < 0 || a[s] > a[best]) best = s;
+    }
+    a[best]--;
+    tot--;
+  }
+  int next = 0;
+  for (int s = 0; s < k; ++s) {
+    SetSpec S;
+    std::memset(&S, 0, sizeof(S));
+    std::vector<int> active;
+    for (int i = 0; i < a[s]; ++i) active.push_back(next + i);
+    next += a[s];
+    std::vector<int> bits;
+    if (s == 0) {
+      for (int j = 0; j < L; ++j) bits.push_back(j);
+    } else {
+      std::set<int> act(active.begin(), active.end());
+      bits = active;
+      for (int gbit = 0; (int)bits.size() < L; ++gbit)
+        if (!act.count(gbit)) bits.push_back(gbit);
+      std::sort(bits.begin(), bits.end());
+    }
+    uint64_t tilemask = 0;
+    for (int j = 0; j < L; ++j) {
+      S.pos[j] = (uint8_t)bits[j];
+      tilemask |= 1ull << bits[j];
+      if (std::find(active.begin(), active.end(), bits[j]) != active.end()) S.act |= 1u << j;
+    }
+    for (int j = L; j < 16; ++j) S.pos[j] = kDummy;
+    S.dummy = 0;
+    const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    S.fixmask = all & ~tilemask;
+    S.ntiles = 1u << (n - L);
+    sets.push_back(S);
+  }
+  return sets;
+}
+
+int zig(int i, int k) {
+  if (k == 1) return 0;
+  const int per = 2 * (k - 1);
+  const int m = i % per;
+  return (m <= k - 1) ? m : per - m;
+}
+
+SweepProg blank() {
+  SweepProg s;
+  std::memset(&s, 0, sizeof(s));
+  s.pre_layer = s.mid_layer = s.mixA_layer = s.mixB_layer = -1;
+  return s;
+}
+
+// Forward (and, with grad, backward) sweep programs.
+//  multi-set (k >= 2): zig-zag over the sets; each layer boundary (phase) sits inside
+//  a sweep that finishes layer l's mixing on its set, applies the next phase and starts
+//  layer l+1 on the same set, so p layers take p(k-1)+1 sweeps.  The last forward sweep
+//  evaluates h(z) and, for gradients, creates lambda = h psi and undoes the last mixer
+//  part on both states; the backward sweeps mirror the forward ones.
+//  single set (k == 1): the whole state is one tile; a sweep strings together
+//  [ops, mixer, ops, mixer] and the program is the plain gate sequence.
+std::vector<SweepProg> build_progs(int k, int p, bool grad, uint8_t energy_ops, bool store_final) {
+  std::vector<SweepProg> out;
+  if (k == 1) {
+    struct Step {
+      bool mix;
+      uint8_t ops;
+      int layer;
+      int dir;
+      bool grad;
+    };
+    std::vector<Step> st;
+    for (int l = 0; l < p; ++l) {
+      st.push_back({false, OP_PHASE, l, 0, false});
+      st.push_back({true, 0, l, +1, false});
+    }
+    st.push_back({false, energy_ops, -1, 0, false});
+    if (grad) {
+      for (int l = p - 1; l >= 0; --l) {
+        st.push_back({true, 0, l, -1, true});
+        st.push_back({false, (uint8_t)(l > 0 ? (OP_GRADG | OP_UNPHASE) : OP_GRADG), l, 0, false});
+      }
+    }
+    bool lam = false;
+    for (size_t i = 0; i < st.size(); i += 4) {
+      SweepProg s = blank();
+      s.set = 0;
+      const bool first = i == 0, last = i + 4 >= st.size();
+      s.flags = first ? F_INIT : (uint8_t)(F_LOAD_PSI | (lam ? (F_LOAD_LAM | F_LAM_LIVE) : 0));
+      for (size_t j = i; j < std::min(st.size(), i + 4); ++j) {
+        const Step& x = st[j];
+        const int slot = (int)(j - i);
+        if (slot == 0) {
+          s.pre_ops = x.ops;
+          s.pre_layer = (int8_t)x.layer;
+        } else if (slot == 1) {
+          s.mixA_layer = (int8_t)x.layer;
+          s.mixA_dir = (int8_t)x.dir;
+          s.mixA_grad = x.grad;
+        } else if (slot == 2) {
+          s.mid_ops = x.ops;
+          s.mid_layer = (int8_t)x.layer;
+        } else {
+          s.mixB_layer = (int8_t)x.layer;
+          s.mixB_dir = (int8_t)x.dir;
+          s.mixB_grad = x.grad;
+        }
+        if (!x.mix && (x.ops & OP_ENERGY) && grad) {
+          s.flags |= F_MAKE_LAM;
+          lam = true;
+        }
+      }
+      if (!last) s.flags |= F_STORE_PSI | (lam ? F_STORE_LAM : 0);
+      if (last && store_final) s.flags |= F_STORE_PSI;
+      out.push_back(s);
+    }
+    return out;
+  }
+  const int F = p * (k - 1) + 1;
+  for (int i = 0; i < F; ++i) {
+    SweepProg s = blank();
+    s.set = (int8_t)zig(i, k);
+    if (i == 0) {
+      s.flags = F_INIT | F_STORE_PSI;
+      s.pre_ops = OP_PHASE;
+      s.pre_layer = 0;
+      s.mixA_layer = 0;
+      s.mixA_dir = 1;
+    } else if (i < F - 1) {
+      s.flags = F_LOAD_PSI | F_STORE_PSI;
+      s.mixA_layer = (int8_t)((i - 1) / (k - 1));
+      s.mixA_dir = 1;
+      if (i % (k - 1) == 0) {
+        const int l = i / (k - 1);
+        s.mid_ops = OP_PHASE;
+        s.mid_layer = (int8_t)l;
+        s.mixB_layer = (int8_t)l;
+        s.mixB_dir = 1;
+      }
+    } else {
+      s.flags = F_LOAD_PSI;
+      s.mixA_layer = (int8_t)(p - 1);
+      s.mixA_dir = 1;
+      s.mid_ops = energy_ops;
+      if (grad) {
+        s.flags |= F_MAKE_LAM | F_STORE_LAM;
+        s.mixB_layer = (int8_t)(p - 1);
+        s.mixB_dir = -1;
+        s.mixB_grad = 1;
+      }
+      if (store_final) s.flags |= F_STORE_PSI;
+    }
+    out.push_back(s);
+  }
+  if (grad) {
+    for (int i = F - 2; i >= 0; --i) {
+      SweepProg s = blank();
+      s.set = (int8_t)zig(i, k);
+      s.flags = F_LOAD_PSI | F_LOAD_LAM | F_LAM_LIVE | F_STORE_PSI | F_STORE_LAM;
+      if (i == 0) {
+        s.flags = F_LOAD_PSI | F_LOAD_LAM | F_LAM_LIVE;
+        s.mixA_layer = 0;
+        s.mixA_dir = -1;
+        s.mixA_grad = 1;
+        s.mid_ops = OP_GRADG;
+        s.mid_layer = 0;
+      } else if (i % (k - 1) == 0) {
+        const int l = i / (k - 1);
+        s.mixA_layer = (int8_t)l;
+        s.mixA_dir = -1;
+        s.mixA_grad = 1;
+        s.mid_ops = OP_GRADG | OP_UNPHASE;
+        s.mid_layer = (int8_t)l;
+        s.mixB_layer = (int8_t)(l - 1);
+        s.mixB_dir = -1;
+        s.mixB_grad = 1;
+      } else {
+        s.mixA_layer = (int8_t)((i - 1) / (k - 1));
+        s.mixA_dir = -1;
+        s.mixA_grad = 1;
+      }
+      out.push_back(s);
+    }
+  }
+  return out;
+}
+
+bool needs_two_states(const SweepProg& s) {
+  return (s.flags & (F_LAM_LIVE | F_MAKE_LAM | F_LOAD_LAM)) != 0;
+}
+
+// ------------------------------------------------------------------ single-instance layout
+struct Layout {
+  size_t graph = 0, terms = 0, params = 0, src = 0, srcb = 0, upload_end = 0;
+  size_t tab = 0, mixcs = 0, partial = 0, zzpart = 0, out = 0, total = 0;
+  int nsweep = 0, nslot = 0, ntiles = 0, nout = 0, nsrc = 0, T = 0;
+};
+
+constexpr int kZZBlocks = 1024;
+
+struct Single {
+  int n, p, T, cmax, L, k;
+  bool dbl, grad;
+  aaq_aggregation agg;
+  std::vector<SetSpec> sets;
+  std::vector<SweepProg> progs;
+  std::vector<RedSrcHost> src;
+  std::vector<int32_t> srcb;
+  Layout lay;
+};
+
+aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
+                       aaq_precision prec, Single& S) {
+  if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
+  if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
+    return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
+  if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  if (grad && agg != AAQ_AGG_FUSED) return fail(AAQ_ERR_UNSUPPORTED, "gradients use fused aggregation");
+  S.n = pr->n;
+  S.p = p;
+  S.dbl = prec == AAQ_PREC_C128;
+  S.grad = grad;
+  S.agg = agg;
+  S.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
+  S.cmax = pr->num_edges;
+  S.L = tile_bits(S.dbl);
+  S.sets = make_sets(S.n, S.L);
+  S.k = (int)S.sets.size();
+  uint8_t eops = OP_ENERGY | (agg == AAQ_AGG_PER_TERM ? OP_PERTERM : 0);
+  S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM);
+  Layout& L = S.lay;
+  L.nsweep = (int)S.progs.size();
+  L.T = S.T;
+  L.nslot = SLOT_TERMS + (agg == AAQ_AGG_PER_TERM ? S.T : 0);
+  L.ntiles = (int)S.sets[0].ntiles;
+  const bool zzp = agg == AAQ_AGG_PASS_PER_TERM;
+  L.nout = 2 + 2 * p + ((agg != AAQ_AGG_FUSED) ? S.T : 0);
+  // reduction sources
+  std::vector<std::vector<RedSrcHost>> per(L.nout);
+  auto part_off = [&](int sw, int slot) { return (int64_t)(sw * L.nslot + slot) * L.ntiles; };
+  for (int sw = 0; sw < L.nsweep; ++sw) {
+    const SweepProg& s = S.progs[sw];
+    auto add = [&](int o, int slot, double scale) { per[o].push_back({part_off(sw, slot), L.ntiles, o, scale}); };
+    if ((s.pre_ops | s.mid_ops) & OP_ENERGY) {
+      add(0, SLOT_E, 1.0);
+      add(1, SLOT_NORM, 1.0);
+      if (agg == AAQ_AGG_PER_TERM)
+        for (int t = 0; t < S.T; ++t) add(2 + 2 * p + t, SLOT_TERMS + t, 1.0);
+    }
+    if (s.pre_ops & OP_GRADG) add(2 + s.pre_layer, SLOT_GPRE, 2.0);
+    if (s.mid_ops & OP_GRADG) add(2 + s.mid_layer, SLOT_GMID, 2.0);
+    if (s.mixA_grad) add(2 + p + s.mixA_layer, SLOT_BA, 2.0);
+    if (s.mixB_grad) add(2 + p + s.mixB_layer, SLOT_BB, 2.0);
+  }
+  size_t off = 0;
+  L.graph = off;
+  off = align_up(off + sizeof(GraphDev));
+  L.terms = off;
+  off = align_up(off + sizeof(int4) * std::max(S.T, 1));
+  L.params = off;
+  off = align_up(off + sizeof(double) * 2 * p);
+  // the zz-pass partial area starts after the sweep partials
+  const int64_t sweep_part = (int64_t)L.nsweep * L.nslot * L.ntiles;
+  if (zzp)
+    for (int t = 0; t < S.T; ++t) per[2 + 2 * p + t].push_back({sweep_part + (int64_t)t * kZZBlocks, kZZBlocks, 2 + 2 * p + t, 1.0});
+  S.src.clear();
+  S.srcb.assign(L.nout + 1, 0);
+  for (int o = 0; o < L.nout; ++o) {
+    S.srcb[o] = (int32_t)S.src.size();
+    for (auto& x : per[o]) S.src.push_back(x);
+  }
+  S.srcb[L.nout] = (int32_t)S.src.size();
+  L.nsrc = (int)S.src.size();
+  L.src = off;
+  off = align_up(off + sizeof(RedSrcHost) * std::max(L.nsrc, 1));
+  L.srcb = off;
+  off = align_up(off + sizeof(int32_t) * (L.nout + 1));
+  L.upload_end = off;
+  const size_t amp = S.dbl ? 16 : 8;
+  L.tab = off;
+  off = align_up(off + amp * (size_t)p * (S.cmax + 1));
+  L.mixcs = off;
+  off = align_up(off + amp * p);
+  L.partial = off;
+  off = align_up(off + sizeof(double) * (size_t)(sweep_part + (zzp ? (int64_t)S.T * kZZBlocks : 0)));
+  L.out = off;
+  off = align_up(off + sizeof(double) * L.nout);
+  L.total = off;
+  return AAQ_OK;
+}
+
+aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
+                      aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
+                      void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res) {
+  aaq_status st = validate_problem(pr);
+  if (st) return st;
+  if ((st = validate_p(p))) return st;
+  if ((st = validate_params(p, gamma, beta))) return st;
+  Single S;
+  if ((st = plan_single(pr, p, grad, obs, agg, prec, S))) return st;
+  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
+  if (state_bytes < need_state) return fail(AAQ_ERR_BUFFER, "state buffer smaller than 2^n amplitudes");
+  if (grad) {
+    if (!d_lam) return fail(AAQ_ERR_INVALID_ARG, "d_lambda is NULL");
+    if (lam_bytes < need_state) return fail(AAQ_ERR_BUFFER, "lambda buffer smaller than 2^n amplitudes");
+  }
+  if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < S.lay.total) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(S.lay.total) + " bytes)");
+  const Layout& L = S.lay;
+  hipStream_t hs = (hipStream_t)stream;
+  unsigned char* ws = (unsigned char*)d_ws;
+  // host staging of everything that is uploaded
+  std::vector<unsigned char> up(L.upload_end, 0);
+  GraphDev g = make_graph(pr);
+  std::vector<int4> terms = make_terms(pr, obs);
+  g.T = S.T;
+  std::memcpy(up.data() + L.graph, &g, sizeof(g));
+  if (!terms.empty()) std::memcpy(up.data() + L.terms, terms.data(), sizeof(int4) * terms.size());
+  std::memcpy(up.data() + L.params, gamma, sizeof(double) * p);
+  std::memcpy(up.data() + L.params + sizeof(double) * p, beta, sizeof(double) * p);
+  if (!S.src.empty()) std::memcpy(up.data() + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
+  std::memcpy(up.data() + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
+  HIPCHK(hipMemcpyAsync(ws, up.data(), L.upload_end, hipMemcpyHostToDevice, hs));
+  const double* dparams = (const double*)(ws + L.params);
+  HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, ws + L.mixcs, S.dbl, hs));
+  for (int sw = 0; sw < L.nsweep; ++sw) {
+    LaunchSweep A;
+    A.psi = d_state;
+    A.lam = grad ? d_lam : nullptr;
+    A.g = (const GraphDev*)(ws + L.graph);
+    A.terms = (const int4*)(ws + L.terms);
+    A.tab = ws + L.tab;
+    A.mixcs = ws + L.mixcs;
+    A.partial = (double*)(ws + L.partial) + (size_t)sw * L.nslot * L.ntiles;
+    A.nslot = L.nslot;
+    A.T = S.T;
+    A.cmax = S.cmax;
+    A.amp = std::exp2(-0.5 * S.n);
+    A.set = S.sets[S.progs[sw].set];
+    A.prog = S.progs[sw];
+    A.two_states = needs_two_states(S.progs[sw]);
+    HIPCHK(launch_sweep(A, S.dbl, hs));
+  }
+  if (agg == AAQ_AGG_PASS_PER_TERM) {
+    double* zp = (double*)(ws + L.partial) + (size_t)L.nsweep * L.nslot * L.ntiles;
+    for (int t = 0; t < S.T; ++t)
+      HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y, zp + (size_t)t * kZZBlocks, kZZBlocks,
+                            S.dbl, hs));
+  }
+  HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb), (double*)(ws + L.out),
+                       L.nout, hs));
+  res.assign(L.nout, 0.0);
+  HIPCHK(hipMemcpyAsync(res.data(), ws + L.out, sizeof(double) * L.nout, hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (agg != AAQ_AGG_FUSED) {
+    // energy from the per-term <ZZ>: sum_t (w_t/2)(1 - <ZZ>_t)
+    double e = 0.0;
+    for (int t = 0; t < S.T; ++t) e += 0.5 * terms[t].z * (1.0 - res[2 + 2 * p + t]);
+    res[0] = e;
+  }
+  return AAQ_OK;
+}
+
+}  // namespace
+
+// ====================================================================== plans
+struct aaq_plan {
+  int count = 0, p = 0;
+  bool grad = false, dbl = false;
+  aaq_plan_opts opts;
+  unsigned char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t units_off = 0, progs_off = 0, order_off = 0, counter_off = 0;
+  int blocks = 0;
+  int tabmax = 1;
+  // captured graph
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const double* g_params = nullptr;
+  double* g_out = nullptr;
+  hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+struct PlanLayout {
+  size_t units = 0, progs = 0, order = 0, counter = 0, graphs = 0, total = 0;
+  std::vector<UnitDesc> ud;
+  std::vector<SweepProg> progs_v;
+  std::vector<int32_t> order_v;
+  std::vector<unsigned char> blob;  // graphs + terms (uploaded), offsets relative to `graphs`
+};
+
+aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observable obs, bool grad, const aaq_plan_opts& o,
+                       PlanLayout& PL) {
+  if (!probs || count < 1) return fail(AAQ_ERR_INVALID_ARG, "probs is NULL or count < 1");
+  aaq_status st = validate_p(p);
+  if (st) return st;
+  if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
+  const bool dbl = o.prec == AAQ_PREC_C128;
+  const int L = tile_bits(dbl);
+  const size_t amp = dbl ? 16 : 8;
+  for (int i = 0; i < count; ++i) {
+    if ((st = validate_problem(&probs[i]))) {
+      g_err = "unit " + std::to_string(i) + ": " + g_err;
+      return st;
+    }
+  }
+  // shared graph blocks: identical instance arrays are stored once
+  std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*>, std::pair<int64_t, int64_t>> gmap;
+  PL.ud.assign(count, UnitDesc{});
+  PL.blob.clear();
+  std::vector<std::vector<SweepProg>> progs(count);
+  for (int i = 0; i < count; ++i) {
+    const aaq_problem* pr = &probs[i];
+    UnitDesc& D = PL.ud[i];
+    std::memset(&D, 0, sizeof(D));
+    D.n = pr->n;
+    D.p = p;
+    D.row = i;
+    D.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
+    D.cmax = pr->num_edges;
+    auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size);
+    auto it = gmap.find(key);
+    if (it == gmap.end()) {
+      GraphDev g = make_graph(pr);
+      g.T = D.T;
+      std::vector<int4> t = make_terms(pr, obs);
+      int64_t goff = (int64_t)PL.blob.size();
+      PL.blob.resize(align_up(PL.blob.size() + sizeof(GraphDev)));
+      std::memcpy(PL.blob.data() + goff, &g, sizeof(g));
+      int64_t toff = (int64_t)PL.blob.size();
+      PL.blob.resize(align_up(PL.blob.size() + sizeof(int4) * std::max<size_t>(t.size(), 1)));
+      if (!t.empty()) std::memcpy(PL.blob.data() + toff, t.data(), sizeof(int4) * t.size());
+      it = gmap.emplace(key, std::make_pair(goff, toff)).first;
+    }
+    D.graph_off = it->second.first;  // relative to the graph area; fixed up below
+    D.terms_off = it->second.second;
+    std::vector<SetSpec> sets = make_sets(pr->n, L);
+    D.nsets = (int)sets.size();
+    for (int s = 0; s < D.nsets; ++s) D.sets[s] = sets[s];
+    progs[i] = build_progs(D.nsets, p, grad, OP_ENERGY, false);
+    D.nsweep = (int)progs[i].size();
+  }
+  // offsets
+  size_t off = 0;
+  PL.units = off;
+  off = align_up(off + sizeof(UnitDesc) * count);
+  PL.progs_v.clear();
+  for (int i = 0; i < count; ++i) {
+    PL.ud[i].prog_off = (int32_t)PL.progs_v.size();
+    PL.progs_v.insert(PL.progs_v.end(), progs[i].begin(), progs[i].end());
+  }
+  PL.progs = off;
+  off = align_up(off + sizeof(SweepProg) * PL.progs_v.size());
+  PL.order = off;
+  off = align_up(off + sizeof(int32_t) * count);
+  PL.counter = off;
+  off = align_up(off + sizeof(int32_t));
+  PL.graphs = off;
+  off = align_up(off + PL.blob.size());
+  for (int i = 0; i < count; ++i) {
+    PL.ud[i].graph_off += (int64_t)PL.graphs;
+    PL.ud[i].terms_off += (int64_t)PL.graphs;
+  }
+  for (int i = 0; i < count; ++i) {
+    UnitDesc& D = PL.ud[i];
+    D.tab_off = (int64_t)off;
+    off = align_up(off + amp * ((size_t)p * (D.cmax + 1) + p));
+  }
+  for (int i = 0; i < count; ++i) {
+    UnitDesc& D = PL.ud[i];
+    if (D.n > L) {
+      D.state_off = (int64_t)off;
+      off = align_up(off + amp * ((size_t)1 << D.n) * (grad ? 2 : 1));
+    } else {
+      D.state_off = -1;
+    }
+  }
+  PL.total = off;
+  PL.order_v.resize(count);
+  for (int i = 0; i < count; ++i) PL.order_v[i] = i;
+  if (o.sort_units)
+    std::stable_sort(PL.order_v.begin(), PL.order_v.end(), [&](int a, int b) { return PL.ud[a].n > PL.ud[b].n; });
+  return AAQ_OK;
+}
+
+int device_cus() {
+  int dev = 0, cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+  return cu;
+}
+
+aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipStream_t hs) {
+  LaunchUnits U;
+  U.units = (const UnitDesc*)(P->ws + P->units_off);
+  U.progs = (const SweepProg*)(P->ws + P->progs_off);
+  U.order = (const int32_t*)(P->ws + P->order_off);
+  U.ws = P->ws;
+  U.params = d_params;
+  U.out = d_out;
+  U.counter = (int32_t*)(P->ws + P->counter_off);
+  U.count = P->count;
+  U.out_stride = 2 + 2 * P->p;
+  U.tabmax = P->tabmax;
+  U.psi_io = nullptr;
+  HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));
+  HIPCHK(launch_units(U, P->grad, P->dbl, P->blocks, hs));
+  return AAQ_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* aaq_status_string(aaq_status s) {
+  switch (s) {
+    case AAQ_OK: return "ok";
+    case AAQ_ERR_INVALID_ARG: return "invalid argument";
+    case AAQ_ERR_GRAPH: return "invalid graph";
+    case AAQ_ERR_ORBITS: return "invalid edge orbits";
+    case AAQ_ERR_PARAMS: return "invalid parameters";
+    case AAQ_ERR_BUFFER: return "buffer too small";
+    case AAQ_ERR_UNSUPPORTED: return "unsupported";
+    case AAQ_ERR_HIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+const char* aaq_last_error_message(void) { return g_err.c_str(); }
+
+const char* aaq_version(void) { return "aaqaoa 0.1 gfx950"; }
+
+aaq_status aaq_validate(const aaq_problem* prob, int p) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  return validate_p(p);
+}
+
+aaq_status aaq_state_bytes(const aaq_problem* prob, aaq_precision prec, size_t* bytes) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  *bytes = ((size_t)1 << prob->n) * (prec == AAQ_PREC_C128 ? 16 : 8);
+  return AAQ_OK;
+}
+
+aaq_status aaq_workspace_size(const aaq_problem* prob, int p, int with_grad, aaq_observable obs, aaq_aggregation agg,
+                              aaq_precision prec, size_t* bytes) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if ((s = validate_p(p))) return s;
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  Single S;
+  if ((s = plan_single(prob, p, with_grad != 0, obs, agg, prec, S))) return s;
+  *bytes = S.lay.total;
+  return AAQ_OK;
+}
+
+aaq_status aaq_energy(const aaq_problem* prob, int p, const double* gamma, const double* beta, aaq_observable obs,
+                      aaq_aggregation agg, aaq_precision prec, void* d_state, size_t state_bytes, void* d_ws,
+                      size_t ws_bytes, void* stream, double* energy_out, double* zz_out, double* norm_out) {
+  if (!energy_out) return fail(AAQ_ERR_INVALID_ARG, "energy_out is NULL");
+  std::vector<double> res;
+  aaq_status s = run_single(prob, p, gamma, beta, obs, agg, prec, false, d_state, state_bytes, nullptr, 0, d_ws, ws_bytes,
+                            stream, res);
+  if (s) return s;
+  *energy_out = res[0];
+  if (norm_out) *norm_out = res[1];
+  if (zz_out && agg != AAQ_AGG_FUSED) {
+    const int T = (obs == AAQ_OBS_HC) ? prob->num_edges : prob->num_orbits;
+    for (int t = 0; t < T; ++t) zz_out[t] = res[2 + 2 * p + t];
+  }
+  return AAQ_OK;
+}
+
+aaq_status aaq_energy_grad(const aaq_problem* prob, int p, const double* gamma, const double* beta, aaq_observable obs,
+                           aaq_precision prec, void* d_state, size_t state_bytes, void* d_lambda, size_t lambda_bytes,
+                           void* d_ws, size_t ws_bytes, void* stream, double* energy_out, double* dgamma_out,
+                           double* dbeta_out, double* norm_out) {
+  if (!energy_out || !dgamma_out || !dbeta_out) return fail(AAQ_ERR_INVALID_ARG, "output pointer is NULL");
+  std::vector<double> res;
+  aaq_status s = run_single(prob, p, gamma, beta, obs, AAQ_AGG_FUSED, prec, true, d_state, state_bytes, d_lambda,
+                            lambda_bytes, d_ws, ws_bytes, stream, res);
+  if (s) return s;
+  *energy_out = res[0];
+  if (norm_out) *norm_out = res[1];
+  for (int l = 0; l < p; ++l) {
+    dgamma_out[l] = res[2 + l];
+    dbeta_out[l] = res[2 + p + l];
+  }
+  return AAQ_OK;
+}
+
+aaq_status aaq_cut_values_layout(const aaq_problem* prob, aaq_observable obs, int set_index, int arrangement,
+                                 aaq_precision prec, void* d_ws, size_t ws_bytes, int32_t* d_out, void* stream) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if (prob->n > 30) return fail(AAQ_ERR_UNSUPPORTED, "cut-value dumps are limited to n <= 30");
+  if (!d_out || !d_ws) return fail(AAQ_ERR_INVALID_ARG, "d_out / d_ws is NULL");
+  if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
+  if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  const bool dbl = prec == AAQ_PREC_C128;
+  std::vector<SetSpec> sets = make_sets(prob->n, tile_bits(dbl));
+  if (set_index < 0 || set_index >= (int)sets.size()) return fail(AAQ_ERR_INVALID_ARG, "set_index out of range");
+  if (arrangement != 0 && arrangement != 1) return fail(AAQ_ERR_INVALID_ARG, "arrangement must be 0 or 1");
+  const int T = (obs == AAQ_OBS_HC) ? prob->num_edges : prob->num_orbits;
+  const size_t need = align_up(sizeof(GraphDev)) + sizeof(int4) * std::max(T, 1);
+  if (ws_bytes < need) return fail(AAQ_ERR_BUFFER, "workspace too small for the graph block");
+  std::vector<unsigned char> up(need, 0);
+  GraphDev g = make_graph(prob);
+  g.T = T;
+  std::vector<int4> terms = make_terms(prob, obs);
+  std::memcpy(up.data(), &g, sizeof(g));
+  if (!terms.empty()) std::memcpy(up.data() + align_up(sizeof(GraphDev)), terms.data(), sizeof(int4) * terms.size());
+  hipStream_t hs = (hipStream_t)stream;
+  unsigned char* ws = (unsigned char*)d_ws;
+  HIPCHK(hipMemcpyAsync(ws, up.data(), need, hipMemcpyHostToDevice, hs));
+  HIPCHK(launch_cuts((const GraphDev*)ws, (const int4*)(ws + align_up(sizeof(GraphDev))), T, obs == AAQ_OBS_HRED ? 1 : 0,
+                     sets[set_index], arrangement, d_out, dbl, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  return AAQ_OK;
+}
+
+aaq_status aaq_cut_values(const aaq_problem* prob, aaq_observable obs, void* d_ws, size_t ws_bytes, int32_t* d_out,
+                          void* stream) {
+  return aaq_cut_values_layout(prob, obs, 0, 0, AAQ_PREC_C64, d_ws, ws_bytes, d_out, stream);
+}
+
+int aaq_num_sets(int n, aaq_precision prec) {
+  if (n < 1 || n > AAQ_MAX_N) return 0;
+  return (int)make_sets(n, tile_bits(prec == AAQ_PREC_C128)).size();
+}
+
+void aaq_plan_default_opts(aaq_plan_opts* o) {
+  if (!o) return;
+  o->use_graph = 1;
+  o->workgroups = 0;
+  o->sort_units = 1;
+  o->prec = AAQ_PREC_C64;
+}
+
+aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
+                                   const aaq_plan_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  aaq_plan_opts o;
+  aaq_plan_default_opts(&o);
+  if (opts) o = *opts;
+  PlanLayout PL;
+  aaq_status s = plan_layout(probs, count, p, obs, with_grad != 0, o, PL);
+  if (s) return s;
+  *bytes = PL.total;
+  return AAQ_OK;
+}
+
+aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
+                           const aaq_plan_opts* opts, void* d_ws, size_t ws_bytes, void* stream, aaq_plan** out) {
+  if (!out) return fail(AAQ_ERR_INVALID_ARG, "out is NULL");
+  aaq_plan_opts o;
+  aaq_plan_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.prec != AAQ_PREC_C64 && o.prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  PlanLayout PL;
+  aaq_status s = plan_layout(probs, count, p, obs, with_grad != 0, o, PL);
+  if (s) return s;
+  if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < PL.total) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(PL.total) + " bytes)");
+  hipStream_t hs = (hipStream_t)stream;
+  unsigned char* ws = (unsigned char*)d_ws;
+  std::vector<unsigned char> up(PL.graphs + PL.blob.size(), 0);
+  std::memcpy(up.data() + PL.units, PL.ud.data(), sizeof(UnitDesc) * count);
+  if (!PL.progs_v.empty()) std::memcpy(up.data() + PL.progs, PL.progs_v.data(), sizeof(SweepProg) * PL.progs_v.size());
+  std::memcpy(up.data() + PL.order, PL.order_v.data(), sizeof(int32_t) * count);
+  if (!PL.blob.empty()) std::memcpy(up.data() + PL.graphs, PL.blob.data(), PL.blob.size());
+  HIPCHK(hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  aaq_plan* P = new aaq_plan();
+  P->count = count;
+  P->p = p;
+  P->grad = with_grad != 0;
+  P->dbl = o.prec == AAQ_PREC_C128;
+  P->opts = o;
+  P->ws = ws;
+  P->ws_bytes = ws_bytes;
+  P->units_off = PL.units;
+  P->progs_off = PL.progs;
+  P->order_off = PL.order;
+  P->counter_off = PL.counter;
+  for (int i = 0; i < count; ++i) P->tabmax = std::max(P->tabmax, PL.ud[i].cmax + 1);
+  P->blocks = o.workgroups > 0 ? o.workgroups : 2 * device_cus();
+  if (P->blocks > count) P->blocks = count;
+  *out = P;
+  return AAQ_OK;
+}
+
+aaq_status aaq_plan_execute(aaq_plan* P, const double* d_params, double* d_out, void* stream) {
+  if (!P || !d_params || !d_out) return fail(AAQ_ERR_INVALID_ARG, "plan / d_params / d_out is NULL");
+  hipStream_t hs = (hipStream_t)stream;
+  if (!P->opts.use_graph || hs == nullptr) return plan_launch(P, d_params, d_out, hs);
+  if (!P->exec || P->g_params != d_params || P->g_out != d_out || P->g_stream != hs) {
+    if (P->exec) {
+      (void)hipGraphExecDestroy(P->exec);
+      P->exec = nullptr;
+    }
+    if (P->graph) {
+      (void)hipGraphDestroy(P->graph);
+      P->graph = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+    aaq_status s = plan_launch(P, d_params, d_out, hs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(hs, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(AAQ_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    P->graph = g;
+    HIPCHK(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0));
+    P->g_params = d_params;
+    P->g_out = d_out;
+    P->g_stream = hs;
+  }
+  HIPCHK(hipGraphLaunch(P->exec, hs));
+  return AAQ_OK;
+}
+
+void aaq_plan_destroy(aaq_plan* P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  delete P;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal data structures shared by the host planner and the HIP kernels.
+//
+// State layout: amplitude z (vertex v = bit v of z) at element z of a flat array of
+// complex64 (float2) or complex128 (double2).  A "tile" is 2^L amplitudes that one
+// 512-thread workgroup holds in registers (L = 14 for complex64, 13 for complex128):
+// tile bit j is global index bit pos[j]; the remaining global bits are enumerated by
+// the tile id (ascending).  Tile bits always include global bits 0..4 so that every
+// global load/store touches >= 256 contiguous bytes.
+#pragma once
+#include <stdint.h>
+
+namespace aaq {
+
+constexpr int kMaxN = 34;
+constexpr int kMaxP = 64;
+constexpr int kMaxT = 34 * 33 / 2;  // max terms (complete graph on 34 vertices)
+constexpr int kMaxSets = 4;
+constexpr int kThreads = 512;
+constexpr int kMinContig = 5;       // low global bits every tile must contain
+constexpr int kSmallN = 14;         // n <= kSmallN: whole state in one tile (complex64)
+constexpr uint8_t kDummy = 0xFF;    // tile bit without a vertex (n < L)
+
+// per-position operations inside a sweep
+enum : uint8_t {
+  OP_PHASE = 1,    // multiply live states by exp(-i gamma_l C(z))
+  OP_UNPHASE = 2,  // multiply live states by exp(+i gamma_l C(z))
+  OP_GRADG = 4,    // accumulate 2 Im sum conj(lam) C psi  (d/dgamma_l)
+  OP_ENERGY = 8,   // accumulate sum |psi|^2 h(z) and |psi|^2; with F_MAKE_LAM: lam = h psi
+  OP_PERTERM = 16  // with OP_ENERGY: accumulate <Z_i Z_j> per term
+};
+
+// sweep flags
+enum : uint8_t {
+  F_LOAD_PSI = 1,
+  F_LOAD_LAM = 2,
+  F_STORE_PSI = 4,
+  F_STORE_LAM = 8,
+  F_INIT = 16,      // synthesize |+> instead of loading psi
+  F_LAM_LIVE = 32,  // lambda is live at sweep start
+  F_MAKE_LAM = 64   // OP_ENERGY creates lambda = h psi
+};
+
+// partial-sum slots written per sweep and tile
+enum : int { SLOT_E = 0, SLOT_NORM = 1, SLOT_GPRE = 2, SLOT_GMID = 3, SLOT_BA = 4, SLOT_BB = 5, SLOT_TERMS = 6 };
+
+struct SetSpec {
+  uint8_t pos[16];   // global bit of tile bit j, kDummy if none
+  uint32_t act;      // tile-bit mask mixed in this set
+  uint32_t dummy;    // tile-bit mask of dummy bits
+  uint64_t fixmask;  // global bits enumerated by the tile id
+  uint32_t ntiles;
+  uint32_t pad;
+};
+
+struct SweepProg {
+  int8_t set;
+  uint8_t flags;
+  uint8_t pre_ops;
+  int8_t pre_layer;
+  int8_t mixA_layer;
+  int8_t mixA_dir;  // +1 apply e^{-i beta X}, -1 apply its inverse, 0 none
+  uint8_t mixA_grad;
+  uint8_t mid_ops;
+  int8_t mid_layer;
+  int8_t mixB_layer;
+  int8_t mixB_dir;
+  uint8_t mixB_grad;
+};
+
+// graph block in device memory (uniform, read with scalar loads)
+struct GraphDev {
+  int32_t n, m, T, cmax;   // cmax = |E| = last phase-table index
+  uint64_t adj[kMaxN];     // adjacency bitmasks
+  int32_t deg[kMaxN];
+  int32_t pad[2];
+};
+
+// one batched unit (instance x parameter point)
+struct UnitDesc {
+  int32_t n, p, nsweep, nsets;
+  int64_t graph_off;   // byte offset of GraphDev in the workspace
+  int64_t terms_off;   // byte offset of int4 terms (i, j, w, 0)
+  int64_t tab_off;     // byte offset of this unit's phase tables [p][cmax+1] + mixer (cos,sin)[p]
+  int64_t state_off;   // byte offset of psi (lambda follows), -1 when n <= L
+  int32_t prog_off;    // index of the first SweepProg
+  int32_t row;         // row in d_params / d_out
+  int32_t T, cmax;
+  SetSpec sets[kMaxSets];
+};
+
+}  // namespace aaq

@@ -1,0 +1,865 @@
+// HIP kernels (gfx950) for the p-layer MaxCut QAOA statevector estimator.
+//
+// One 512-thread workgroup owns a tile of 2^L = 8192 amplitudes in registers
+// (16 per thread), for complex64 and complex128 alike.
+// The tile's register bits are switched between "arrangements" through an LDS
+// transpose so that every mixer butterfly is a register-to-register operation:
+// arrangement k keeps tile bits [b0(k), b0(k)+RB) in registers and spreads the
+// other tile bits over the threads.  The last arrangement (high tile bits in
+// registers) is the one used for global loads and stores: consecutive lanes then
+// touch consecutive amplitudes.
+//
+// A sweep = load (or synthesise |+>) -> ops at the load arrangement -> mixer A
+// through the arrangements in ascending order -> ops at the "phase" arrangement ->
+// mixer B in descending order -> store.  The ops are the cost phase
+// exp(-i gamma C(z)) (QAOA section, U_P), its inverse, the energy / lambda step
+// and the gradient accumulations of the adjoint method.  C(z) and h(z) are exact
+// integers recomputed per amplitude from uint64 adjacency masks and the term list.
+#include <hip/hip_runtime.h>
+
+#include "aaq_internal.h"
+
+namespace aaq {
+
+template <class R> struct Cx;
+template <> struct Cx<float> {
+  using V = float2;
+  static constexpr int L = 13, RB = 4;
+};
+template <> struct Cx<double> {
+  using V = double2;
+  static constexpr int L = 13, RB = 4;
+};
+
+template <class R> struct Geo {
+  using V = typename Cx<R>::V;
+  static constexpr int L = Cx<R>::L, RB = Cx<R>::RB, NR = 1 << RB;
+  static constexpr int NA = (L + RB - 1) / RB;
+  static constexpr int LAST = NA - 1, P = NA - 2;
+  static constexpr int TILE = 1 << L;
+  static constexpr int LB = L - RB;  // thread bits: 2^LB = 512 threads
+  __host__ __device__ static constexpr int b0(int k) { return (k * RB < L - RB) ? k * RB : L - RB; }
+};
+static_assert((1 << Geo<float>::LB) == kThreads, "complex64 tile must map to 512 threads");
+static_assert((1 << Geo<double>::LB) == kThreads, "complex128 tile must map to 512 threads");
+
+
+template <class R> __device__ __forceinline__ typename Cx<R>::V mkv(R x, R y) {
+  typename Cx<R>::V v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+// tile index of register r of thread t in an arrangement whose register bits start at B0
+template <int B0, int RB> __device__ __forceinline__ uint32_t tidx(uint32_t t, uint32_t r) {
+  return (t & ((1u << B0) - 1u)) | (r << B0) | ((t >> B0) << (B0 + RB));
+}
+// LDS slot of tile index j (xor swizzle of the low RB bits by the next RB bits)
+template <int RB> __device__ __forceinline__ uint32_t swz(uint32_t j) {
+  return j ^ ((j >> RB) & ((1u << RB) - 1u));
+}
+
+// e^{-i theta X} on an amplitude pair with c = cos(theta), s = sin(theta):
+// (x, y) -> (c x - i s y, -i s x + c y)
+template <class V, class R> __device__ __forceinline__ void bfly(V& x, V& y, R c, R s) {
+  const V x0 = x, y0 = y;
+  x.x = c * x0.x + s * y0.y;
+  x.y = c * x0.y - s * y0.x;
+  y.x = c * y0.x + s * x0.y;
+  y.y = c * y0.y - s * x0.x;
+}
+// Im(conj(u) v)
+template <class V> __device__ __forceinline__ auto imcm(const V& u, const V& v) { return u.x * v.y - u.y * v.x; }
+
+__device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  for (uint64_t bit = 1; mask; bit <<= 1) {
+    const uint64_t low = mask & (~mask + 1);
+    if (x & bit) r |= low;
+    mask &= mask - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------
+// Per-sweep context (all uniform across the workgroup).
+template <class R> struct Ctx {
+  using V = typename Cx<R>::V;
+  const GraphDev* g;
+  const int4* terms;
+  const V* tab;    // [p][cmax+1]
+  const V* mixcs;  // [p] (cos beta, sin beta)
+  V* psi;          // global state (nullptr when the tile never leaves registers)
+  V* lam;
+  R amp;           // 2^{-n/2}
+  int T;
+  int cmax;
+};
+
+// Per-thread accumulators for one sweep.
+struct Acc {
+  double e, nrm, gpre, gmid, ba, bb;
+  __device__ void zero() { e = nrm = gpre = gmid = ba = bb = 0.0; }
+};
+
+template <class R, int NS> struct Tile {
+  using G = Geo<R>;
+  using V = typename G::V;
+  static constexpr int NR = G::NR, RB = G::RB, L = G::L, LB = G::LB, NA = G::NA, LAST = G::LAST, P = G::P;
+
+  V a[NS][NR];
+  bool lam_live;
+
+  // -------------------------------------------------------------- LDS transpose
+  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) lds[swz<RB>(tidx<G::b0(KF), RB>(t, r))] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[r] = lds[swz<RB>(tidx<G::b0(KT), RB>(t, r))];
+    __syncthreads();
+  }
+  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds) {
+    xchg1<KF, KT>(a[0], lds);
+    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
+  }
+
+  // -------------------------------------------------------------- mixer butterflies
+  // butterflies on every tile bit of `todo` held in registers by arrangement K
+  template <int K> __device__ __forceinline__ void mix_at(uint32_t& todo, R c, R s, bool grad, double& gacc) {
+    constexpr int B0 = G::b0(K);
+    R gsum = R(0);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if ((todo >> (B0 + b)) & 1u) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r & (1 << b)) continue;
+          const int r1 = r | (1 << b);
+          if (NS == 2) {
+            if (grad) gsum += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
+            if (lam_live) bfly(a[NS - 1][r], a[NS - 1][r1], c, s);
+          }
+          bfly(a[0][r], a[0][r1], c, s);
+        }
+      }
+    }
+    todo &= ~(((1u << RB) - 1u) << B0);
+    gacc += (double)gsum;
+  }
+
+  // -------------------------------------------------------------- z of register 0
+  template <int K> __device__ __forceinline__ uint64_t zbase(const SetSpec& S, uint64_t tile_base) const {
+    constexpr int B0 = G::b0(K);
+    const uint32_t t = threadIdx.x;
+    uint64_t z = tile_base;
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int tb = (i < B0) ? i : i + RB;
+      const uint32_t p = S.pos[tb];
+      if (p != kDummy) z |= (uint64_t)((t >> i) & 1u) << p;
+    }
+    return z;
+  }
+
+  // C(z) for every register amplitude at arrangement K:
+  // C(zb ^ m) = C(zb) + sum_{b in m} d_b - 2 #{edges inside m}, d_b = deg v_b - 2 |N(v_b) & zb|
+  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, const GraphDev* g, int (&cv)[NR]) const {
+    constexpr int B0 = G::b0(K);
+    const int n = g->n;
+    int c0 = 0;
+    for (int v = 0; v < n; ++v) {
+      const uint64_t av = g->adj[v];
+      c0 += (int)((zb >> v) & 1u) * __popcll(av & ~zb);
+    }
+    int d[RB];
+    uint32_t rr[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const uint32_t v = S.pos[B0 + b];
+      d[b] = 0;
+      rr[b] = 0;
+      if (v != kDummy) {
+        const uint64_t av = g->adj[v];
+        d[b] = g->deg[v] - 2 * __popcll(av & zb);
+#pragma unroll
+        for (int b2 = 0; b2 < RB; ++b2) {
+          const uint32_t w = S.pos[B0 + b2];
+          if (w != kDummy && ((av >> w) & 1u)) rr[b] |= 1u << b2;
+        }
+      }
+    }
+    cv[0] = c0;
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+      const int hb = 31 - __builtin_clz(r);
+      const int rest = r ^ (1 << hb);
+      cv[r] = cv[rest] + d[hb] - 2 * __popc(rr[hb] & (uint32_t)rest);
+    }
+  }
+
+  // h(z) = sum_t w_t [z_i != z_j] for every register amplitude at arrangement K
+  template <int K> __device__ __forceinline__ void hvals(const SetSpec& S, uint64_t zb, const int4* terms, int T, int (&hv)[NR]) const {
+    constexpr int B0 = G::b0(K);
+    int h0 = 0;
+    int dh[RB];
+    int corr[NR];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) dh[b] = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) corr[r] = 0;
+    for (int t = 0; t < T; ++t) {
+      const int4 tm = terms[t];
+      int ri = -1, rj = -1;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (S.pos[B0 + b] == (uint32_t)tm.x) ri = b;
+        if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
+      }
+      const int bi = (int)((zb >> tm.x) & 1u), bj = (int)((zb >> tm.y) & 1u);
+      h0 += tm.z * (bi ^ bj);
+      if (ri >= 0) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if (ri == b) dh[b] += tm.z * (1 - 2 * bj);
+      }
+      if (rj >= 0) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          if (rj == b) dh[b] += tm.z * (1 - 2 * bi);
+      }
+      if (ri >= 0 && rj >= 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (((r >> ri) & 1) && ((r >> rj) & 1)) corr[r] -= 2 * tm.z;
+      }
+    }
+    int lin[NR];
+    lin[0] = h0;
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+      const int hb = 31 - __builtin_clz(r);
+      lin[r] = lin[r ^ (1 << hb)] + dh[hb];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) hv[r] = lin[r] + corr[r];
+  }
+
+  // -------------------------------------------------------------- ops at one position
+  template <int K>
+  __device__ __forceinline__ void ops_at(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, const Ctx<R>& cx,
+                                         const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
+    if (!ops) return;
+    const uint64_t zb = zbase<K>(S, tile_base);
+    if (ops & OP_ENERGY) {
+      int hv[NR];
+      hvals<K>(S, zb, cx.terms, cx.T, hv);
+      double e = 0.0, nr = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const R p2 = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
+        e += (double)p2 * (double)hv[r];
+        nr += (double)p2;
+      }
+      acc.e += e;
+      acc.nrm += nr;
+      if (ops & OP_PERTERM) perterm<K>(S, zb, cx, zz_lds);
+      if (NS == 2 && make_lam) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const R h = (R)hv[r];
+          a[NS - 1][r] = mkv<R>(h * a[0][r].x, h * a[0][r].y);
+        }
+        lam_live = true;
+      }
+    }
+    if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
+      int cv[NR];
+      cuts<K>(S, zb, cx.g, cv);
+      if (NS == 2 && (ops & OP_GRADG)) {
+        R gs = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+        gacc += (double)gs;
+      }
+      if (ops & (OP_PHASE | OP_UNPHASE)) {
+        const R sg = (ops & OP_UNPHASE) ? R(-1) : R(1);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const V tv = ltab[cv[r]];
+          const R tc = tv.x, ts = sg * tv.y;  // exp(-i g c) = (tc, ts); inverse conjugates
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            if (s == 0 || lam_live) {
+              const V x = a[s][r];
+              a[s][r] = mkv<R>(x.x * tc - x.y * ts, x.x * ts + x.y * tc);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // <Z_i Z_j> partial sums per term, reduced per wave and added into LDS
+  template <int K> __device__ __forceinline__ void perterm(const SetSpec& S, uint64_t zb, const Ctx<R>& cx, double* zz_lds) const {
+    constexpr int B0 = G::b0(K);
+    R p2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) p2[r] = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
+    for (int t = 0; t < cx.T; ++t) {
+      const int4 tm = cx.terms[t];
+      int ri = -1, rj = -1;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (S.pos[B0 + b] == (uint32_t)tm.x) ri = b;
+        if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
+      }
+      const uint32_t sm = (ri >= 0 ? (1u << ri) : 0u) ^ (rj >= 0 ? (1u << rj) : 0u);
+      R acc = R(0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc += (__popc((uint32_t)r & sm) & 1) ? -p2[r] : p2[r];
+      const int odd = (int)(((zb >> tm.x) ^ (zb >> tm.y)) & 1u);
+      double v = odd ? -(double)acc : (double)acc;
+      v = wave_sum(v);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&zz_lds[t], v);
+    }
+  }
+
+  // -------------------------------------------------------------- global I/O at LAST
+  // Thread bits are tile bits 0..LB-1, register bits are tile bits LB..L-1.  Dummy tile
+  // bits (whole state smaller than a tile) have no global position: amplitudes with a
+  // dummy bit set are neither loaded (they are zero) nor stored.
+  __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const {
+    const uint32_t t = threadIdx.x;
+    uint64_t toff = 0;
+#pragma unroll
+    for (int i = 0; i < LB; ++i)
+      if (S.pos[i] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[i];
+    return toff;
+  }
+  template <int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+      if (((r >> b) & 1) && S.pos[LB + b] != kDummy) o |= (uint64_t)1 << S.pos[LB + b];
+    return o;
+  }
+  template <int r> __device__ __forceinline__ void load_r(int s, const V* p, const SetSpec& S) {
+    if (S.dummy && (tidx<G::b0(LAST), RB>(threadIdx.x, r) & S.dummy))
+      a[s][r] = mkv<R>(R(0), R(0));
+    else
+      a[s][r] = p[reg_off<r>(S)];
+  }
+  template <int r> __device__ __forceinline__ void store_r(int s, V* p, const SetSpec& S) const {
+    if (!(S.dummy && (tidx<G::b0(LAST), RB>(threadIdx.x, r) & S.dummy))) p[reg_off<r>(S)] = a[s][r];
+  }
+  template <int r = 0> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
+    if constexpr (r < NR) {
+      load_r<r>(s, p, S);
+      load_all<r + 1>(s, p, S);
+    }
+  }
+  template <int r = 0> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
+    if constexpr (r < NR) {
+      store_r<r>(s, p, S);
+      store_all<r + 1>(s, p, S);
+    }
+  }
+  __device__ __forceinline__ void load(int s, const V* __restrict__ src, const SetSpec& S, uint64_t tile_base) {
+    load_all(s, src + tile_base + thread_off(S), S);
+  }
+  __device__ __forceinline__ void store(int s, V* __restrict__ dst, const SetSpec& S, uint64_t tile_base) const {
+    store_all(s, dst + tile_base + thread_off(S), S);
+  }
+  __device__ __forceinline__ void init_plus(const SetSpec& S, R amp) {
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t j = tidx<G::b0(LAST), RB>(t, r);
+      a[0][r] = mkv<R>((j & S.dummy) ? R(0) : amp, R(0));
+    }
+  }
+
+  // -------------------------------------------------------------- one sweep on one tile
+  // Executes program `pg` on the tile with id `tile` of set S.  With `io` false the
+  // state stays in registers (whole state in one tile); stores still happen when the
+  // program asks for them and a destination exists.
+  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, uint64_t tile, const Ctx<R>& cx, bool io, V* lds_x,
+                      const V* ltab_pre, const V* ltab_mid, Acc& acc, double* zz_lds) {
+    const uint64_t tile_base = pdep64(tile, S.fixmask);
+    if (pg.flags & F_INIT) {
+      init_plus(S, cx.amp);
+      lam_live = false;
+    } else if (io) {
+      if (pg.flags & F_LOAD_PSI) load(0, cx.psi, S, tile_base);
+      lam_live = (pg.flags & F_LAM_LIVE) != 0;
+      if (NS == 2 && (pg.flags & F_LOAD_LAM)) load(NS - 1, cx.lam, S, tile_base);
+    }
+    const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
+    // position "pre" at the load arrangement
+    ops_at<LAST>(pg.pre_ops, make_lam, S, tile_base, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    int at = LAST;
+    if (pg.mixA_dir) {
+      const typename G::V cs = cx.mixcs[pg.mixA_layer];
+      const R c = cs.x, s = (pg.mixA_dir > 0) ? cs.y : -cs.y;
+      uint32_t todo = S.act;
+      const bool gr = pg.mixA_grad != 0;
+      static_assert(NA == 4, "arrangement sequence written for four arrangements");
+      mix_at<3>(todo, c, s, gr, acc.ba);
+      xchg<3, 0>(lds_x);
+      mix_at<0>(todo, c, s, gr, acc.ba);
+      xchg<0, 1>(lds_x);
+      mix_at<1>(todo, c, s, gr, acc.ba);
+      xchg<1, 2>(lds_x);
+      mix_at<2>(todo, c, s, gr, acc.ba);
+      at = P;
+    }
+    const bool need_mid = pg.mid_ops || pg.mixB_dir;
+    if (need_mid && at == LAST) {
+      xchg<LAST, P>(lds_x);
+      at = P;
+    }
+    ops_at<P>(pg.mid_ops, make_lam, S, tile_base, cx, ltab_mid, acc.gmid, acc, zz_lds);
+    if (pg.mixB_dir) {
+      const typename G::V cs = cx.mixcs[pg.mixB_layer];
+      const R c = cs.x, s = (pg.mixB_dir > 0) ? cs.y : -cs.y;
+      uint32_t todo = S.act;
+      const bool gr = pg.mixB_grad != 0;
+      mix_at<2>(todo, c, s, gr, acc.bb);
+      xchg<2, 1>(lds_x);
+      mix_at<1>(todo, c, s, gr, acc.bb);
+      xchg<1, 0>(lds_x);
+      mix_at<0>(todo, c, s, gr, acc.bb);
+      xchg<0, 3>(lds_x);
+      mix_at<3>(todo, c, s, gr, acc.bb);
+      at = LAST;
+    }
+    const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
+    const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
+    if ((st_psi || st_lam) && at != LAST) {
+      xchg<P, LAST>(lds_x);
+      at = LAST;
+    }
+    if (st_psi) store(0, cx.psi, S, tile_base);
+    if (st_lam) store(NS - 1, cx.lam, S, tile_base);
+  }
+};
+
+// ---------------------------------------------------------------------------------
+// workgroup reduction of a few doubles; result valid in thread 0
+template <int N> __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[wave * N + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) s += red[w * N + i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+template <class R> __device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename Cx<R>::V* tab, int layer,
+                                                            int cmax) {
+  if (layer < 0) return;
+  const typename Cx<R>::V* src = tab + (size_t)layer * (cmax + 1);
+  for (int c = threadIdx.x; c <= cmax; c += kThreads) ltab[c] = src[c];
+}
+
+// ---------------------------------------------------------------------------------
+// One sweep of a large state: one workgroup per tile.
+template <class R> struct SweepArgs {
+  typename Cx<R>::V* psi;
+  typename Cx<R>::V* lam;
+  const GraphDev* g;
+  const int4* terms;
+  const typename Cx<R>::V* tab;
+  const typename Cx<R>::V* mixcs;
+  double* partial;  // [nslot][ntiles]
+  int nslot;
+  int T;
+  int cmax;
+  R amp;
+  SetSpec set;
+  SweepProg prog;
+};
+
+// two 512-thread workgroups per CU: <= 128 VGPRs, LDS tile 64 KB (complex64)
+#define AAQ_TILE_BOUNDS __launch_bounds__(kThreads, 2)
+
+template <class R, int NS, bool PT> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
+  using G = Geo<R>;
+  using V = typename G::V;
+  __shared__ V lds_x[G::TILE];
+  __shared__ double red[(kThreads / 64) * 6];
+  __shared__ double zz[PT ? kMaxT : 1];
+  extern __shared__ unsigned char dyn_lds[];  // two phase tables of cmax+1 entries
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + (A.cmax + 1);
+  const uint32_t tile = blockIdx.x;
+  const uint8_t pre_ph = A.prog.pre_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG);
+  const uint8_t mid_ph = A.prog.mid_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG);
+  if (pre_ph) load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax);
+  if (mid_ph) load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax);
+  if (PT)
+    for (int t = threadIdx.x; t < A.T; t += kThreads) zz[t] = 0.0;
+  __syncthreads();
+  Ctx<R> cx{A.g, A.terms, A.tab, A.mixcs, A.psi, A.lam, A.amp, A.T, A.cmax};
+  Tile<R, NS> tl;
+  Acc acc;
+  acc.zero();
+  tl.run(A.prog, A.set, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+  block_sum<6>(v, red);
+  const uint32_t nt = A.set.ntiles;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) A.partial[(size_t)i * nt + tile] = v[i];
+  }
+  if (PT) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < A.T; t += kThreads) A.partial[(size_t)(SLOT_TERMS + t) * nt + tile] = zz[t];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Batched units: each workgroup takes the next unit from a counter and runs all of
+// its sweeps.  Units with n <= L keep their state in registers; larger units sweep
+// tile by tile over their own slice of the workspace.
+template <class R> struct UnitArgs {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* order;      // unit indices in processing order
+  unsigned char* ws;         // workspace base (graphs, terms, tables, states)
+  const double* params;      // [rows][2p] (only used by the table kernel)
+  double* out;               // [rows][2 + 2p]
+  int32_t* counter;
+  int count;
+  int out_stride;
+  int tabmax;                 // max cmax+1 over the units (dynamic LDS sizing)
+  typename Cx<R>::V* psi_io;  // optional external state for single-unit calls (n <= L): final psi store
+};
+
+template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A) {
+  using G = Geo<R>;
+  using V = typename G::V;
+  __shared__ V lds_x[G::TILE];
+  __shared__ double red[(kThreads / 64) * 6];
+  __shared__ double outacc[2 + 2 * kMaxP];
+  __shared__ int s_idx;
+  extern __shared__ unsigned char dyn_lds[];  // two phase tables of up to A.tabmax entries
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + A.tabmax;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+    if (idx >= A.count) break;
+    const int u = __builtin_amdgcn_readfirstlane(A.order[idx]);
+    const UnitDesc* D = A.units + u;
+    const int p = D->p;
+    for (int i = threadIdx.x; i < 2 + 2 * p; i += kThreads) outacc[i] = 0.0;
+    const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
+    const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
+    const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
+    const V* mixcs = tab + (size_t)p * (D->cmax + 1);
+    const bool big = D->state_off >= 0;
+    V* psi = big ? reinterpret_cast<V*>(A.ws + D->state_off) : A.psi_io;
+    V* lam = big ? psi + ((size_t)1 << D->n) : nullptr;
+    Ctx<R> cx{g, terms, tab, mixcs, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+    Tile<R, NS> tl;
+    tl.lam_live = false;
+    const int ns = D->nsweep;
+    for (int si = 0; si < ns; ++si) {
+      const SweepProg pg = A.progs[D->prog_off + si];
+      const SetSpec& S = D->sets[pg.set];
+      __syncthreads();  // previous sweep's table readers are done
+      if (pg.pre_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG)) load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax);
+      if (pg.mid_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG)) load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax);
+      __syncthreads();
+      Acc acc;
+      acc.zero();
+      const uint32_t nt = big ? S.ntiles : 1u;
+      for (uint32_t t = 0; t < nt; ++t) tl.run(pg, S, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
+      double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+      block_sum<6>(v, red);
+      if (threadIdx.x == 0) {
+        if (pg.pre_ops & OP_ENERGY || pg.mid_ops & OP_ENERGY) {
+          outacc[0] += v[0];
+          outacc[1] += v[1];
+        }
+        if (NS == 2) {
+          if (pg.pre_ops & OP_GRADG) outacc[2 + pg.pre_layer] += 2.0 * v[2];
+          if (pg.mid_ops & OP_GRADG) outacc[2 + pg.mid_layer] += 2.0 * v[3];
+          if (pg.mixA_grad) outacc[2 + p + pg.mixA_layer] += 2.0 * v[4];
+          if (pg.mixB_grad) outacc[2 + p + pg.mixB_layer] += 2.0 * v[5];
+        }
+      }
+    }
+    __syncthreads();
+    double* o = A.out + (size_t)D->row * A.out_stride;
+    for (int i = threadIdx.x; i < 2 + 2 * p; i += kThreads) o[i] = outacc[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Phase tables exp(-i gamma_l c), c = 0..cmax, and mixer (cos beta_l, sin beta_l).
+// gamma_l * c is formed and reduced in FP64; the result is rounded to R.
+template <class R>
+__global__ void k_tables(const double* __restrict__ gamma, const double* __restrict__ beta, int p, int cmax,
+                         typename Cx<R>::V* __restrict__ tab, typename Cx<R>::V* __restrict__ mixcs) {
+  const int tot = p * (cmax + 1);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+    const int l = i / (cmax + 1), c = i % (cmax + 1);
+    double sn, cs;
+    sincos(gamma[l] * (double)c, &sn, &cs);
+    tab[i] = mkv<R>((R)cs, (R)(-sn));
+  }
+  if (blockIdx.x == 0)
+    for (int l = threadIdx.x; l < p; l += blockDim.x) {
+      double sn, cs;
+      sincos(beta[l], &sn, &cs);
+      mixcs[l] = mkv<R>((R)cs, (R)sn);
+    }
+}
+
+// per-unit tables for a plan; block b handles unit b; also resets the work counter
+template <class R> __global__ void k_plan_tables(UnitArgs<R> A, int p, int pstride) {
+  using V = typename Cx<R>::V;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *A.counter = 0;
+  const UnitDesc* D = A.units + blockIdx.x;
+  const double* prm = A.params + (size_t)D->row * pstride;
+  V* tab = reinterpret_cast<V*>(A.ws + D->tab_off);
+  const int cm = D->cmax;
+  for (int i = threadIdx.x; i < p * (cm + 1); i += blockDim.x) {
+    const int l = i / (cm + 1), c = i % (cm + 1);
+    double sn, cs;
+    sincos(prm[l] * (double)c, &sn, &cs);
+    tab[i] = mkv<R>((R)cs, (R)(-sn));
+  }
+  V* mixcs = tab + (size_t)p * (cm + 1);
+  for (int l = threadIdx.x; l < p; l += blockDim.x) {
+    double sn, cs;
+    sincos(prm[p + l], &sn, &cs);
+    mixcs[l] = mkv<R>((R)cs, (R)sn);
+  }
+}
+
+// fixed-order sums of per-tile partials: out[o] = scale_o * sum_{sources of o} sum_tiles
+struct RedSrc {
+  int64_t off;   // element offset into the partial buffer
+  int32_t count;
+  int32_t out;   // output index
+  double scale;
+};
+__global__ void k_reduce(const double* __restrict__ partial, const RedSrc* __restrict__ src, const int32_t* __restrict__ src_begin,
+                         double* __restrict__ out) {
+  __shared__ double red[kThreads / 64];
+  const int o = blockIdx.x;
+  double tot = 0.0;
+  for (int k = src_begin[o]; k < src_begin[o + 1]; ++k) {
+    const RedSrc s = src[k];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < s.count; i += blockDim.x) v += partial[s.off + i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += red[w];
+      tot += s.scale * t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[o] = tot;
+}
+
+// one <Z_i Z_j> pass over the final state (per-term estimator structure)
+template <class R>
+__global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __restrict__ psi, uint64_t N, int i, int j,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += stride) {
+    const typename Cx<R>::V a = psi[z];
+    const double p2 = (double)(a.x * a.x + a.y * a.y);
+    acc += (((z >> i) ^ (z >> j)) & 1u) ? -p2 : p2;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// exact integer diagonal values through the same per-amplitude code as the kernels,
+// computed at arrangement K (0: load arrangement, 1: phase arrangement) of set S
+template <class R, int K>
+__global__ __launch_bounds__(kThreads) void k_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, SetSpec S,
+                                                   int32_t* __restrict__ out) {
+  using G = Geo<R>;
+  constexpr int KK = (K == 0) ? G::LAST : G::P;
+  const uint64_t tile_base = pdep64(blockIdx.x, S.fixmask);
+  Tile<R, 1> tl;
+  const uint64_t zb = tl.template zbase<KK>(S, tile_base);
+  int v[G::NR];
+  if (use_terms)
+    tl.template hvals<KK>(S, zb, terms, T, v);
+  else
+    tl.template cuts<KK>(S, zb, g, v);
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < G::NR; ++r) {
+    const uint32_t j = tidx<G::b0(KK), G::RB>(t, r);
+    if (j & S.dummy) continue;
+    uint64_t z = tile_base;
+    for (int b = 0; b < G::L; ++b)
+      if ((j >> b) & 1u) z |= (uint64_t)1 << S.pos[b];
+    out[z] = v[r];
+  }
+}
+
+}  // namespace aaq
+
+// ------------------------------------------------------------------------------------
+// launch wrappers used by the host code
+#include "aaq_launch.h"
+
+namespace aaq {
+
+template <class R> static hipError_t sweep_launch(const LaunchSweep& L, hipStream_t st) {
+  SweepArgs<R> A;
+  A.psi = reinterpret_cast<typename Cx<R>::V*>(L.psi);
+  A.lam = reinterpret_cast<typename Cx<R>::V*>(L.lam);
+  A.g = L.g;
+  A.terms = L.terms;
+  A.tab = reinterpret_cast<const typename Cx<R>::V*>(L.tab);
+  A.mixcs = reinterpret_cast<const typename Cx<R>::V*>(L.mixcs);
+  A.partial = L.partial;
+  A.nslot = L.nslot;
+  A.T = L.T;
+  A.cmax = L.cmax;
+  A.amp = (R)L.amp;
+  A.set = L.set;
+  A.prog = L.prog;
+  const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);
+  const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
+  if (pt)
+    hipLaunchKernelGGL((k_sweep<R, 1, true>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+  else if (L.two_states)
+    hipLaunchKernelGGL((k_sweep<R, 2, false>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_sweep<R, 1, false>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st) {
+  return dbl ? sweep_launch<double>(L, st) : sweep_launch<float>(L, st);
+}
+
+hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, void* mixcs, bool dbl,
+                         hipStream_t st) {
+  const int tot = p * (cmax + 1);
+  const int blocks = (tot + 255) / 256;
+  if (dbl)
+    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
+                       reinterpret_cast<double2*>(tab), reinterpret_cast<double2*>(mixcs));
+  else
+    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
+                       reinterpret_cast<float2*>(tab), reinterpret_cast<float2*>(mixcs));
+  return hipGetLastError();
+}
+
+template <class R> static UnitArgs<R> unit_args(const LaunchUnits& L) {
+  UnitArgs<R> A;
+  A.units = L.units;
+  A.progs = L.progs;
+  A.order = L.order;
+  A.ws = L.ws;
+  A.params = L.params;
+  A.out = L.out;
+  A.counter = L.counter;
+  A.count = L.count;
+  A.out_stride = L.out_stride;
+  A.tabmax = L.tabmax;
+  A.psi_io = reinterpret_cast<typename Cx<R>::V*>(L.psi_io);
+  return A;
+}
+
+hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_plan_tables<double>, dim3(L.count), dim3(256), 0, st, unit_args<double>(L), p, 2 * p);
+  else
+    hipLaunchKernelGGL(k_plan_tables<float>, dim3(L.count), dim3(256), 0, st, unit_args<float>(L), p, 2 * p);
+  return hipGetLastError();
+}
+
+hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, hipStream_t st) {
+  if (dbl) {
+    auto A = unit_args<double>(L);
+    const size_t dyn = 2 * sizeof(double2) * (size_t)L.tabmax;
+    if (grad)
+      hipLaunchKernelGGL((k_units<double, 2>), dim3(blocks), dim3(kThreads), dyn, st, A);
+    else
+      hipLaunchKernelGGL((k_units<double, 1>), dim3(blocks), dim3(kThreads), dyn, st, A);
+  } else {
+    auto A = unit_args<float>(L);
+    const size_t dyn = 2 * sizeof(float2) * (size_t)L.tabmax;
+    if (grad)
+      hipLaunchKernelGGL((k_units<float, 2>), dim3(blocks), dim3(kThreads), dyn, st, A);
+    else
+      hipLaunchKernelGGL((k_units<float, 1>), dim3(blocks), dim3(kThreads), dyn, st, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nout), dim3(256), 0, st, partial, reinterpret_cast<const RedSrc*>(src), src_begin, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, double* partial, int blocks, bool dbl, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j, partial);
+  else
+    hipLaunchKernelGGL(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr, int32_t* out,
+                       bool dbl, hipStream_t st) {
+  if (dbl) {
+    if (arr == 0)
+      hipLaunchKernelGGL((k_cuts<double, 0>), dim3(S.ntiles), dim3(kThreads), 0, st, g, terms, T, use_terms, S, out);
+    else
+      hipLaunchKernelGGL((k_cuts<double, 1>), dim3(S.ntiles), dim3(kThreads), 0, st, g, terms, T, use_terms, S, out);
+  } else {
+    if (arr == 0)
+      hipLaunchKernelGGL((k_cuts<float, 0>), dim3(S.ntiles), dim3(kThreads), 0, st, g, terms, T, use_terms, S, out);
+    else
+      hipLaunchKernelGGL((k_cuts<float, 1>), dim3(S.ntiles), dim3(kThreads), 0, st, g, terms, T, use_terms, S, out);
+  }
+  return hipGetLastError();
+}
+
+int tile_bits(bool dbl) { return dbl ? Geo<double>::L : Geo<float>::L; }
+
+}  // namespace aaq

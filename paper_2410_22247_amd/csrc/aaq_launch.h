@@ -1,0 +1,59 @@
+// Kernel launch interface between the host planner and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "aaq_internal.h"
+
+namespace aaq {
+
+struct LaunchSweep {
+  void* psi;
+  void* lam;
+  const GraphDev* g;
+  const int4* terms;
+  const void* tab;
+  const void* mixcs;
+  double* partial;
+  int nslot, T, cmax;
+  double amp;
+  SetSpec set;
+  SweepProg prog;
+  bool two_states;
+};
+
+struct LaunchUnits {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* order;
+  unsigned char* ws;
+  const double* params;
+  double* out;
+  int32_t* counter;
+  int count;
+  int out_stride;
+  int tabmax;
+  void* psi_io;
+};
+
+hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st);
+hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, void* mixcs, bool dbl,
+                         hipStream_t st);
+hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
+hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, hipStream_t st);
+hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
+                         hipStream_t st);
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, double* partial, int blocks, bool dbl,
+                          hipStream_t st);
+hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
+                       int32_t* out, bool dbl, hipStream_t st);
+int tile_bits(bool dbl);
+
+// RedSrc layout mirrored on the host
+struct RedSrcHost {
+  int64_t off;
+  int32_t count;
+  int32_t out;
+  double scale;
+};
+
+}  // namespace aaq

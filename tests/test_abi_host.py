@@ -1,0 +1,132 @@
+"""The C-ABI library on the host: it loads, exports every function declared in
+include/aaqaoa.h, and its host-side validation returns the documented status
+for each bad input (no GPU needed: validation runs before any HIP call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2410_22247_amd as A
+from paper_2410_22247_amd import _lib
+from workloads import graphs as G
+from workloads.configs import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "aaqaoa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(aaq_[a-z_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(_lib.EXPORTS) == set(names)
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in A.aaq_version()
+    L = _lib.lib()
+    for s in range(8):
+        assert L.aaq_status_string(s)
+
+
+def prob(g):
+    return A.Problem.from_workload(make_problem(g))
+
+
+def status_of(fn, *args, **kw):
+    try:
+        fn(*args, **kw)
+    except A.AAQError as e:
+        return e.status
+    return 0
+
+
+def test_validation_error_codes():
+    ok = prob(G.binary_tree(7))
+    assert status_of(A.aaq_validate, ok, 2) == 0
+    assert status_of(A.aaq_validate, ok, 0) == 1
+    assert status_of(A.aaq_validate, ok, 65) == 1
+    assert status_of(A.aaq_validate, A.Problem(0, np.zeros((0, 2))), 1) == 1
+    assert status_of(A.aaq_validate, A.Problem(35, np.zeros((0, 2))), 1) == 1
+    assert status_of(A.aaq_validate, A.Problem(3, [[0, 3]]), 1) == 2          # vertex out of range
+    assert status_of(A.aaq_validate, A.Problem(3, [[1, 1]]), 1) == 2          # self-loop
+    assert status_of(A.aaq_validate, A.Problem(3, [[0, 1], [1, 0]]), 1) == 2  # duplicate edge
+    # orbits: sizes must sum to |E|, representatives must be edges, sizes >= 1
+    e = [[0, 1], [1, 2], [2, 0]]
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0], [3]), 1) == 0
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0], [2]), 1) == 3
+    assert status_of(A.aaq_validate, A.Problem(3, e, [5], [3]), 1) == 3
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0, 1], [3, 0]), 1) == 3
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0, 0], [2, 1]), 1) == 3
+    # edge_orbit consistency
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0, 1], [2, 1], [0, 0, 1]), 1) == 3  # rep 1 lies in orbit 0
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0, 2], [2, 1], [0, 0, 1]), 1) == 0
+    assert status_of(A.aaq_validate, A.Problem(3, e, [0, 2], [2, 1], [0, 1, 1]), 1) == 3
+    # a graph with no edges has no orbits
+    assert status_of(A.aaq_validate, A.Problem(4, np.zeros((0, 2)), [], []), 1) == 0
+
+
+def test_entry_points_reject_bad_arguments_before_touching_the_gpu():
+    pr = prob(G.binary_tree(9))
+    L = _lib.lib()
+    e = ctypes.c_double()
+    g = np.array([0.1, 0.2])
+    b = np.array([0.3, 0.4])
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # null state
+    st = L.aaq_energy(pr.ref(), 2, dp(g), dp(b), 1, 0, 0, None, 0, fake, 1 << 20, None, ctypes.byref(e), None, None)
+    assert st == 1
+    # state too small
+    st = L.aaq_energy(pr.ref(), 2, dp(g), dp(b), 1, 0, 0, fake, 16, fake, 1 << 20, None, ctypes.byref(e), None, None)
+    assert st == 5
+    # workspace too small
+    st = L.aaq_energy(pr.ref(), 2, dp(g), dp(b), 1, 0, 0, fake, 1 << 20, fake, 8, None, ctypes.byref(e), None, None)
+    assert st == 5
+    # non-finite parameters
+    gn = np.array([np.nan, 0.2])
+    st = L.aaq_energy(pr.ref(), 2, dp(gn), dp(b), 1, 0, 0, fake, 1 << 20, fake, 1 << 20, None, ctypes.byref(e), None,
+                      None)
+    assert st == 4
+    # bad enums
+    st = L.aaq_energy(pr.ref(), 2, dp(g), dp(b), 7, 0, 0, fake, 1 << 20, fake, 1 << 20, None, ctypes.byref(e), None, None)
+    assert st == 1
+    st = L.aaq_energy(pr.ref(), 2, dp(g), dp(b), 1, 9, 0, fake, 1 << 20, fake, 1 << 20, None, ctypes.byref(e), None, None)
+    assert st == 1
+    # gradients need a lambda buffer; outputs untouched on error
+    dg = np.full(2, 7.0)
+    db = np.full(2, 7.0)
+    e.value = 3.5
+    st = L.aaq_energy_grad(pr.ref(), 2, dp(g), dp(b), 1, 0, fake, 1 << 20, None, 0, fake, 1 << 20, None,
+                           ctypes.byref(e), dp(dg), dp(db), None)
+    assert st == 1 and e.value == 3.5 and (dg == 7).all() and (db == 7).all()
+    assert b"lambda" in L.aaq_last_error_message()
+
+
+def test_workspace_and_state_sizes():
+    pr = prob(G.prufer_tree(26, 3))
+    assert A.aaq_state_bytes(pr) == 8 << 26
+    assert A.aaq_state_bytes(pr, A.AAQ_PREC_C128) == 16 << 26
+    w_e = A.aaq_workspace_size(pr, 4, False)
+    w_g = A.aaq_workspace_size(pr, 4, True)
+    assert 0 < w_e < w_g < (64 << 20)
+    assert A.aaq_num_sets(26) == 3 and A.aaq_num_sets(13) == 1 and A.aaq_num_sets(14) == 2
+    assert A.aaq_num_sets(34) == 4 and A.aaq_num_sets(33) == 4
+
+
+def test_plan_workspace_size_host_only():
+    probs = [prob(G.star(7)), prob(G.complete(9)), prob(G.prufer_tree(16, 2))]
+    w = A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True)
+    # the n = 16 unit needs psi and lambda slices in the workspace
+    assert w > 2 * (8 << 16)
+    assert status_of(A.aaq_plan_workspace_size, probs, 0, A.AAQ_OBS_HRED, True) == 1

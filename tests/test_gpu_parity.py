@@ -1,0 +1,232 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (the accuracy target of the complex64 path, normwise reading for
+gradients whose components can vanish):
+  energies   |E - E_ref| <= 1e-5 |E_ref|           (complex128: 1e-10)
+  gradients  ||g - g_ref|| <= 1e-5 ||g_ref|| and per component
+             |g_k - g_ref,k| <= 1e-5 max(|g_ref,k|, ||g_ref||)
+  <ZZ>       absolute 1e-5
+  cut values bit-exact
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2410_22247_amd as A
+from oracle import reduced as Rd
+from workloads import graphs as G
+from workloads.configs import OBS_HC, OBS_HRED, make_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EREL = 1e-5
+GREL = 1e-5
+
+
+def dev_bytes(nbytes):
+    return torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+
+
+def rand_graph(n, pe, seed):
+    rng = np.random.default_rng(seed)
+    es = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < pe]
+    return G.Graph(n, es or [(0, 1)], name=f"G({n},{pe},{seed})")
+
+
+def check_energy(e, ref, rel=EREL):
+    assert abs(e - ref) <= rel * max(abs(ref), 1e-12), (e, ref, abs(e - ref) / max(abs(ref), 1e-12))
+
+
+def check_grad(g, ref, rel=GREL):
+    g, ref = np.asarray(g), np.asarray(ref)
+    nrm = np.linalg.norm(ref)
+    assert np.linalg.norm(g - ref) <= rel * max(nrm, 1e-12), (g, ref)
+    assert np.all(np.abs(g - ref) <= rel * np.maximum(np.abs(ref), nrm) + 1e-14), (g, ref)
+
+
+# ------------------------------------------------------------------ cut values (bit-exact)
+CUT_GRAPHS = [G.binary_tree(5), rand_graph(9, 0.5, 1), G.complete(13), G.star(13), G.prufer_tree(14, 3),
+              G.generalized_petersen(8, 3), rand_graph(17, 0.3, 2), G.random_regular(3, 22, seed=7)]
+
+
+@pytest.mark.parametrize("g", CUT_GRAPHS, ids=lambda g: f"{g.name}-n{g.n}")
+def test_cut_values_bit_exact_every_layout(g):
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    ws = dev_bytes(1 << 16)
+    out = torch.empty(1 << g.n, dtype=torch.int32, device="cuda")
+    ref_c = O.cut_values(g.n, g.edge_array())
+    ref_h = O.term_values(g.n, wp.terms(OBS_HRED)).astype(np.int64)
+    for prec in (A.AAQ_PREC_C64, A.AAQ_PREC_C128):
+        for s in range(A.aaq_num_sets(g.n, prec)):
+            for arr in (0, 1):
+                for obs, ref in ((A.AAQ_OBS_HC, ref_c), (A.AAQ_OBS_HRED, ref_h)):
+                    out.fill_(-1)
+                    A.aaq_cut_values_layout(pr, obs, s, arr, prec, ws, out)
+                    got = out.cpu().numpy()
+                    assert np.array_equal(got, ref), (prec, s, arr, obs)
+    out.fill_(-1)
+    A.aaq_cut_values(pr, A.AAQ_OBS_HC, ws, out)
+    assert np.array_equal(out.cpu().numpy(), ref_c)
+
+
+# ------------------------------------------------------------------ energies
+ENERGY_CASES = [
+    (G.Graph(1, []), 1), (G.Graph(2, [(0, 1)]), 2), (G.binary_tree(5), 3), (rand_graph(8, 0.5, 4), 2),
+    (G.complete(12), 1), (G.binary_tree(13), 2), (G.prufer_tree(14, 1), 3), (G.star(16), 2),
+    (G.generalized_petersen(9, 2), 2), (G.prufer_tree(20, 6), 3), (rand_graph(22, 0.15, 9), 1),
+]
+
+
+@pytest.mark.parametrize("g,p", ENERGY_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_energy_matches_oracle(g, p):
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(g.n * 31 + p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    st = dev_bytes(A.aaq_state_bytes(pr, A.AAQ_PREC_C128))
+    for obs in (OBS_HC, OBS_HRED):
+        ref = O.energy(g.n, g.edge_array(), wp.terms(obs), gam, bet) if g.m else 0.0
+        for prec, tol in ((A.AAQ_PREC_C64, EREL), (A.AAQ_PREC_C128, 1e-10)):
+            ws = dev_bytes(A.aaq_workspace_size(pr, p, False, obs, A.AAQ_AGG_FUSED, prec))
+            e, _, nrm = A.aaq_energy(pr, gam, bet, obs, A.AAQ_AGG_FUSED, prec, st, ws)
+            if g.m:
+                check_energy(e, ref, tol)
+            else:
+                assert e == 0.0
+            assert abs(nrm - 1) <= (1e-5 if prec == A.AAQ_PREC_C64 else 1e-12)
+
+
+def test_energy_hred_equals_hc_and_closed_form():
+    g = G.binary_tree(15)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, 1, A.AAQ_OBS_HRED, A.AAQ_PREC_C128, grad=False)
+    for gam, bet in [(math.pi / 3, math.pi / 8), (0.4, 1.3)]:
+        cf = 7 + 0.25 * math.sin(4 * bet) * math.sin(gam) * (8 + 2 * math.cos(gam) + 18 * math.cos(gam) ** 2)
+        eh = est.energy([gam], [bet], obs=A.AAQ_OBS_HC)[0]
+        er = est.energy([gam], [bet], obs=A.AAQ_OBS_HRED)[0]
+        assert abs(eh - cf) < 1e-11 and abs(er - cf) < 1e-11
+
+
+@pytest.mark.parametrize("agg", [A.AAQ_AGG_PER_TERM, A.AAQ_AGG_PASS_PER_TERM], ids=["per_term", "pass_per_term"])
+@pytest.mark.parametrize("g,p", [(G.binary_tree(11), 2), (G.complete(16), 1), (G.prufer_tree(18, 2), 2)],
+                         ids=["tree11", "K16", "prufer18"])
+def test_per_term_aggregation(agg, g, p):
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(5)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HC, A.AAQ_PREC_C64, grad=False, agg=agg)
+    for obs in (OBS_HC, OBS_HRED):
+        e_ref, _, zz_ref, _ = O.energy(g.n, g.edge_array(), wp.terms(obs), gam, bet, full=True)
+        e, zz, _ = est.energy(gam, bet, obs=obs, agg=agg)
+        assert np.max(np.abs(zz - zz_ref)) <= 1e-5
+        check_energy(e, e_ref)
+    # Eq. A3 on the device: per-edge <ZZ> equal within every orbit
+    _, zz, _ = est.energy(gam, bet, obs=OBS_HC, agg=agg)
+    for orb in wp.orbits.orbits:
+        assert np.ptp(zz[orb]) <= 2e-6
+
+
+# ------------------------------------------------------------------ gradients
+GRAD_CASES = [
+    (G.Graph(2, [(0, 1)]), 1), (G.binary_tree(6), 2), (rand_graph(9, 0.5, 2), 3), (G.complete(10), 2),
+    (G.binary_tree(13), 1), (G.prufer_tree(14, 5), 2), (G.star(17), 3), (G.prufer_tree(21, 8), 2),
+]
+
+
+@pytest.mark.parametrize("g,p", GRAD_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_energy_grad_matches_oracle_adjoint(g, p):
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(g.n * 7 + p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    for obs in (OBS_HRED, OBS_HC):
+        e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(obs), gam, bet)
+        est = A.Estimator(pr, p, obs, A.AAQ_PREC_C64, grad=True)
+        e, dg, db, nrm = est.energy_grad(gam, bet)
+        check_energy(e, e_ref)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref]))
+        assert abs(nrm - 1) < 1e-5
+
+
+def test_energy_grad_complex128():
+    g = G.prufer_tree(15, 4)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    gam, bet = np.array([0.7, 2.1]), np.array([0.3, 1.2])
+    e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(OBS_HRED), gam, bet)
+    est = A.Estimator(pr, 2, OBS_HRED, A.AAQ_PREC_C128, grad=True)
+    e, dg, db, _ = est.energy_grad(gam, bet)
+    check_energy(e, e_ref, 1e-11)
+    check_grad(np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref]), 1e-10)
+
+
+def test_energy_grad_n26_config3_point():
+    """Full configuration-3 size (n = 26, p = 4, 2^26 amplitudes): gradient against
+    the light-cone FP64 adjoint (exact for the QAOA state), energy also against the
+    full-state oracle at one point."""
+    from workloads.configs import config3
+
+    wp, p, gams, bets = config3(2)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    terms = wp.terms(OBS_HRED)
+    for k in range(2):
+        e, dg, db, nrm = est.energy_grad(gams[k], bets[k])
+        e_lc, dg_lc, db_lc, mb = Rd.light_cone_energy_grad(wp.n, wp.edges(), terms, gams[k], bets[k])
+        assert mb <= 20
+        check_energy(e, e_lc)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc]))
+        eh = est.energy(gams[k], bets[k], obs=OBS_HC)[0]
+        check_energy(eh, e_lc)
+    e_full = O.energy(wp.n, wp.edges(), terms, gams[0], bets[0])
+    check_energy(est.energy(gams[0], bets[0])[0], e_full)
+
+
+# ------------------------------------------------------------------ batched plans
+def test_plan_matches_single_calls_and_oracle():
+    graphs = [G.star(7), G.complete(9), G.prufer_tree(12, 1), G.binary_tree(13), G.prufer_tree(15, 2),
+              G.random_regular(3, 16, seed=3), G.prufer_tree(18, 4)]
+    wps = [make_problem(g) for g in graphs]
+    prs = [A.Problem.from_workload(w) for w in wps]
+    p = 2
+    rng = np.random.default_rng(11)
+    units = [prs[i % len(prs)] for i in range(2 * len(prs))]
+    gam = rng.uniform(0, math.pi, (len(units), p))
+    bet = rng.uniform(0, math.pi / 2, (len(units), p))
+    for use_graph in (False, True):
+        plan = A.Plan(units, p, A.AAQ_OBS_HRED, with_grad=True, use_graph=use_graph)
+        plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
+        for rep in range(3):  # graph replays with eager work in between
+            out = plan.execute().cpu().numpy()
+            torch.cuda.synchronize()
+            for u, pr in enumerate(units):
+                w = wps[u % len(prs)]
+                e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+                check_energy(out[u, 0], e_ref)
+                assert abs(out[u, 1] - 1) < 1e-5
+                check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
+            plan.params.mul_(1.0)
+        plan.close()
+
+
+def test_plan_energy_only_complex128_grid():
+    """Configuration-1 style: the 15-vertex binary tree, p = 1, a parameter grid,
+    complex128, both observables equal to the closed form."""
+    g = G.binary_tree(15)
+    pr = A.Problem.from_workload(make_problem(g))
+    a = np.arange(16)
+    gg, bb = np.meshgrid(a * math.pi / 15, a * math.pi / 30, indexing="ij")
+    gam, bet = gg.reshape(-1), bb.reshape(-1)
+    cf = 7 + 0.25 * np.sin(4 * bet) * np.sin(gam) * (8 + 2 * np.cos(gam) + 18 * np.cos(gam) ** 2)
+    for obs in (A.AAQ_OBS_HC, A.AAQ_OBS_HRED):
+        plan = A.Plan([pr] * 256, 1, obs, with_grad=False, prec=A.AAQ_PREC_C128)
+        plan.params.copy_(torch.from_numpy(np.stack([gam, bet], 1)))
+        out = plan.execute().cpu().numpy()
+        assert np.max(np.abs(out[:, 0] - cf)) < 1e-11
+        plan.close()
