@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: energy + adjoint gradient evaluations per second of the p=4 QAOA
+estimator on the 26-vertex random tree (Pruefer sequence, seed 3), H_red observable,
+complex64 amplitudes, one MI355X.
+
+One step = one aaq_energy_grad call (the whole hot path: phase tables, every forward
+and backward statevector sweep, the FP64 reductions) at one of the 32 seeded
+parameter points.  Prints ONE JSON line.  Alongside the headline number it reports
+the roofline of the dominant kernel (HIP events around every launch, on the stream
+the kernel runs on), the FP64 CPU oracle timed on the host cores, and H_red vs H_C
+in the three aggregation modes.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "<H>+adjoint-grad evals/s (n=26,p=4), % HBM roofline, H_red vs H_C"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCES = ["paper_2410_22247_amd/csrc/aaq_kernels.hip", "paper_2410_22247_amd/csrc/aaq_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kclass: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None when
+    they were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    k = t.get("kernels", {}).get(kclass)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time for the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2410_22247_amd as A
+    from workloads.configs import config3
+
+    wp, p, gams, bets = config3(32)
+    pr = A.Problem.from_workload(wp)
+    torch.cuda.set_device(0)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    stream = torch.cuda.current_stream()
+
+    for k in range(args.warmup):
+        est.energy_grad(gams[k % 32], bets[k % 32])
+    torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- timed region
+    A.aaq_timing_read(reset=True)
+    A.aaq_timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    energies = []
+    for k in range(args.steps):
+        e, dg, db, nrm = est.energy_grad(gams[k % 32], bets[k % 32])
+        energies.append(e)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    A.aaq_timing_enable(False)
+    timing = A.aaq_timing_read(reset=True)
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = args.steps / wall
+
+    # dominant kernel class by summed event time
+    dom = max(timing, key=lambda c: timing[c]["total_ms"])
+    d = timing[dom]
+    per_launch_bytes = d["bytes"] / d["launches"]
+    avg_ms = d["total_ms"] / d["launches"]
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = load_traffic(dom)
+    sweep_bytes = sum(timing[c]["bytes"] for c in timing)
+    sweep_ms = sum(timing[c]["total_ms"] for c in ("sweep_1state", "sweep_2state") if c in timing)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {
+            "workload": "random tree n=26 (Pruefer, seed 3), p=4, H_red (20 orbit terms), energy + adjoint gradient, "
+                        "complex64, 32 seeded (gamma, beta) points cycled",
+            "n": 26, "p": 4, "observable": "H_red", "edges": int(wp.m), "orbits": int(wp.orbits.count),
+            "tile_sets": A.aaq_num_sets(26),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": per_launch_bytes,
+            "avg_launch_ms": round(avg_ms, 5),
+            "launches": d["launches"],
+        },
+        "kernel_timing": {c: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                              "GB/s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["bytes"] else None}
+                          for c, v in timing.items()},
+        "sweep_bytes_per_eval": sweep_bytes / args.steps,
+        "sweep_GBps_per_eval": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1) if sweep_ms else None,
+        "event_ms_per_step": round(ev0.elapsed_time(ev1) / args.steps, 4),
+    }
+
+    # ---------------------------------------------------------------- H_red vs H_C
+    if not args.no_extras:
+        ext = {}
+        reps = 10
+
+        def rate(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return reps / (time.perf_counter() - t)
+
+        g0, b0 = gams[0], bets[0]
+        ests = {agg: A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=False, agg=agg)
+                for agg in (A.AAQ_AGG_FUSED, A.AAQ_AGG_PER_TERM, A.AAQ_AGG_PASS_PER_TERM)}
+        names = {A.AAQ_AGG_FUSED: "fused", A.AAQ_AGG_PER_TERM: "per_term", A.AAQ_AGG_PASS_PER_TERM: "pass_per_term"}
+        for agg, es in ests.items():
+            r_red = rate(lambda: es.energy(g0, b0, obs=A.AAQ_OBS_HRED))
+            r_hc = rate(lambda: es.energy(g0, b0, obs=A.AAQ_OBS_HC))
+            ext[f"energy_{names[agg]}"] = {"H_red_evals_s": round(r_red, 2), "H_C_evals_s": round(r_hc, 2),
+                                           "speedup": round(r_red / r_hc, 3)}
+        del ests
+        r_red = rate(lambda: est.energy_grad(g0, b0, obs=A.AAQ_OBS_HRED))
+        r_hc = rate(lambda: est.energy_grad(g0, b0, obs=A.AAQ_OBS_HC))
+        ext["energy_grad_fused"] = {"H_red_evals_s": round(r_red, 2), "H_C_evals_s": round(r_hc, 2),
+                                    "speedup": round(r_red / r_hc, 3)}
+        ext["orbit_ratio_E_over_OE"] = round(wp.m / wp.orbits.count, 3)
+        out["hred_vs_hc"] = ext
+
+    # ---------------------------------------------------------------- CPU oracle baseline
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        terms = wp.terms(1)
+        n_done = 0
+        t = time.perf_counter()
+        while True:
+            O.energy_grad(wp.n, wp.edges(), terms, gams[n_done % 32], bets[n_done % 32])
+            n_done += 1
+            el = time.perf_counter() - t
+            if el >= args.cpu_seconds or el / n_done * (n_done + 1) > 2.5 * args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {
+            "value": round(n_done / el, 4),
+            "unit": "evals/s",
+            "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_done} full-state FP64 energy + adjoint-gradient evaluation(s) of the same workload "
+                      f"(n=26, p=4, H_red), first {n_done} of the 32 points, {el:.1f} s",
+        }
+        out["gpu_over_cpu"] = round(value / (n_done / el), 1)
+
+    out["kernel_sha"] = kernel_hash()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

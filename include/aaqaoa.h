@@ -187,6 +187,21 @@ aaq_status aaq_plan_execute(aaq_plan *plan, const double *d_params, double *d_ou
 void aaq_plan_destroy(aaq_plan *plan);
 
 /* ---------------------------------------------------------------- diagnostics */
+/* Per-kernel timing.  While enabled, every kernel launch of the library is bracketed
+ * by two HIP events recorded on the stream it is launched on; aaq_timing_read waits
+ * for the recorded events and returns, per kernel class ("sweep_1state",
+ * "sweep_2state", "tables", "reduce", "zz_pass", "units"), the launch count, the summed
+ * event time and the algorithmic bytes of the state buffers the launches read and
+ * write.  For measurement only: it adds two event records per launch. */
+typedef struct {
+  char name[32];
+  long long launches;
+  double total_ms;
+  double bytes;
+} aaq_kernel_timing;
+aaq_status aaq_timing_enable(int on);
+aaq_status aaq_timing_read(aaq_kernel_timing *out, int max, int *count, int reset);
+
 const char *aaq_status_string(aaq_status s);
 const char *aaq_last_error_message(void);
 

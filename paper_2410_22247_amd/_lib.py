@@ -20,6 +20,15 @@ class CProblem(ctypes.Structure):
     ]
 
 
+class CKernelTiming(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32),
+        ("launches", ctypes.c_longlong),
+        ("total_ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
 class CPlanOpts(ctypes.Structure):
     _fields_ = [
         ("use_graph", ctypes.c_int),
@@ -33,6 +42,7 @@ EXPORTS = (
     "aaq_validate", "aaq_state_bytes", "aaq_workspace_size", "aaq_energy", "aaq_energy_grad", "aaq_cut_values",
     "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
     "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
+    "aaq_timing_enable", "aaq_timing_read",
 )
 
 
@@ -66,6 +76,8 @@ def lib():
         "aaq_status_string": (ctypes.c_char_p, [i]),
         "aaq_last_error_message": (ctypes.c_char_p, []),
         "aaq_version": (ctypes.c_char_p, []),
+        "aaq_timing_enable": (i, [i]),
+        "aaq_timing_read": (i, [ctypes.POINTER(CKernelTiming), i, ctypes.POINTER(i), i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

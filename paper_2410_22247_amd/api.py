@@ -223,6 +223,19 @@ def aaq_plan_destroy(plan) -> None:
         _lib.lib().aaq_plan_destroy(plan)
 
 
+def aaq_timing_enable(on: bool) -> None:
+    _check(_lib.lib().aaq_timing_enable(int(bool(on))))
+
+
+def aaq_timing_read(reset: bool = True) -> dict:
+    """{class: {"launches", "total_ms", "bytes"}} accumulated since the last reset."""
+    arr = (_lib.CKernelTiming * 16)()
+    cnt = ctypes.c_int()
+    _check(_lib.lib().aaq_timing_read(arr, 16, ctypes.byref(cnt), int(bool(reset))))
+    return {arr[k].name.decode(): {"launches": int(arr[k].launches), "total_ms": float(arr[k].total_ms),
+                                   "bytes": float(arr[k].bytes)} for k in range(min(cnt.value, 16))}
+
+
 # ------------------------------------------------------------------ conveniences
 class Estimator:
     """Owns the device buffers (torch) for repeated evaluations of one instance."""
@@ -233,8 +246,9 @@ class Estimator:
 
         self.prob, self.p, self.obs, self.prec, self.agg = prob, int(p), obs, prec, agg
         sb = aaq_state_bytes(prob, prec)
-        wb = max(aaq_workspace_size(prob, p, grad, obs, AAQ_AGG_FUSED, prec),
-                 aaq_workspace_size(prob, p, False, obs, agg, prec))
+        # large enough for either observable, so one Estimator serves H_C and H_red
+        wb = max(max(aaq_workspace_size(prob, p, grad, o, AAQ_AGG_FUSED, prec),
+                     aaq_workspace_size(prob, p, False, o, agg, prec)) for o in (AAQ_OBS_HC, AAQ_OBS_HRED))
         self.state = torch.empty(sb, dtype=torch.uint8, device=device)
         self.lam = torch.empty(sb, dtype=torch.uint8, device=device) if grad else None
         self.ws = torch.empty(wb, dtype=torch.uint8, device=device)

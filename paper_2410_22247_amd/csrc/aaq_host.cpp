@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <utility>
@@ -33,6 +34,47 @@ aaq_status fail(aaq_status s, const std::string& msg) {
   } while (0)
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ optional per-kernel timing
+// When enabled, launches are bracketed by HIP events on the launching stream and the
+// elapsed times are accumulated per kernel class with the algorithmic bytes moved.
+enum KClass { KC_SWEEP1 = 0, KC_SWEEP2 = 1, KC_TABLES = 2, KC_REDUCE = 3, KC_ZZPASS = 4, KC_UNITS = 5, KC_N = 6 };
+const char* kc_name[KC_N] = {"sweep_1state", "sweep_2state", "tables", "reduce", "zz_pass", "units"};
+struct Pending {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<Pending> g_pending;
+double g_tot_ms[KC_N], g_tot_bytes[KC_N];
+long long g_launches[KC_N];
+
+struct TimedLaunch {
+  bool on;
+  Pending pe;
+  hipStream_t st;
+  TimedLaunch(int cls, double bytes, hipStream_t s) : on(false), st(s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    pe.cls = cls;
+    pe.bytes = bytes;
+    if (hipEventCreate(&pe.a) != hipSuccess) return;
+    if (hipEventCreate(&pe.b) != hipSuccess) {
+      (void)hipEventDestroy(pe.a);
+      return;
+    }
+    on = hipEventRecord(pe.a, st) == hipSuccess;
+  }
+  void done() {
+    if (!on) return;
+    (void)hipEventRecord(pe.b, st);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back(pe);
+    on = false;
+  }
+};
 
 // ------------------------------------------------------------------ validation
 aaq_status validate_problem(const aaq_problem* pr) {
@@ -476,7 +518,11 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   std::memcpy(up.data() + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
   HIPCHK(hipMemcpyAsync(ws, up.data(), L.upload_end, hipMemcpyHostToDevice, hs));
   const double* dparams = (const double*)(ws + L.params);
-  HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, ws + L.mixcs, S.dbl, hs));
+  {
+    TimedLaunch tl(KC_TABLES, 0.0, hs);
+    HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, ws + L.mixcs, S.dbl, hs));
+    tl.done();
+  }
   for (int sw = 0; sw < L.nsweep; ++sw) {
     LaunchSweep A;
     A.psi = d_state;
@@ -493,16 +539,28 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     A.set = S.sets[S.progs[sw].set];
     A.prog = S.progs[sw];
     A.two_states = needs_two_states(S.progs[sw]);
+    const SweepProg& pg = S.progs[sw];
+    const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
+                      !!(pg.flags & F_STORE_LAM);
+    TimedLaunch tl(A.two_states ? KC_SWEEP2 : KC_SWEEP1, (double)moves * (double)need_state, hs);
     HIPCHK(launch_sweep(A, S.dbl, hs));
+    tl.done();
   }
   if (agg == AAQ_AGG_PASS_PER_TERM) {
     double* zp = (double*)(ws + L.partial) + (size_t)L.nsweep * L.nslot * L.ntiles;
-    for (int t = 0; t < S.T; ++t)
+    for (int t = 0; t < S.T; ++t) {
+      TimedLaunch tl(KC_ZZPASS, (double)need_state, hs);
       HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y, zp + (size_t)t * kZZBlocks, kZZBlocks,
                             S.dbl, hs));
+      tl.done();
+    }
   }
-  HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb), (double*)(ws + L.out),
-                       L.nout, hs));
+  {
+    TimedLaunch tl(KC_REDUCE, 0.0, hs);
+    HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb),
+                         (double*)(ws + L.out), L.nout, hs));
+    tl.done();
+  }
   res.assign(L.nout, 0.0);
   HIPCHK(hipMemcpyAsync(res.data(), ws + L.out, sizeof(double) * L.nout, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
@@ -659,7 +717,9 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
   U.tabmax = P->tabmax;
   U.psi_io = nullptr;
   HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));
+  TimedLaunch tl(KC_UNITS, 0.0, hs);
   HIPCHK(launch_units(U, P->grad, P->dbl, P->blocks, hs));
+  tl.done();
   return AAQ_OK;
 }
 
@@ -878,6 +938,43 @@ aaq_status aaq_plan_execute(aaq_plan* P, const double* d_params, double* d_out, 
     P->g_stream = hs;
   }
   HIPCHK(hipGraphLaunch(P->exec, hs));
+  return AAQ_OK;
+}
+
+aaq_status aaq_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = on != 0;
+  return AAQ_OK;
+}
+
+aaq_status aaq_timing_read(aaq_kernel_timing* out, int max, int* count, int reset) {
+  if (!count || (max > 0 && !out)) return fail(AAQ_ERR_INVALID_ARG, "NULL output");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& pe : g_pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventSynchronize(pe.b));
+    HIPCHK(hipEventElapsedTime(&ms, pe.a, pe.b));
+    g_tot_ms[pe.cls] += ms;
+    g_tot_bytes[pe.cls] += pe.bytes;
+    g_launches[pe.cls] += 1;
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  g_pending.clear();
+  int k = 0;
+  for (int c = 0; c < KC_N; ++c) {
+    if (!g_launches[c]) continue;
+    if (k < max) {
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", kc_name[c]);
+      out[k].launches = g_launches[c];
+      out[k].total_ms = g_tot_ms[c];
+      out[k].bytes = g_tot_bytes[c];
+    }
+    ++k;
+  }
+  *count = k;
+  if (reset)
+    for (int c = 0; c < KC_N; ++c) g_tot_ms[c] = g_tot_bytes[c] = 0.0, g_launches[c] = 0;
   return AAQ_OK;
 }
 
