@@ -58,6 +58,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time for the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
@@ -68,6 +70,14 @@ def main():
 
     import paper_2410_22247_amd as A
     from workloads.configs import config3
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     wp, p, gams, bets = config3(32)
     pr = A.Problem.from_workload(wp)

@@ -170,6 +170,18 @@ std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
 // tile with the lowest remaining global bits, so that every tile holds global bits
 // 0..4 (>= 256 contiguous bytes per access).  k is the smallest possible, sizes as
 // even as the caps allow.
+// element offsets of the register slots at the load/store arrangement (register bits
+// are the top RB = L - 9 tile bits)
+void fill_roff(SetSpec& s, int L) {
+  const int RB = L - 9;
+  for (int r = 0; r < 16; ++r) {
+    uint64_t o = 0;
+    for (int b = 0; b < RB; ++b)
+      if (((r >> b) & 1) && s.pos[9 + b] != kDummy) o |= 1ull << s.pos[9 + b];
+    s.roff[r] = (r < (1 << RB)) ? o : 0;
+  }
+}
+
 std::vector<SetSpec> make_sets(int n, int L) {
   std::vector<SetSpec> sets;
   if (n <= L) {
@@ -180,6 +192,7 @@ std::vector<SetSpec> make_sets(int n, int L) {
     s.dummy = ((1u << L) - 1u) & ~s.act;
     s.fixmask = 0;
     s.ntiles = 1;
+    fill_roff(s, L);
     sets.push_back(s);
     return sets;
   }
@@ -227,6 +240,7 @@ std::vector<SetSpec> make_sets(int n, int L) {
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     S.fixmask = all & ~tilemask;
     S.ntiles = 1u << (n - L);
+    fill_roff(S, L);
     sets.push_back(S);
   }
   return sets;
@@ -386,8 +400,8 @@ bool needs_two_states(const SweepProg& s) {
 
 // ------------------------------------------------------------------ single-instance layout
 struct Layout {
-  size_t graph = 0, terms = 0, params = 0, src = 0, srcb = 0, upload_end = 0;
-  size_t tab = 0, mixcs = 0, partial = 0, zzpart = 0, out = 0, total = 0;
+  size_t graph = 0, terms = 0, params = 0, src = 0, srcb = 0, progs = 0, sets = 0, upload_end = 0;
+  size_t tab = 0, scales = 0, partial = 0, zzpart = 0, out = 0, total = 0;
   int nsweep = 0, nslot = 0, ntiles = 0, nout = 0, nsrc = 0, T = 0;
 };
 
@@ -470,12 +484,16 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   off = align_up(off + sizeof(RedSrcHost) * std::max(L.nsrc, 1));
   L.srcb = off;
   off = align_up(off + sizeof(int32_t) * (L.nout + 1));
+  L.progs = off;
+  off = align_up(off + sizeof(SweepProg) * L.nsweep);
+  L.sets = off;
+  off = align_up(off + sizeof(SetSpec) * S.sets.size());
   L.upload_end = off;
   const size_t amp = S.dbl ? 16 : 8;
   L.tab = off;
   off = align_up(off + amp * (size_t)p * (S.cmax + 1));
-  L.mixcs = off;
-  off = align_up(off + amp * p);
+  L.scales = off;
+  off = align_up(off + sizeof(SwScale) * (L.nsweep + 1));
   L.partial = off;
   off = align_up(off + sizeof(double) * (size_t)(sweep_part + (zzp ? (int64_t)S.T * kZZBlocks : 0)));
   L.out = off;
@@ -516,11 +534,14 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   std::memcpy(up.data() + L.params + sizeof(double) * p, beta, sizeof(double) * p);
   if (!S.src.empty()) std::memcpy(up.data() + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
   std::memcpy(up.data() + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
+  std::memcpy(up.data() + L.progs, S.progs.data(), sizeof(SweepProg) * S.progs.size());
+  std::memcpy(up.data() + L.sets, S.sets.data(), sizeof(SetSpec) * S.sets.size());
   HIPCHK(hipMemcpyAsync(ws, up.data(), L.upload_end, hipMemcpyHostToDevice, hs));
   const double* dparams = (const double*)(ws + L.params);
   {
     TimedLaunch tl(KC_TABLES, 0.0, hs);
-    HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, ws + L.mixcs, S.dbl, hs));
+    HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, (const SweepProg*)(ws + L.progs), L.nsweep,
+                         (const SetSpec*)(ws + L.sets), (SwScale*)(ws + L.scales), S.dbl, hs));
     tl.done();
   }
   for (int sw = 0; sw < L.nsweep; ++sw) {
@@ -530,7 +551,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     A.g = (const GraphDev*)(ws + L.graph);
     A.terms = (const int4*)(ws + L.terms);
     A.tab = ws + L.tab;
-    A.mixcs = ws + L.mixcs;
+    A.scale = (const SwScale*)(ws + L.scales) + sw;
     A.partial = (double*)(ws + L.partial) + (size_t)sw * L.nslot * L.ntiles;
     A.nslot = L.nslot;
     A.T = S.T;
@@ -550,7 +571,8 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     double* zp = (double*)(ws + L.partial) + (size_t)L.nsweep * L.nslot * L.ntiles;
     for (int t = 0; t < S.T; ++t) {
       TimedLaunch tl(KC_ZZPASS, (double)need_state, hs);
-      HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y, zp + (size_t)t * kZZBlocks, kZZBlocks,
+      HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y,
+                            &((const SwScale*)(ws + L.scales) + L.nsweep)->s_pre, zp + (size_t)t * kZZBlocks, kZZBlocks,
                             S.dbl, hs));
       tl.done();
     }
@@ -678,7 +700,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];
     D.tab_off = (int64_t)off;
-    off = align_up(off + amp * ((size_t)p * (D.cmax + 1) + p));
+    off = align_up(off + amp * (size_t)p * (D.cmax + 1) + sizeof(SwScale) * (D.nsweep + 1));
   }
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];

@@ -50,6 +50,7 @@ struct SetSpec {
   uint64_t fixmask;  // global bits enumerated by the tile id
   uint32_t ntiles;
   uint32_t pad;
+  uint64_t roff[16];  // element offset of register r at the load/store arrangement
 };
 
 struct SweepProg {
@@ -67,6 +68,22 @@ struct SweepProg {
   uint8_t mixB_grad;
 };
 
+// Per-sweep scale record.  Mixer gates are applied as (I - i k X) per qubit, with
+// |k| <= 1; the dropped scalar factor phi per qubit (cos b, or +-i sin b together with
+// a bit flip X) accumulates into a uniform complex scale sigma = stored / true.  The
+// device tracks sigma along the sweep sequence and cancels it in the phase tables
+// (rho = 1/sigma), the energy and the gradient sums (s = 1/|sigma|^2).
+struct SwScale {
+  double rho_pre[2];  // complex multiplier folded into the pre-position phase table
+  double rho_mid[2];
+  double s_pre, s_mid;  // 1/|sigma|^2 at the pre / mid position
+  double s_A, s_B;      // 1/|sigma|^2 at the start of mixer A / B
+  double kA, wA, kB, wB;  // butterfly coefficient, per-qubit |phi|^2 of mixer A / B
+  uint32_t flipA, flipB;  // tile bits flipped by mixer A / B (X part of the gate)
+  double lam_fix[2];      // multiplier for lambda when loaded (equalises the scales of psi and lambda)
+  uint32_t fix_lam, pad;  // nonzero when lam_fix != 1
+};
+
 // graph block in device memory (uniform, read with scalar loads)
 struct GraphDev {
   int32_t n, m, T, cmax;   // cmax = |E| = last phase-table index
@@ -80,7 +97,7 @@ struct UnitDesc {
   int32_t n, p, nsweep, nsets;
   int64_t graph_off;   // byte offset of GraphDev in the workspace
   int64_t terms_off;   // byte offset of int4 terms (i, j, w, 0)
-  int64_t tab_off;     // byte offset of this unit's phase tables [p][cmax+1] + mixer (cos,sin)[p]
+  int64_t tab_off;     // byte offset of this unit's phase tables [p][cmax+1], then SwScale[nsweep+1]
   int64_t state_off;   // byte offset of psi (lambda follows), -1 when n <= L
   int32_t prog_off;    // index of the first SweepProg
   int32_t row;         // row in d_params / d_out

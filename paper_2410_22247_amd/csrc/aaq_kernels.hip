@@ -55,9 +55,13 @@ template <class R> __device__ __forceinline__ typename Cx<R>::V mkv(R x, R y) {
 template <int B0, int RB> __device__ __forceinline__ uint32_t tidx(uint32_t t, uint32_t r) {
   return (t & ((1u << B0) - 1u)) | (r << B0) | ((t >> B0) << (B0 + RB));
 }
-// LDS slot of tile index j (xor swizzle of the low RB bits by the next RB bits)
-template <int RB> __device__ __forceinline__ uint32_t swz(uint32_t j) {
-  return j ^ ((j >> RB) & ((1u << RB) - 1u));
+// LDS slot of tile index j: one padding slot per 16 entries.  P is additive over
+// disjoint bit sets, P(a | b) = P(a) + P(b), so the slot of (thread part | register
+// part) is a per-thread base plus a compile-time offset.
+__host__ __device__ constexpr uint32_t lds_slot(uint32_t j) { return j + (j >> 4); }
+// thread part of the tile index in an arrangement whose register bits start at B0
+template <int B0, int RB> __device__ __forceinline__ uint32_t tpart(uint32_t t) {
+  return (t & ((1u << B0) - 1u)) | ((t >> B0) << (B0 + RB));
 }
 
 // e^{-i theta X} on an amplitude pair with c = cos(theta), s = sin(theta):
@@ -68,6 +72,14 @@ template <class V, class R> __device__ __forceinline__ void bfly(V& x, V& y, R c
   x.y = c * x0.y - s * y0.x;
   y.x = c * y0.x + s * x0.y;
   y.y = c * y0.y - s * x0.x;
+}
+// (I - i k X) on a pair: (x, y) -> (x - i k y, y - i k x)
+template <class V, class R> __device__ __forceinline__ void bflyk(V& x, V& y, R k) {
+  const V x0 = x, y0 = y;
+  x.x = x0.x + k * y0.y;
+  x.y = x0.y - k * y0.x;
+  y.x = y0.x + k * x0.y;
+  y.y = y0.y - k * x0.x;
 }
 // Im(conj(u) v)
 template <class V> __device__ __forceinline__ auto imcm(const V& u, const V& v) { return u.x * v.y - u.y * v.x; }
@@ -95,7 +107,6 @@ template <class R> struct Ctx {
   const GraphDev* g;
   const int4* terms;
   const V* tab;    // [p][cmax+1]
-  const V* mixcs;  // [p] (cos beta, sin beta)
   V* psi;          // global state (nullptr when the tile never leaves registers)
   V* lam;
   R amp;           // 2^{-n/2}
@@ -109,7 +120,8 @@ struct Acc {
   __device__ void zero() { e = nrm = gpre = gmid = ba = bb = 0.0; }
 };
 
-template <class R, int NS> struct Tile {
+// EN: the energy / lambda step is compiled in (only the last forward sweep needs it)
+template <class R, int NS, bool EN = true> struct Tile {
   using G = Geo<R>;
   using V = typename G::V;
   static constexpr int NR = G::NR, RB = G::RB, L = G::L, LB = G::LB, NA = G::NA, LAST = G::LAST, P = G::P;
@@ -118,42 +130,55 @@ template <class R, int NS> struct Tile {
   bool lam_live;
 
   // -------------------------------------------------------------- LDS transpose
-  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
+  // flip: tile-index bits inverted on the way through (the X part of a mixer gate).
+  // Bits that are thread bits of KF are flipped on the write side, the others (register
+  // bits of KF, thread bits of KT) on the read side; both stay per-thread constants.
+  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds, uint32_t flip) {
+    constexpr int BF = G::b0(KF), BT = G::b0(KT);
+    constexpr uint32_t regF = ((1u << RB) - 1u) << BF;
     const uint32_t t = threadIdx.x;
+    V* wb = lds + lds_slot(tpart<BF, RB>(t) ^ (flip & ~regF));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) lds[swz<RB>(tidx<G::b0(KF), RB>(t, r))] = x[r];
+    for (int r = 0; r < NR; ++r) wb[lds_slot((uint32_t)r << BF)] = x[r];
     __syncthreads();
+    const V* rb = lds + lds_slot(tpart<BT, RB>(t) ^ (flip & regF));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) x[r] = lds[swz<RB>(tidx<G::b0(KT), RB>(t, r))];
+    for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
     __syncthreads();
   }
-  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds) {
-    xchg1<KF, KT>(a[0], lds);
-    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
+  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds, uint32_t flip = 0) {
+    // a nonzero flip needs disjoint register sets of KF and KT (true for the first
+    // exchange of every mixer: 3->0 and 2->1)
+    xchg1<KF, KT>(a[0], lds, flip);
+    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds, flip);
   }
 
   // -------------------------------------------------------------- mixer butterflies
-  // butterflies on every tile bit of `todo` held in registers by arrangement K
-  template <int K> __device__ __forceinline__ void mix_at(uint32_t& todo, R c, R s, bool grad, double& gacc) {
+  // (I - i k X_q) on every tile bit of `todo` held in registers by arrangement K:
+  // (x, y) -> (x - i k y, y - i k x), two FMAs per amplitude.  With `grad`, the pair's
+  // Im <lam|X_q|psi> is accumulated with weight wcur, which tracks the scale change of
+  // the preceding gates of the same mixer (wcur *= w after every qubit).
+  template <int K> __device__ __forceinline__ void mix_at(uint32_t& todo, R k, R w, R& wcur, bool grad, R& gsum) {
     constexpr int B0 = G::b0(K);
-    R gsum = R(0);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       if ((todo >> (B0 + b)) & 1u) {
+        R gq = R(0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r & (1 << b)) continue;
           const int r1 = r | (1 << b);
           if (NS == 2) {
-            if (grad) gsum += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
-            if (lam_live) bfly(a[NS - 1][r], a[NS - 1][r1], c, s);
+            if (grad) gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
+            if (lam_live) bflyk(a[NS - 1][r], a[NS - 1][r1], k);
           }
-          bfly(a[0][r], a[0][r1], c, s);
+          bflyk(a[0][r], a[0][r1], k);
         }
+        if (NS == 2 && grad) gsum += wcur * gq;
+        wcur *= w;
       }
     }
     todo &= ~(((1u << RB) - 1u) << B0);
-    gacc += (double)gsum;
   }
 
   // -------------------------------------------------------------- z of register 0
@@ -259,7 +284,7 @@ template <class R, int NS> struct Tile {
                                          const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
     if (!ops) return;
     const uint64_t zb = zbase<K>(S, tile_base);
-    if (ops & OP_ENERGY) {
+    if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
       hvals<K>(S, zb, cx.terms, cx.T, hv);
       double e = 0.0, nr = 0.0;
@@ -291,11 +316,10 @@ template <class R, int NS> struct Tile {
         gacc += (double)gs;
       }
       if (ops & (OP_PHASE | OP_UNPHASE)) {
-        const R sg = (ops & OP_UNPHASE) ? R(-1) : R(1);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const V tv = ltab[cv[r]];
-          const R tc = tv.x, ts = sg * tv.y;  // exp(-i g c) = (tc, ts); inverse conjugates
+          const V tv = ltab[cv[r]];  // exp(-+i gamma C) times the scale correction
+          const R tc = tv.x, ts = tv.y;
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             if (s == 0 || lam_live) {
@@ -345,13 +369,7 @@ template <class R, int NS> struct Tile {
       if (S.pos[i] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[i];
     return toff;
   }
-  template <int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) {
-    uint64_t o = 0;
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-      if (((r >> b) & 1) && S.pos[LB + b] != kDummy) o |= (uint64_t)1 << S.pos[LB + b];
-    return o;
-  }
+  template <int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) { return S.roff[r]; }
   template <int r> __device__ __forceinline__ void load_r(int s, const V* p, const SetSpec& S) {
     if (S.dummy && (tidx<G::b0(LAST), RB>(threadIdx.x, r) & S.dummy))
       a[s][r] = mkv<R>(R(0), R(0));
@@ -392,8 +410,9 @@ template <class R, int NS> struct Tile {
   // Executes program `pg` on the tile with id `tile` of set S.  With `io` false the
   // state stays in registers (whole state in one tile); stores still happen when the
   // program asks for them and a destination exists.
-  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, uint64_t tile, const Ctx<R>& cx, bool io, V* lds_x,
-                      const V* ltab_pre, const V* ltab_mid, Acc& acc, double* zz_lds) {
+  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+                                      const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
+                                      double* zz_lds) {
     const uint64_t tile_base = pdep64(tile, S.fixmask);
     if (pg.flags & F_INIT) {
       init_plus(S, cx.amp);
@@ -401,25 +420,36 @@ template <class R, int NS> struct Tile {
     } else if (io) {
       if (pg.flags & F_LOAD_PSI) load(0, cx.psi, S, tile_base);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
-      if (NS == 2 && (pg.flags & F_LOAD_LAM)) load(NS - 1, cx.lam, S, tile_base);
+      if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
+        load(NS - 1, cx.lam, S, tile_base);
+        if (sc.fix_lam) {
+          const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const V x = a[NS - 1][r];
+            a[NS - 1][r] = mkv<R>(x.x * fr - x.y * fi, x.x * fi + x.y * fr);
+          }
+        }
+      }
     }
     const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
     // position "pre" at the load arrangement
     ops_at<LAST>(pg.pre_ops, make_lam, S, tile_base, cx, ltab_pre, acc.gpre, acc, zz_lds);
     int at = LAST;
     if (pg.mixA_dir) {
-      const typename G::V cs = cx.mixcs[pg.mixA_layer];
-      const R c = cs.x, s = (pg.mixA_dir > 0) ? cs.y : -cs.y;
+      const R k = (R)sc.kA, w = (R)sc.wA;
+      R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
       const bool gr = pg.mixA_grad != 0;
       static_assert(NA == 4, "arrangement sequence written for four arrangements");
-      mix_at<3>(todo, c, s, gr, acc.ba);
-      xchg<3, 0>(lds_x);
-      mix_at<0>(todo, c, s, gr, acc.ba);
+      mix_at<3>(todo, k, w, wcur, gr, gs);
+      xchg<3, 0>(lds_x, sc.flipA);
+      mix_at<0>(todo, k, w, wcur, gr, gs);
       xchg<0, 1>(lds_x);
-      mix_at<1>(todo, c, s, gr, acc.ba);
+      mix_at<1>(todo, k, w, wcur, gr, gs);
       xchg<1, 2>(lds_x);
-      mix_at<2>(todo, c, s, gr, acc.ba);
+      mix_at<2>(todo, k, w, wcur, gr, gs);
+      acc.ba += (double)gs;
       at = P;
     }
     const bool need_mid = pg.mid_ops || pg.mixB_dir;
@@ -429,17 +459,18 @@ template <class R, int NS> struct Tile {
     }
     ops_at<P>(pg.mid_ops, make_lam, S, tile_base, cx, ltab_mid, acc.gmid, acc, zz_lds);
     if (pg.mixB_dir) {
-      const typename G::V cs = cx.mixcs[pg.mixB_layer];
-      const R c = cs.x, s = (pg.mixB_dir > 0) ? cs.y : -cs.y;
+      const R k = (R)sc.kB, w = (R)sc.wB;
+      R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
       const bool gr = pg.mixB_grad != 0;
-      mix_at<2>(todo, c, s, gr, acc.bb);
-      xchg<2, 1>(lds_x);
-      mix_at<1>(todo, c, s, gr, acc.bb);
+      mix_at<2>(todo, k, w, wcur, gr, gs);
+      xchg<2, 1>(lds_x, sc.flipB);
+      mix_at<1>(todo, k, w, wcur, gr, gs);
       xchg<1, 0>(lds_x);
-      mix_at<0>(todo, c, s, gr, acc.bb);
+      mix_at<0>(todo, k, w, wcur, gr, gs);
       xchg<0, 3>(lds_x);
-      mix_at<3>(todo, c, s, gr, acc.bb);
+      mix_at<3>(todo, k, w, wcur, gr, gs);
+      acc.bb += (double)gs;
       at = LAST;
     }
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
@@ -475,11 +506,130 @@ template <int N> __device__ __forceinline__ void block_sum(double (&v)[N], doubl
   __syncthreads();
 }
 
-template <class R> __device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename Cx<R>::V* tab, int layer,
-                                                            int cmax) {
+// phase-table multipliers of one position into LDS: exp(-i gamma_l c) (conjugated for
+// the inverse gate) times the complex scale correction rho
+template <class R>
+__device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename Cx<R>::V* tab, int layer, int cmax,
+                                         bool conj, const double* rho) {
   if (layer < 0) return;
   const typename Cx<R>::V* src = tab + (size_t)layer * (cmax + 1);
-  for (int c = threadIdx.x; c <= cmax; c += kThreads) ltab[c] = src[c];
+  const double rr = rho[0], ri = rho[1];
+  for (int c = threadIdx.x; c <= cmax; c += kThreads) {
+    const double tr = (double)src[c].x, ti = conj ? -(double)src[c].y : (double)src[c].y;
+    ltab[c] = mkv<R>((R)(tr * rr - ti * ri), (R)(tr * ri + ti * rr));
+  }
+}
+
+// apply a sweep's scale corrections to the per-thread sums
+__device__ __forceinline__ void scale_acc(Acc& acc, const SweepProg& pg, const SwScale& sc) {
+  const double se = (pg.pre_ops & OP_ENERGY) ? sc.s_pre : sc.s_mid;
+  acc.e *= se;
+  acc.nrm *= se;
+  acc.gpre *= sc.s_pre;
+  acc.gmid *= sc.s_mid;
+  acc.ba *= sc.s_A;
+  acc.bb *= sc.s_B;
+}
+
+// Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
+// the scale corrections (see SwScale).  out[nsweep].s_pre is 1/|sigma|^2 at the end.
+__device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* sets, const double* beta, SwScale* out) {
+  double sr = 1.0, si = 0.0;  // sigma
+  auto position = [&](uint8_t ops, double* rho, double& sx) {
+    const double a2 = sr * sr + si * si;
+    sx = 1.0 / a2;
+    rho[0] = 1.0;
+    rho[1] = 0.0;
+    if (ops & (OP_PHASE | OP_UNPHASE)) {
+      rho[0] = sr / a2;
+      rho[1] = -si / a2;
+      sr = 1.0;
+      si = 0.0;
+    }
+  };
+  auto mixer = [&](int layer, int dir, uint32_t act, double& k, double& w, uint32_t& flip, double& sx) {
+    k = 0.0;
+    w = 1.0;
+    flip = 0;
+    sx = 1.0 / (sr * sr + si * si);
+    if (!dir) return;
+    double sn, cs;
+    sincos(beta[layer], &sn, &cs);
+    double pr, pi;  // phi
+    if (fabs(cs) >= fabs(sn)) {
+      k = dir * sn / cs;
+      pr = cs;
+      pi = 0.0;
+    } else {
+      k = -dir * cs / sn;
+      pr = 0.0;
+      pi = -dir * sn;
+      flip = act;
+    }
+    w = pr * pr + pi * pi;
+    // sigma /= phi^m
+    double qr = 1.0, qi = 0.0;
+    for (int i = __popc(act); i > 0; --i) {
+      const double tr = qr * pr - qi * pi;
+      qi = qr * pi + qi * pr;
+      qr = tr;
+    }
+    const double q2 = qr * qr + qi * qi;
+    const double nr = (sr * qr + si * qi) / q2, ni = (si * qr - sr * qi) / q2;
+    sr = nr;
+    si = ni;
+  };
+  // scales of the buffers in memory: psi and lambda differ after a sweep that stores
+  // only lambda (the last forward sweep leaves psi untouched in memory)
+  double mpr = 1.0, mpi = 0.0, mlr = 1.0, mli = 0.0;
+  for (int i = 0; i < nsweep; ++i) {
+    const SweepProg pg = progs[i];
+    SwScale r;
+    r.lam_fix[0] = 1.0;
+    r.lam_fix[1] = 0.0;
+    r.fix_lam = 0;
+    r.pad = 0;
+    if (pg.flags & F_INIT) {
+      sr = 1.0;
+      si = 0.0;
+    } else if (pg.flags & F_LOAD_PSI) {
+      sr = mpr;
+      si = mpi;
+    }
+    if (pg.flags & F_LOAD_LAM) {  // lambda <- lambda * sigma_psi / sigma_lam
+      const double d = mlr * mlr + mli * mli;
+      const double fr = (sr * mlr + si * mli) / d, fi = (si * mlr - sr * mli) / d;
+      r.lam_fix[0] = fr;
+      r.lam_fix[1] = fi;
+      r.fix_lam = (fr != 1.0 || fi != 0.0) ? 1u : 0u;
+    }
+    const uint32_t act = sets[pg.set].act;
+    position(pg.pre_ops, r.rho_pre, r.s_pre);
+    mixer(pg.mixA_layer, pg.mixA_dir, act, r.kA, r.wA, r.flipA, r.s_A);
+    position(pg.mid_ops, r.rho_mid, r.s_mid);
+    mixer(pg.mixB_layer, pg.mixB_dir, act, r.kB, r.wB, r.flipB, r.s_B);
+    if (pg.flags & F_STORE_PSI) {
+      mpr = sr;
+      mpi = si;
+    }
+    if (pg.flags & F_STORE_LAM) {
+      mlr = sr;
+      mli = si;
+    }
+    out[i] = r;
+  }
+  SwScale f;
+  position(0, f.rho_pre, f.s_pre);
+  f.rho_mid[0] = 1.0;
+  f.rho_mid[1] = 0.0;
+  f.s_mid = f.s_A = f.s_B = 1.0;
+  f.kA = f.kB = 0.0;
+  f.wA = f.wB = 1.0;
+  f.flipA = f.flipB = 0;
+  f.lam_fix[0] = 1.0;
+  f.lam_fix[1] = 0.0;
+  f.fix_lam = f.pad = 0;
+  out[nsweep] = f;
 }
 
 // ---------------------------------------------------------------------------------
@@ -490,8 +640,8 @@ template <class R> struct SweepArgs {
   const GraphDev* g;
   const int4* terms;
   const typename Cx<R>::V* tab;
-  const typename Cx<R>::V* mixcs;
-  double* partial;  // [nslot][ntiles]
+  const SwScale* scale;  // this sweep's scale record
+  double* partial;       // [nslot][ntiles]
   int nslot;
   int T;
   int cmax;
@@ -500,31 +650,32 @@ template <class R> struct SweepArgs {
   SweepProg prog;
 };
 
-// two 512-thread workgroups per CU: <= 128 VGPRs, LDS tile 64 KB (complex64)
-#define AAQ_TILE_BOUNDS __launch_bounds__(kThreads, 2)
+#define AAQ_TILE_BOUNDS __launch_bounds__(kThreads)
 
-template <class R, int NS, bool PT> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
+template <class R, int NS, bool PT, bool EN> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
   using G = Geo<R>;
   using V = typename G::V;
-  __shared__ V lds_x[G::TILE];
+  __shared__ V lds_x[lds_slot(G::TILE)];
   __shared__ double red[(kThreads / 64) * 6];
   __shared__ double zz[PT ? kMaxT : 1];
   extern __shared__ unsigned char dyn_lds[];  // two phase tables of cmax+1 entries
   V* ltab0 = reinterpret_cast<V*>(dyn_lds);
   V* ltab1 = ltab0 + (A.cmax + 1);
   const uint32_t tile = blockIdx.x;
-  const uint8_t pre_ph = A.prog.pre_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG);
-  const uint8_t mid_ph = A.prog.mid_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG);
-  if (pre_ph) load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax);
-  if (mid_ph) load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax);
+  const SwScale& sc = *A.scale;
+  if (A.prog.pre_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax, (A.prog.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+  if (A.prog.mid_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax, (A.prog.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += kThreads) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.mixcs, A.psi, A.lam, A.amp, A.T, A.cmax};
-  Tile<R, NS> tl;
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax};
+  Tile<R, NS, EN> tl;
   Acc acc;
   acc.zero();
-  tl.run(A.prog, A.set, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  tl.run(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  scale_acc(acc, A.prog, sc);
   double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
   block_sum<6>(v, red);
   const uint32_t nt = A.set.ntiles;
@@ -534,7 +685,8 @@ template <class R, int NS, bool PT> __global__ AAQ_TILE_BOUNDS void k_sweep(Swee
   }
   if (PT) {
     __syncthreads();
-    for (int t = threadIdx.x; t < A.T; t += kThreads) A.partial[(size_t)(SLOT_TERMS + t) * nt + tile] = zz[t];
+    const double se = (A.prog.pre_ops & OP_ENERGY) ? sc.s_pre : sc.s_mid;
+    for (int t = threadIdx.x; t < A.T; t += kThreads) A.partial[(size_t)(SLOT_TERMS + t) * nt + tile] = se * zz[t];
   }
 }
 
@@ -556,10 +708,15 @@ template <class R> struct UnitArgs {
   typename Cx<R>::V* psi_io;  // optional external state for single-unit calls (n <= L): final psi store
 };
 
+template <class R> __device__ __forceinline__ const SwScale* unit_scales(const unsigned char* ws, const UnitDesc* D) {
+  const size_t amp = sizeof(typename Cx<R>::V);
+  return reinterpret_cast<const SwScale*>(ws + D->tab_off + amp * (size_t)D->p * (D->cmax + 1));
+}
+
 template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A) {
   using G = Geo<R>;
   using V = typename G::V;
-  __shared__ V lds_x[G::TILE];
+  __shared__ V lds_x[lds_slot(G::TILE)];
   __shared__ double red[(kThreads / 64) * 6];
   __shared__ double outacc[2 + 2 * kMaxP];
   __shared__ int s_idx;
@@ -578,25 +735,29 @@ template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A
     const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
     const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
     const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
-    const V* mixcs = tab + (size_t)p * (D->cmax + 1);
+    const SwScale* scales = unit_scales<R>(A.ws, D);
     const bool big = D->state_off >= 0;
     V* psi = big ? reinterpret_cast<V*>(A.ws + D->state_off) : A.psi_io;
     V* lam = big ? psi + ((size_t)1 << D->n) : nullptr;
-    Ctx<R> cx{g, terms, tab, mixcs, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+    Ctx<R> cx{g, terms, tab, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
     Tile<R, NS> tl;
     tl.lam_live = false;
     const int ns = D->nsweep;
     for (int si = 0; si < ns; ++si) {
       const SweepProg pg = A.progs[D->prog_off + si];
       const SetSpec& S = D->sets[pg.set];
+      const SwScale& sc = scales[si];
       __syncthreads();  // previous sweep's table readers are done
-      if (pg.pre_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG)) load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax);
-      if (pg.mid_ops & (OP_PHASE | OP_UNPHASE | OP_GRADG)) load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax);
+      if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+        load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+      if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+        load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
       __syncthreads();
       Acc acc;
       acc.zero();
       const uint32_t nt = big ? S.ntiles : 1u;
-      for (uint32_t t = 0; t < nt; ++t) tl.run(pg, S, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
+      for (uint32_t t = 0; t < nt; ++t) tl.run(pg, S, sc, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
+      scale_acc(acc, pg, sc);
       double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
       block_sum<6>(v, red);
       if (threadIdx.x == 0) {
@@ -620,11 +781,12 @@ template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A
 }
 
 // ---------------------------------------------------------------------------------
-// Phase tables exp(-i gamma_l c), c = 0..cmax, and mixer (cos beta_l, sin beta_l).
-// gamma_l * c is formed and reduced in FP64; the result is rounded to R.
+// Phase tables exp(-i gamma_l c), c = 0..cmax (gamma_l * c formed and reduced in FP64,
+// rounded to R), then the sweep scale records.
 template <class R>
 __global__ void k_tables(const double* __restrict__ gamma, const double* __restrict__ beta, int p, int cmax,
-                         typename Cx<R>::V* __restrict__ tab, typename Cx<R>::V* __restrict__ mixcs) {
+                         typename Cx<R>::V* __restrict__ tab, const SweepProg* progs, int nsweep, const SetSpec* sets,
+                         SwScale* scales) {
   const int tot = p * (cmax + 1);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
     const int l = i / (cmax + 1), c = i % (cmax + 1);
@@ -632,12 +794,7 @@ __global__ void k_tables(const double* __restrict__ gamma, const double* __restr
     sincos(gamma[l] * (double)c, &sn, &cs);
     tab[i] = mkv<R>((R)cs, (R)(-sn));
   }
-  if (blockIdx.x == 0)
-    for (int l = threadIdx.x; l < p; l += blockDim.x) {
-      double sn, cs;
-      sincos(beta[l], &sn, &cs);
-      mixcs[l] = mkv<R>((R)cs, (R)sn);
-    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) build_scales(progs, nsweep, sets, beta, scales);
 }
 
 // per-unit tables for a plan; block b handles unit b; also resets the work counter
@@ -654,12 +811,8 @@ template <class R> __global__ void k_plan_tables(UnitArgs<R> A, int p, int pstri
     sincos(prm[l] * (double)c, &sn, &cs);
     tab[i] = mkv<R>((R)cs, (R)(-sn));
   }
-  V* mixcs = tab + (size_t)p * (cm + 1);
-  for (int l = threadIdx.x; l < p; l += blockDim.x) {
-    double sn, cs;
-    sincos(prm[p + l], &sn, &cs);
-    mixcs[l] = mkv<R>((R)cs, (R)sn);
-  }
+  if (threadIdx.x == 0)
+    build_scales(A.progs + D->prog_off, D->nsweep, D->sets, prm + p, const_cast<SwScale*>(unit_scales<R>(A.ws, D)));
 }
 
 // fixed-order sums of per-tile partials: out[o] = scale_o * sum_{sources of o} sum_tiles
@@ -694,7 +847,7 @@ __global__ void k_reduce(const double* __restrict__ partial, const RedSrc* __res
 // one <Z_i Z_j> pass over the final state (per-term estimator structure)
 template <class R>
 __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __restrict__ psi, uint64_t N, int i, int j,
-                                                 double* __restrict__ partial) {
+                                                 const double* __restrict__ scale, double* __restrict__ partial) {
   __shared__ double red[4];
   double acc = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -706,7 +859,7 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) partial[blockIdx.x] = *scale * (red[0] + red[1] + red[2] + red[3]);
 }
 
 // exact integer diagonal values through the same per-amplitude code as the kernels,
@@ -751,7 +904,7 @@ template <class R> static hipError_t sweep_launch(const LaunchSweep& L, hipStrea
   A.g = L.g;
   A.terms = L.terms;
   A.tab = reinterpret_cast<const typename Cx<R>::V*>(L.tab);
-  A.mixcs = reinterpret_cast<const typename Cx<R>::V*>(L.mixcs);
+  A.scale = L.scale;
   A.partial = L.partial;
   A.nslot = L.nslot;
   A.T = L.T;
@@ -761,12 +914,18 @@ template <class R> static hipError_t sweep_launch(const LaunchSweep& L, hipStrea
   A.prog = L.prog;
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);
   const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
+  const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
+  const dim3 grid(L.set.ntiles), blk(kThreads);
   if (pt)
-    hipLaunchKernelGGL((k_sweep<R, 1, true>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 1, true, true>), grid, blk, dyn, st, A);
+  else if (L.two_states && en)
+    hipLaunchKernelGGL((k_sweep<R, 2, false, true>), grid, blk, dyn, st, A);
   else if (L.two_states)
-    hipLaunchKernelGGL((k_sweep<R, 2, false>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 2, false, false>), grid, blk, dyn, st, A);
+  else if (en)
+    hipLaunchKernelGGL((k_sweep<R, 1, false, true>), grid, blk, dyn, st, A);
   else
-    hipLaunchKernelGGL((k_sweep<R, 1, false>), dim3(L.set.ntiles), dim3(kThreads), dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 1, false, false>), grid, blk, dyn, st, A);
   return hipGetLastError();
 }
 
@@ -774,16 +933,16 @@ hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st) {
   return dbl ? sweep_launch<double>(L, st) : sweep_launch<float>(L, st);
 }
 
-hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, void* mixcs, bool dbl,
-                         hipStream_t st) {
+hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
+                         int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st) {
   const int tot = p * (cmax + 1);
   const int blocks = (tot + 255) / 256;
   if (dbl)
     hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
-                       reinterpret_cast<double2*>(tab), reinterpret_cast<double2*>(mixcs));
+                       reinterpret_cast<double2*>(tab), progs, nsweep, sets, scales);
   else
     hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
-                       reinterpret_cast<float2*>(tab), reinterpret_cast<float2*>(mixcs));
+                       reinterpret_cast<float2*>(tab), progs, nsweep, sets, scales);
   return hipGetLastError();
 }
 
@@ -836,11 +995,14 @@ hipError_t launch_reduce(const double* partial, const void* src, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, double* partial, int blocks, bool dbl, hipStream_t st) {
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, double* partial, int blocks,
+                          bool dbl, hipStream_t st) {
   if (dbl)
-    hipLaunchKernelGGL(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j, partial);
+    hipLaunchKernelGGL(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j,
+                       scale, partial);
   else
-    hipLaunchKernelGGL(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j, partial);
+    hipLaunchKernelGGL(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j,
+                       scale, partial);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ struct LaunchSweep {
   const GraphDev* g;
   const int4* terms;
   const void* tab;
-  const void* mixcs;
+  const SwScale* scale;
   double* partial;
   int nslot, T, cmax;
   double amp;
@@ -36,14 +36,14 @@ struct LaunchUnits {
 };
 
 hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st);
-hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, void* mixcs, bool dbl,
-                         hipStream_t st);
+hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
+                         int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
 hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, hipStream_t st);
 hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
                          hipStream_t st);
-hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, double* partial, int blocks, bool dbl,
-                          hipStream_t st);
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, double* partial, int blocks,
+                          bool dbl, hipStream_t st);
 hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
                        int32_t* out, bool dbl, hipStream_t st);
 int tile_bits(bool dbl);
