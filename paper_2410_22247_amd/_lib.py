@@ -77,6 +77,7 @@ def lib():
         "aaq_last_error_message": (ctypes.c_char_p, []),
         "aaq_version": (ctypes.c_char_p, []),
         "aaq_timing_enable": (i, [i]),
+
         "aaq_timing_read": (i, [ctypes.POINTER(CKernelTiming), i, ctypes.POINTER(i), i]),
     }
     for name, (res, args) in sig.items():

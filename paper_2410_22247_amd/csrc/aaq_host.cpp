@@ -76,6 +76,17 @@ struct TimedLaunch {
   }
 };
 
+// ------------------------------------------------------------------ launch tuning
+int device_cus() {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    cached = cu > 0 ? cu : 256;
+  }
+  return cached;
+}
+
 // ------------------------------------------------------------------ validation
 aaq_status validate_problem(const aaq_problem* pr) {
   if (!pr) return fail(AAQ_ERR_INVALID_ARG, "problem is NULL");
@@ -170,16 +181,28 @@ std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
 // tile with the lowest remaining global bits, so that every tile holds global bits
 // 0..4 (>= 256 contiguous bytes per access).  k is the smallest possible, sizes as
 // even as the caps allow.
-// element offsets of the register slots at the load/store arrangement (register bits
-// are the top RB = L - 9 tile bits)
-void fill_roff(SetSpec& s, int L) {
-  const int RB = L - 9;
+// Register layouts ("arrangements"), L = 13 and 4 register bits per thread:
+// arrangement k keeps tile bits [b0(k), b0(k)+4) in registers, b0 = 0, 4, 8, 9.
+constexpr int kNA = 4, kRB = 4, kP = 2;
+uint32_t arr_regs(int k) { return 0xFu << (k == 3 ? 9 : 4 * k); }
+
+// Load arrangement, mixer route, active-qubit mask and register offsets of a set.
+// Every set loads and stores with the top tile bits in registers (arrangement 3, the
+// element offsets of its registers are tabulated).  Set 0 mixes along 3 -> 0 -> 1 -> 2;
+// the later sets hold only tile bits >= 5 active and skip arrangement 0: 3 -> 1 -> 2.
+void finish_set(SetSpec& s, int n, bool first) {
+  s.kl = 3;
+  s.route = first ? ROUTE_3012 : ROUTE_312;
+  s.gact = 0;
+  for (int j = 0; j < 16; ++j)
+    if (((s.act >> j) & 1u) && s.pos[j] != kDummy) s.gact |= 1ull << s.pos[j];
   for (int r = 0; r < 16; ++r) {
     uint64_t o = 0;
-    for (int b = 0; b < RB; ++b)
+    for (int b = 0; b < kRB; ++b)
       if (((r >> b) & 1) && s.pos[9 + b] != kDummy) o |= 1ull << s.pos[9 + b];
-    s.roff[r] = (r < (1 << RB)) ? o : 0;
+    s.roff[r] = o;
   }
+  (void)n;
 }
 
 std::vector<SetSpec> make_sets(int n, int L) {
@@ -192,7 +215,7 @@ std::vector<SetSpec> make_sets(int n, int L) {
     s.dummy = ((1u << L) - 1u) & ~s.act;
     s.fixmask = 0;
     s.ntiles = 1;
-    fill_roff(s, L);
+    finish_set(s, n, true);
     sets.push_back(s);
     return sets;
   }
@@ -240,7 +263,7 @@ std::vector<SetSpec> make_sets(int n, int L) {
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     S.fixmask = all & ~tilemask;
     S.ntiles = 1u << (n - L);
-    fill_roff(S, L);
+    finish_set(S, n, s == 0);
     sets.push_back(S);
   }
   return sets;
@@ -415,11 +438,14 @@ struct Single {
   std::vector<SweepProg> progs;
   std::vector<RedSrcHost> src;
   std::vector<int32_t> srcb;
+  std::vector<int> grids;
   Layout lay;
 };
 
+// grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
+// sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
 aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
-                       aaq_precision prec, Single& S) {
+                       aaq_precision prec, Single& S, bool with_grids = false) {
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
     return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
@@ -447,9 +473,11 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   // reduction sources
   std::vector<std::vector<RedSrcHost>> per(L.nout);
   auto part_off = [&](int sw, int slot) { return (int64_t)(sw * L.nslot + slot) * L.ntiles; };
+  S.grids.assign(L.nsweep, L.ntiles);
   for (int sw = 0; sw < L.nsweep; ++sw) {
     const SweepProg& s = S.progs[sw];
-    auto add = [&](int o, int slot, double scale) { per[o].push_back({part_off(sw, slot), L.ntiles, o, scale}); };
+    const int np = S.grids[sw];
+    auto add = [&](int o, int slot, double scale) { per[o].push_back({part_off(sw, slot), np, o, scale}); };
     if ((s.pre_ops | s.mid_ops) & OP_ENERGY) {
       add(0, SLOT_E, 1.0);
       add(1, SLOT_NORM, 1.0);
@@ -510,7 +538,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   if ((st = validate_p(p))) return st;
   if ((st = validate_params(p, gamma, beta))) return st;
   Single S;
-  if ((st = plan_single(pr, p, grad, obs, agg, prec, S))) return st;
+  if ((st = plan_single(pr, p, grad, obs, agg, prec, S, true))) return st;
   const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
   if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
   if (state_bytes < need_state) return fail(AAQ_ERR_BUFFER, "state buffer smaller than 2^n amplitudes");
@@ -572,7 +600,8 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     for (int t = 0; t < S.T; ++t) {
       TimedLaunch tl(KC_ZZPASS, (double)need_state, hs);
       HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y,
-                            &((const SwScale*)(ws + L.scales) + L.nsweep)->s_pre, zp + (size_t)t * kZZBlocks, kZZBlocks,
+                            &((const SwScale*)(ws + L.scales) + L.nsweep)->s_pre,
+                            &((const SwScale*)(ws + L.scales) + L.nsweep)->F_pre, zp + (size_t)t * kZZBlocks, kZZBlocks,
                             S.dbl, hs));
       tl.done();
     }
@@ -717,12 +746,6 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   if (o.sort_units)
     std::stable_sort(PL.order_v.begin(), PL.order_v.end(), [&](int a, int b) { return PL.ud[a].n > PL.ud[b].n; });
   return AAQ_OK;
-}
-
-int device_cus() {
-  int dev = 0, cu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
-  return cu;
 }
 
 aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipStream_t hs) {

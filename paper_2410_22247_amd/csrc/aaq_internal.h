@@ -20,6 +20,10 @@ constexpr int kMinContig = 5;       // low global bits every tile must contain
 constexpr int kSmallN = 14;         // n <= kSmallN: whole state in one tile (complex64)
 constexpr uint8_t kDummy = 0xFF;    // tile bit without a vertex (n < L)
 
+// mixer routes through the register arrangements (load arrangement 3 first, phase
+// arrangement 2 last)
+enum : uint8_t { ROUTE_3012 = 0, ROUTE_312 = 1 };
+
 // per-position operations inside a sweep
 enum : uint8_t {
   OP_PHASE = 1,    // multiply live states by exp(-i gamma_l C(z))
@@ -49,7 +53,10 @@ struct SetSpec {
   uint32_t dummy;    // tile-bit mask of dummy bits
   uint64_t fixmask;  // global bits enumerated by the tile id
   uint32_t ntiles;
-  uint32_t pad;
+  uint8_t kl;         // load/store arrangement (3: register bits = the top tile bits)
+  uint8_t route;      // mixer route: ROUTE_3012 or ROUTE_312 (arrangements visited)
+  uint8_t pad[6];
+  uint64_t gact;      // global bits of the active (mixed) qubits
   uint64_t roff[16];  // element offset of register r at the load/store arrangement
 };
 
@@ -70,16 +77,18 @@ struct SweepProg {
 
 // Per-sweep scale record.  Mixer gates are applied as (I - i k X) per qubit, with
 // |k| <= 1; the dropped scalar factor phi per qubit (cos b, or +-i sin b together with
-// a bit flip X) accumulates into a uniform complex scale sigma = stored / true.  The
-// device tracks sigma along the sweep sequence and cancels it in the phase tables
-// (rho = 1/sigma), the energy and the gradient sums (s = 1/|sigma|^2).
+// a bit flip X) accumulates into a uniform complex scale sigma = stored / true, and the
+// bit flips into a uniform global mask F (the buffers hold the amplitude of z ^ F at
+// index z; flips are never moved in memory).  The device tracks sigma and F along the
+// sweep sequence, cancels sigma in the phase tables (rho = 1/sigma), the energy and
+// the gradient sums (s = 1/|sigma|^2), and evaluates C and h at z ^ F.
 struct SwScale {
   double rho_pre[2];  // complex multiplier folded into the pre-position phase table
   double rho_mid[2];
   double s_pre, s_mid;  // 1/|sigma|^2 at the pre / mid position
   double s_A, s_B;      // 1/|sigma|^2 at the start of mixer A / B
   double kA, wA, kB, wB;  // butterfly coefficient, per-qubit |phi|^2 of mixer A / B
-  uint32_t flipA, flipB;  // tile bits flipped by mixer A / B (X part of the gate)
+  uint64_t F_pre, F_mid;  // flip mask at the pre / mid position: the buffers hold amplitude z ^ F at index z
   double lam_fix[2];      // multiplier for lambda when loaded (equalises the scales of psi and lambda)
   uint32_t fix_lam, pad;  // nonzero when lam_fix != 1
 };

@@ -130,27 +130,21 @@ template <class R, int NS, bool EN = true> struct Tile {
   bool lam_live;
 
   // -------------------------------------------------------------- LDS transpose
-  // flip: tile-index bits inverted on the way through (the X part of a mixer gate).
-  // Bits that are thread bits of KF are flipped on the write side, the others (register
-  // bits of KF, thread bits of KT) on the read side; both stay per-thread constants.
-  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds, uint32_t flip) {
+  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
     constexpr int BF = G::b0(KF), BT = G::b0(KT);
-    constexpr uint32_t regF = ((1u << RB) - 1u) << BF;
     const uint32_t t = threadIdx.x;
-    V* wb = lds + lds_slot(tpart<BF, RB>(t) ^ (flip & ~regF));
+    V* wb = lds + lds_slot(tpart<BF, RB>(t));
 #pragma unroll
     for (int r = 0; r < NR; ++r) wb[lds_slot((uint32_t)r << BF)] = x[r];
     __syncthreads();
-    const V* rb = lds + lds_slot(tpart<BT, RB>(t) ^ (flip & regF));
+    const V* rb = lds + lds_slot(tpart<BT, RB>(t));
 #pragma unroll
     for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
     __syncthreads();
   }
-  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds, uint32_t flip = 0) {
-    // a nonzero flip needs disjoint register sets of KF and KT (true for the first
-    // exchange of every mixer: 3->0 and 2->1)
-    xchg1<KF, KT>(a[0], lds, flip);
-    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds, flip);
+  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds) {
+    xchg1<KF, KT>(a[0], lds);
+    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
   }
 
   // -------------------------------------------------------------- mixer butterflies
@@ -182,7 +176,9 @@ template <class R, int NS, bool EN = true> struct Tile {
   }
 
   // -------------------------------------------------------------- z of register 0
-  template <int K> __device__ __forceinline__ uint64_t zbase(const SetSpec& S, uint64_t tile_base) const {
+  // index z of register 0 at arrangement K, XOR the flip mask F: the register-0
+  // amplitude is the one of basis state zbase ^ F (register bits set where F has them)
+  template <int K> __device__ __forceinline__ uint64_t zbase(const SetSpec& S, uint64_t tile_base, uint64_t F) const {
     constexpr int B0 = G::b0(K);
     const uint32_t t = threadIdx.x;
     uint64_t z = tile_base;
@@ -192,11 +188,13 @@ template <class R, int NS, bool EN = true> struct Tile {
       const uint32_t p = S.pos[tb];
       if (p != kDummy) z |= (uint64_t)((t >> i) & 1u) << p;
     }
-    return z;
+    return z ^ F;
   }
 
-  // C(z) for every register amplitude at arrangement K:
-  // C(zb ^ m) = C(zb) + sum_{b in m} d_b - 2 #{edges inside m}, d_b = deg v_b - 2 |N(v_b) & zb|
+  // C(z) for every register amplitude at arrangement K.  With base b = zb and m the
+  // register bits flipped relative to it: C(b ^ m) = C(b) + sum_{v in m} d_v
+  //   + sum_{edges (v, w) inside m} 2 (2 [b_v != b_w] - 1),
+  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.
   template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, const GraphDev* g, int (&cv)[NR]) const {
     constexpr int B0 = G::b0(K);
     const int n = g->n;
@@ -206,19 +204,24 @@ template <class R, int NS, bool EN = true> struct Tile {
       c0 += (int)((zb >> v) & 1u) * __popcll(av & ~zb);
     }
     int d[RB];
-    uint32_t rr[RB];
+    uint32_t rr[RB], df[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const uint32_t v = S.pos[B0 + b];
       d[b] = 0;
       rr[b] = 0;
+      df[b] = 0;
       if (v != kDummy) {
         const uint64_t av = g->adj[v];
-        d[b] = g->deg[v] - 2 * __popcll(av & zb);
+        const uint64_t bv = (zb >> v) & 1u;
+        d[b] = g->deg[v] - 2 * __popcll(av & (zb ^ (0ull - bv)));
 #pragma unroll
         for (int b2 = 0; b2 < RB; ++b2) {
           const uint32_t w = S.pos[B0 + b2];
-          if (w != kDummy && ((av >> w) & 1u)) rr[b] |= 1u << b2;
+          if (w != kDummy && ((av >> w) & 1u)) {
+            rr[b] |= 1u << b2;
+            if (((zb >> w) & 1u) != bv) df[b] |= 1u << b2;  // register bits of zb are uniform
+          }
         }
       }
     }
@@ -227,7 +230,8 @@ template <class R, int NS, bool EN = true> struct Tile {
     for (int r = 1; r < NR; ++r) {
       const int hb = 31 - __builtin_clz(r);
       const int rest = r ^ (1 << hb);
-      cv[r] = cv[rest] + d[hb] - 2 * __popc(rr[hb] & (uint32_t)rest);
+      const int npair = __popc(rr[hb] & (uint32_t)rest), ndiff = __popc(df[hb] & (uint32_t)rest);
+      cv[r] = cv[rest] + d[hb] + 2 * (2 * ndiff - npair);
     }
   }
 
@@ -250,21 +254,23 @@ template <class R, int NS, bool EN = true> struct Tile {
         if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
       }
       const int bi = (int)((zb >> tm.x) & 1u), bj = (int)((zb >> tm.y) & 1u);
-      h0 += tm.z * (bi ^ bj);
+      const int x = bi ^ bj;
+      h0 += tm.z * x;
+      // flipping one endpoint changes the term by w (1 - 2x); flipping both leaves it
       if (ri >= 0) {
 #pragma unroll
         for (int b = 0; b < RB; ++b)
-          if (ri == b) dh[b] += tm.z * (1 - 2 * bj);
+          if (ri == b) dh[b] += tm.z * (1 - 2 * x);
       }
       if (rj >= 0) {
 #pragma unroll
         for (int b = 0; b < RB; ++b)
-          if (rj == b) dh[b] += tm.z * (1 - 2 * bi);
+          if (rj == b) dh[b] += tm.z * (1 - 2 * x);
       }
       if (ri >= 0 && rj >= 0) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          if (((r >> ri) & 1) && ((r >> rj) & 1)) corr[r] -= 2 * tm.z;
+          if (((r >> ri) & 1) && ((r >> rj) & 1)) corr[r] -= 2 * tm.z * (1 - 2 * x);
       }
     }
     int lin[NR];
@@ -280,10 +286,10 @@ template <class R, int NS, bool EN = true> struct Tile {
 
   // -------------------------------------------------------------- ops at one position
   template <int K>
-  __device__ __forceinline__ void ops_at(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, const Ctx<R>& cx,
-                                         const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
+  __device__ __forceinline__ void ops_at(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, uint64_t F,
+                                         const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
     if (!ops) return;
-    const uint64_t zb = zbase<K>(S, tile_base);
+    const uint64_t zb = zbase<K>(S, tile_base, F);
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
       hvals<K>(S, zb, cx.terms, cx.T, hv);
@@ -357,71 +363,97 @@ template <class R, int NS, bool EN = true> struct Tile {
     }
   }
 
-  // -------------------------------------------------------------- global I/O at LAST
-  // Thread bits are tile bits 0..LB-1, register bits are tile bits LB..L-1.  Dummy tile
-  // bits (whole state smaller than a tile) have no global position: amplitudes with a
-  // dummy bit set are neither loaded (they are zero) nor stored.
-  __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const {
+  // -------------------------------------------------------------- global I/O
+  // Loads and stores happen at the load arrangement LAST: the top tile bits in
+  // registers, tile bits 0..8 over the threads, so 32 lanes touch >= 32 consecutive
+  // amplitudes (>= 256 bytes).  Dummy tile bits (whole state smaller than a tile) have no
+  // global position: amplitudes with a dummy bit set are neither loaded (they are zero)
+  // nor stored.
+  template <int K> __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const {
+    constexpr int B0 = G::b0(K);
     const uint32_t t = threadIdx.x;
     uint64_t toff = 0;
 #pragma unroll
-    for (int i = 0; i < LB; ++i)
-      if (S.pos[i] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[i];
+    for (int i = 0; i < LB; ++i) {
+      const int tb = (i < B0) ? i : i + RB;
+      if (S.pos[tb] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[tb];
+    }
     return toff;
   }
-  template <int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) { return S.roff[r]; }
-  template <int r> __device__ __forceinline__ void load_r(int s, const V* p, const SetSpec& S) {
-    if (S.dummy && (tidx<G::b0(LAST), RB>(threadIdx.x, r) & S.dummy))
-      a[s][r] = mkv<R>(R(0), R(0));
-    else
-      a[s][r] = p[reg_off<r>(S)];
+  // element offset of register r at the load arrangement (host-computed table)
+  template <int K, int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    return S.roff[r];
   }
-  template <int r> __device__ __forceinline__ void store_r(int s, V* p, const SetSpec& S) const {
-    if (!(S.dummy && (tidx<G::b0(LAST), RB>(threadIdx.x, r) & S.dummy))) p[reg_off<r>(S)] = a[s][r];
+  template <int K> __device__ __forceinline__ bool is_dummy(const SetSpec& S, int r) const {
+    return S.dummy && (tidx<G::b0(K), RB>(threadIdx.x, r) & S.dummy);
   }
-  template <int r = 0> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
+  template <int K, int r = 0> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
     if constexpr (r < NR) {
-      load_r<r>(s, p, S);
-      load_all<r + 1>(s, p, S);
+      a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[reg_off<K, r>(S)];
+      load_all<K, r + 1>(s, p, S);
     }
   }
-  template <int r = 0> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
+  template <int K, int r = 0> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
     if constexpr (r < NR) {
-      store_r<r>(s, p, S);
-      store_all<r + 1>(s, p, S);
+      if (!is_dummy<K>(S, r)) p[reg_off<K, r>(S)] = a[s][r];
+      store_all<K, r + 1>(s, p, S);
     }
   }
-  __device__ __forceinline__ void load(int s, const V* __restrict__ src, const SetSpec& S, uint64_t tile_base) {
-    load_all(s, src + tile_base + thread_off(S), S);
-  }
-  __device__ __forceinline__ void store(int s, V* __restrict__ dst, const SetSpec& S, uint64_t tile_base) const {
-    store_all(s, dst + tile_base + thread_off(S), S);
-  }
-  __device__ __forceinline__ void init_plus(const SetSpec& S, R amp) {
-    const uint32_t t = threadIdx.x;
+  template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint32_t j = tidx<G::b0(LAST), RB>(t, r);
-      a[0][r] = mkv<R>((j & S.dummy) ? R(0) : amp, R(0));
-    }
+    for (int r = 0; r < NR; ++r) a[0][r] = mkv<R>(is_dummy<K>(S, r) ? R(0) : amp, R(0));
   }
 
   // -------------------------------------------------------------- one sweep on one tile
-  // Executes program `pg` on the tile with id `tile` of set S.  With `io` false the
-  // state stays in registers (whole state in one tile); stores still happen when the
-  // program asks for them and a destination exists.
+  // Mixer routes (both start at the load arrangement 3): ROUTE_3012 for the set that
+  // holds global bits 0..3 actively, ROUTE_312 for the others, whose active bits are all
+  // tile bits >= 5.  Mixer A walks the route forward and ends at the phase arrangement 2,
+  // mixer B walks it back to the load arrangement.
+  template <int RT> __device__ __forceinline__ void mix_fwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    mix_at<3>(todo, k, w, wcur, gr, gs);
+    if constexpr (RT == ROUTE_3012) {
+      xchg<3, 0>(lds);
+      mix_at<0>(todo, k, w, wcur, gr, gs);
+      xchg<0, 1>(lds);
+    } else {
+      xchg<3, 1>(lds);
+    }
+    mix_at<1>(todo, k, w, wcur, gr, gs);
+    xchg<1, 2>(lds);
+    mix_at<2>(todo, k, w, wcur, gr, gs);
+  }
+  template <int RT> __device__ __forceinline__ void mix_bwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    mix_at<2>(todo, k, w, wcur, gr, gs);
+    xchg<2, 1>(lds);
+    mix_at<1>(todo, k, w, wcur, gr, gs);
+    if constexpr (RT == ROUTE_3012) {
+      xchg<1, 0>(lds);
+      mix_at<0>(todo, k, w, wcur, gr, gs);
+      xchg<0, 3>(lds);
+    } else {
+      xchg<1, 3>(lds);
+    }
+    mix_at<3>(todo, k, w, wcur, gr, gs);
+  }
+
+  // Executes program `pg` on the tile with id `tile` of set S (whose route is RT).
+  // With `io` false the state stays in registers (whole state in one tile); stores still
+  // happen when the program asks for them and a destination exists.
+  template <int RT>
   __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                       const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
                                       double* zz_lds) {
+    constexpr int KL = LAST;
     const uint64_t tile_base = pdep64(tile, S.fixmask);
     if (pg.flags & F_INIT) {
-      init_plus(S, cx.amp);
+      init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load(0, cx.psi, S, tile_base);
+      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
-        load(NS - 1, cx.lam, S, tile_base);
+        load_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -433,54 +465,40 @@ template <class R, int NS, bool EN = true> struct Tile {
       }
     }
     const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
-    // position "pre" at the load arrangement
-    ops_at<LAST>(pg.pre_ops, make_lam, S, tile_base, cx, ltab_pre, acc.gpre, acc, zz_lds);
-    int at = LAST;
+    ops_at<KL>(pg.pre_ops, make_lam, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    bool at_p = false;
     if (pg.mixA_dir) {
-      const R k = (R)sc.kA, w = (R)sc.wA;
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      const bool gr = pg.mixA_grad != 0;
-      static_assert(NA == 4, "arrangement sequence written for four arrangements");
-      mix_at<3>(todo, k, w, wcur, gr, gs);
-      xchg<3, 0>(lds_x, sc.flipA);
-      mix_at<0>(todo, k, w, wcur, gr, gs);
-      xchg<0, 1>(lds_x);
-      mix_at<1>(todo, k, w, wcur, gr, gs);
-      xchg<1, 2>(lds_x);
-      mix_at<2>(todo, k, w, wcur, gr, gs);
+      mix_fwd<RT>(todo, (R)sc.kA, (R)sc.wA, wcur, pg.mixA_grad != 0, gs, lds_x);
       acc.ba += (double)gs;
-      at = P;
+      at_p = true;
     }
-    const bool need_mid = pg.mid_ops || pg.mixB_dir;
-    if (need_mid && at == LAST) {
-      xchg<LAST, P>(lds_x);
-      at = P;
+    if ((pg.mid_ops || pg.mixB_dir) && !at_p) {
+      xchg<KL, P>(lds_x);
+      at_p = true;
     }
-    ops_at<P>(pg.mid_ops, make_lam, S, tile_base, cx, ltab_mid, acc.gmid, acc, zz_lds);
+    ops_at<P>(pg.mid_ops, make_lam, S, tile_base, sc.F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
     if (pg.mixB_dir) {
-      const R k = (R)sc.kB, w = (R)sc.wB;
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      const bool gr = pg.mixB_grad != 0;
-      mix_at<2>(todo, k, w, wcur, gr, gs);
-      xchg<2, 1>(lds_x, sc.flipB);
-      mix_at<1>(todo, k, w, wcur, gr, gs);
-      xchg<1, 0>(lds_x);
-      mix_at<0>(todo, k, w, wcur, gr, gs);
-      xchg<0, 3>(lds_x);
-      mix_at<3>(todo, k, w, wcur, gr, gs);
+      mix_bwd<RT>(todo, (R)sc.kB, (R)sc.wB, wcur, pg.mixB_grad != 0, gs, lds_x);
       acc.bb += (double)gs;
-      at = LAST;
+      at_p = false;
     }
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
-    if ((st_psi || st_lam) && at != LAST) {
-      xchg<P, LAST>(lds_x);
-      at = LAST;
-    }
-    if (st_psi) store(0, cx.psi, S, tile_base);
-    if (st_lam) store(NS - 1, cx.lam, S, tile_base);
+    if ((st_psi || st_lam) && at_p) xchg<P, KL>(lds_x);
+    if (st_psi) store_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
+    if (st_lam) store_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
+  }
+  __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+                                          const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,
+                                          Acc& acc, double* zz_lds) {
+    if (S.route == ROUTE_312)
+      run<ROUTE_312>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
+    else
+      run<ROUTE_3012>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
   }
 };
 
@@ -547,10 +565,10 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       si = 0.0;
     }
   };
-  auto mixer = [&](int layer, int dir, uint32_t act, double& k, double& w, uint32_t& flip, double& sx) {
+  uint64_t F = 0, mF = 0;  // flip mask in registers / of the buffers in memory
+  auto mixer = [&](int layer, int dir, uint32_t act, uint64_t gact, double& k, double& w, double& sx) {
     k = 0.0;
     w = 1.0;
-    flip = 0;
     sx = 1.0 / (sr * sr + si * si);
     if (!dir) return;
     double sn, cs;
@@ -564,7 +582,7 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       k = -dir * cs / sn;
       pr = 0.0;
       pi = -dir * sn;
-      flip = act;
+      F ^= gact;
     }
     w = pr * pr + pi * pi;
     // sigma /= phi^m
@@ -592,9 +610,11 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
     if (pg.flags & F_INIT) {
       sr = 1.0;
       si = 0.0;
+      F = 0;
     } else if (pg.flags & F_LOAD_PSI) {
       sr = mpr;
       si = mpi;
+      F = mF;
     }
     if (pg.flags & F_LOAD_LAM) {  // lambda <- lambda * sigma_psi / sigma_lam
       const double d = mlr * mlr + mli * mli;
@@ -604,13 +624,17 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       r.fix_lam = (fr != 1.0 || fi != 0.0) ? 1u : 0u;
     }
     const uint32_t act = sets[pg.set].act;
+    const uint64_t gact = sets[pg.set].gact;
+    r.F_pre = F;
     position(pg.pre_ops, r.rho_pre, r.s_pre);
-    mixer(pg.mixA_layer, pg.mixA_dir, act, r.kA, r.wA, r.flipA, r.s_A);
+    mixer(pg.mixA_layer, pg.mixA_dir, act, gact, r.kA, r.wA, r.s_A);
+    r.F_mid = F;
     position(pg.mid_ops, r.rho_mid, r.s_mid);
-    mixer(pg.mixB_layer, pg.mixB_dir, act, r.kB, r.wB, r.flipB, r.s_B);
+    mixer(pg.mixB_layer, pg.mixB_dir, act, gact, r.kB, r.wB, r.s_B);
     if (pg.flags & F_STORE_PSI) {
       mpr = sr;
       mpi = si;
+      mF = F;
     }
     if (pg.flags & F_STORE_LAM) {
       mlr = sr;
@@ -625,7 +649,7 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
   f.s_mid = f.s_A = f.s_B = 1.0;
   f.kA = f.kB = 0.0;
   f.wA = f.wB = 1.0;
-  f.flipA = f.flipB = 0;
+  f.F_pre = f.F_mid = F;
   f.lam_fix[0] = 1.0;
   f.lam_fix[1] = 0.0;
   f.fix_lam = f.pad = 0;
@@ -652,7 +676,8 @@ template <class R> struct SweepArgs {
 
 #define AAQ_TILE_BOUNDS __launch_bounds__(kThreads)
 
-template <class R, int NS, bool PT, bool EN> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
+// One workgroup per tile; partial sums per tile: partial[slot][tile].
+template <class R, int NS, bool PT, bool EN, int RT> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
   using G = Geo<R>;
   using V = typename G::V;
   __shared__ V lds_x[lds_slot(G::TILE)];
@@ -661,7 +686,6 @@ template <class R, int NS, bool PT, bool EN> __global__ AAQ_TILE_BOUNDS void k_s
   extern __shared__ unsigned char dyn_lds[];  // two phase tables of cmax+1 entries
   V* ltab0 = reinterpret_cast<V*>(dyn_lds);
   V* ltab1 = ltab0 + (A.cmax + 1);
-  const uint32_t tile = blockIdx.x;
   const SwScale& sc = *A.scale;
   if (A.prog.pre_ops & (OP_PHASE | OP_UNPHASE))
     load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax, (A.prog.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
@@ -674,7 +698,8 @@ template <class R, int NS, bool PT, bool EN> __global__ AAQ_TILE_BOUNDS void k_s
   Tile<R, NS, EN> tl;
   Acc acc;
   acc.zero();
-  tl.run(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  const uint32_t tile = blockIdx.x;
+  tl.template run<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
   scale_acc(acc, A.prog, sc);
   double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
   block_sum<6>(v, red);
@@ -756,7 +781,7 @@ template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A
       Acc acc;
       acc.zero();
       const uint32_t nt = big ? S.ntiles : 1u;
-      for (uint32_t t = 0; t < nt; ++t) tl.run(pg, S, sc, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
+      for (uint32_t t = 0; t < nt; ++t) tl.run_any(pg, S, sc, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
       scale_acc(acc, pg, sc);
       double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
       block_sum<6>(v, red);
@@ -847,8 +872,11 @@ __global__ void k_reduce(const double* __restrict__ partial, const RedSrc* __res
 // one <Z_i Z_j> pass over the final state (per-term estimator structure)
 template <class R>
 __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __restrict__ psi, uint64_t N, int i, int j,
-                                                 const double* __restrict__ scale, double* __restrict__ partial) {
+                                                 const double* __restrict__ scale, const uint64_t* __restrict__ flips,
+                                                 double* __restrict__ partial) {
+  // the buffer holds amplitude z ^ F at index z: the sign of the term flips with F_i ^ F_j
   __shared__ double red[4];
+  const double sign = (((*flips >> i) ^ (*flips >> j)) & 1u) ? -1.0 : 1.0;
   double acc = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t z = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; z < N; z += stride) {
@@ -859,7 +887,7 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = *scale * (red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sign * *scale * (red[0] + red[1] + red[2] + red[3]);
 }
 
 // exact integer diagonal values through the same per-amplitude code as the kernels,
@@ -871,7 +899,7 @@ __global__ __launch_bounds__(kThreads) void k_cuts(const GraphDev* g, const int4
   constexpr int KK = (K == 0) ? G::LAST : G::P;
   const uint64_t tile_base = pdep64(blockIdx.x, S.fixmask);
   Tile<R, 1> tl;
-  const uint64_t zb = tl.template zbase<KK>(S, tile_base);
+  const uint64_t zb = tl.template zbase<KK>(S, tile_base, 0ull);
   int v[G::NR];
   if (use_terms)
     tl.template hvals<KK>(S, zb, terms, T, v);
@@ -897,6 +925,23 @@ __global__ __launch_bounds__(kThreads) void k_cuts(const GraphDev* g, const int4
 
 namespace aaq {
 
+template <class R, int RT> static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t dyn,
+                                                    hipStream_t st) {
+  const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
+  const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
+  const dim3 grid(L.set.ntiles), blk(kThreads);
+  if (pt)
+    hipLaunchKernelGGL((k_sweep<R, 1, true, true, RT>), grid, blk, dyn, st, A);
+  else if (L.two_states && en)
+    hipLaunchKernelGGL((k_sweep<R, 2, false, true, RT>), grid, blk, dyn, st, A);
+  else if (L.two_states)
+    hipLaunchKernelGGL((k_sweep<R, 2, false, false, RT>), grid, blk, dyn, st, A);
+  else if (en)
+    hipLaunchKernelGGL((k_sweep<R, 1, false, true, RT>), grid, blk, dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_sweep<R, 1, false, false, RT>), grid, blk, dyn, st, A);
+}
+
 template <class R> static hipError_t sweep_launch(const LaunchSweep& L, hipStream_t st) {
   SweepArgs<R> A;
   A.psi = reinterpret_cast<typename Cx<R>::V*>(L.psi);
@@ -913,19 +958,10 @@ template <class R> static hipError_t sweep_launch(const LaunchSweep& L, hipStrea
   A.set = L.set;
   A.prog = L.prog;
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);
-  const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
-  const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
-  const dim3 grid(L.set.ntiles), blk(kThreads);
-  if (pt)
-    hipLaunchKernelGGL((k_sweep<R, 1, true, true>), grid, blk, dyn, st, A);
-  else if (L.two_states && en)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, true>), grid, blk, dyn, st, A);
-  else if (L.two_states)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, false>), grid, blk, dyn, st, A);
-  else if (en)
-    hipLaunchKernelGGL((k_sweep<R, 1, false, true>), grid, blk, dyn, st, A);
+  if (L.set.route == ROUTE_312)
+    sweep_launch_rt<R, ROUTE_312>(A, L, dyn, st);
   else
-    hipLaunchKernelGGL((k_sweep<R, 1, false, false>), grid, blk, dyn, st, A);
+    sweep_launch_rt<R, ROUTE_3012>(A, L, dyn, st);
   return hipGetLastError();
 }
 
@@ -995,14 +1031,14 @@ hipError_t launch_reduce(const double* partial, const void* src, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, double* partial, int blocks,
-                          bool dbl, hipStream_t st) {
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, const uint64_t* flips,
+                          double* partial, int blocks, bool dbl, hipStream_t st) {
   if (dbl)
     hipLaunchKernelGGL(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j,
-                       scale, partial);
+                       scale, flips, partial);
   else
     hipLaunchKernelGGL(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j,
-                       scale, partial);
+                       scale, flips, partial);
   return hipGetLastError();
 }
 

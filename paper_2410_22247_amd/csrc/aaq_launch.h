@@ -42,8 +42,8 @@ hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t
 hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, hipStream_t st);
 hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
                          hipStream_t st);
-hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, double* partial, int blocks,
-                          bool dbl, hipStream_t st);
+hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, const uint64_t* flips,
+                          double* partial, int blocks, bool dbl, hipStream_t st);
 hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
                        int32_t* out, bool dbl, hipStream_t st);
 int tile_bits(bool dbl);
