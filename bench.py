@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time for the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b"],
+                    help="c3 (default): the n=26 p=4 energy+gradient headline; the others print their own line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
@@ -70,6 +72,12 @@ def main():
 
     import paper_2410_22247_amd as A
     from workloads.configs import config3
+
+    if args.workload != "c3":
+        import bench_configs
+
+        print(json.dumps(bench_configs.run(args.workload, args)), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float64, device="cuda")

@@ -1,0 +1,178 @@
+"""Secondary benchmark workloads (bench.py --workload ...), each printing one JSON line.
+
+c1   15-vertex binary tree, p=1, 16x16 (gamma, beta) grid, complex128, both observables,
+     one batched plan per observable; parity against the p=1 closed form.
+c2   K_16 p=1, star n=20 p=2, random 3-regular n=22 p=3; 256 seeded points each, both
+     observables, complex64, batched plans; parity against the Dicke / hub x Dicke
+     subspace formulas (K_16, star) and the full FP64 oracle on a sample (3-regular).
+c4   512 mixed graphs (trees, stars, K_n, 3-regular; n = 8..18), p=2, energy + adjoint
+     gradient per graph in one persistent HIP-graph replay vs a loop of single calls.
+c5a  random tree n=34, p=1, complex64 forward energy (2^34 amplitudes, 128 GiB) for
+     H_red and H_C; parity against the p=1 closed form.
+c5b  random tree n=33, p=2, energy + adjoint gradient (two 64 GiB states); parity
+     against the light-cone FP64 adjoint.
+"""
+import math
+import time
+
+import numpy as np
+import torch
+
+import paper_2410_22247_amd as A
+from workloads import configs as C
+
+
+def _timed(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def _plan_rate(units, p, obs, grad, gam, bet, prec=A.AAQ_PREC_C64, reps=10):
+    plan = A.Plan(units, p, obs, with_grad=grad, prec=prec)
+    plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
+    dt = _timed(plan.execute, reps)
+    out = plan.execute().cpu().numpy()
+    plan.close()
+    return len(units) / dt, out
+
+
+def c1(args):
+    wp, p, gam, bet = C.config1()
+    pr = A.Problem.from_workload(wp)
+    g, b = gam[:, 0], bet[:, 0]
+    cf = 7 + 0.25 * np.sin(4 * b) * np.sin(g) * (8 + 2 * np.cos(g) + 18 * np.cos(g) ** 2)
+    res = {}
+    for name, obs in (("H_C", A.AAQ_OBS_HC), ("H_red", A.AAQ_OBS_HRED)):
+        rate, out = _plan_rate([pr] * 256, 1, obs, False, gam, bet, prec=A.AAQ_PREC_C128)
+        err = np.abs(out[:, 0] - cf)
+        res[name] = {"evals_s": round(rate, 1), "max_abs_err_vs_closed_form": float(err.max()),
+                     "max_abs_err_interior": float(err.reshape(16, 16)[1:15, 1:15].max())}
+        res[name + "_energies"] = out[:, 0]
+    diff = float(np.max(np.abs(res["H_C_energies"] - res["H_red_energies"])))
+    del res["H_C_energies"], res["H_red_energies"]
+    return {"workload": "c1: binary tree n=15 p=1, 256-point grid, complex128", "unit": "evals/s", "results": res,
+            "max_abs_HC_minus_Hred": diff}
+
+
+def c2(args):
+    from oracle import reduced as R
+    import oracle as O
+
+    res = {}
+    for name, wp, p, gam, bet in C.config2():
+        pr = A.Problem.from_workload(wp)
+        r = {}
+        outs = {}
+        for oname, obs in (("H_C", A.AAQ_OBS_HC), ("H_red", A.AAQ_OBS_HRED)):
+            rate, out = _plan_rate([pr] * 256, p, obs, False, gam, bet)
+            r[oname + "_evals_s"] = round(rate, 1)
+            outs[oname] = out[:, 0]
+        r["speedup_Hred_over_HC"] = round(r["H_red_evals_s"] / r["H_C_evals_s"], 3)
+        if name == "K16":
+            ref = np.array([R.complete_graph_energy(16, gam[i], bet[i]) for i in range(256)])
+        elif name == "star20":
+            ref = np.array([R.star_energy(19, gam[i], bet[i]) for i in range(256)])
+        else:
+            idx = list(range(0, 256, 32))
+            ref_s = np.array([O.energy(wp.n, wp.edges(), wp.terms(0), gam[i], bet[i]) for i in idx])
+            ref = None
+        for oname in ("H_C", "H_red"):
+            if ref is not None:
+                rel = np.abs(outs[oname] - ref) / np.abs(ref)
+            else:
+                rel = np.abs(outs[oname][idx] - ref_s) / np.abs(ref_s)
+            r[oname + "_max_rel_err"] = float(rel.max())
+        res[name] = r
+    return {"workload": "c2: K16 p=1, star20 p=2, 3reg22 p=3; 256 points each, complex64, batched plans",
+            "unit": "evals/s", "results": res}
+
+
+def c4(args):
+    import oracle as O
+
+    probs, p, gam, bet = C.config4()
+    prs = [A.Problem.from_workload(w) for w in probs]
+    rate, out = _plan_rate(prs, p, A.AAQ_OBS_HRED, True, gam, bet, reps=5)
+    # plain: one aaq_energy_grad call per graph
+    ests = {}
+    for i, pr in enumerate(prs):
+        key = (pr.n, probs[i].graph.name, tuple(probs[i].graph.edges))
+        if key not in ests:
+            ests[key] = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    keys = [(pr.n, probs[i].graph.name, tuple(probs[i].graph.edges)) for i, pr in enumerate(prs)]
+
+    def plain():
+        for i in range(len(prs)):
+            ests[keys[i]].energy_grad(gam[i], bet[i])
+
+    dt_plain = _timed(plain, 1)
+    sample = list(range(0, 512, 16))
+    rel_e, rel_g = [], []
+    for i in sample:
+        w = probs[i]
+        e, dg, db = O.energy_grad(w.n, w.edges(), w.terms(1), gam[i], bet[i])
+        rel_e.append(abs(out[i, 0] - e) / abs(e))
+        gr = np.concatenate([dg, db])
+        rel_g.append(np.linalg.norm(out[i, 2:] - gr) / np.linalg.norm(gr))
+    return {"workload": "c4: 512 mixed graphs n=8..18, p=2, H_red energy + adjoint gradient", "unit": "evals/s",
+            "batched_evals_s": round(rate, 1), "plain_evals_s": round(len(prs) / dt_plain, 1),
+            "batched_over_plain": round(rate * dt_plain / len(prs), 2),
+            "max_rel_err_energy_sample": float(max(rel_e)), "max_rel_err_grad_sample": float(max(rel_g)),
+            "oracle_sample": len(sample)}
+
+
+def c5a(args):
+    from oracle import reduced as R
+
+    wp, p, gam, bet = C.config5a(4)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=False)
+    res = {}
+    for oname, obs in (("H_red", A.AAQ_OBS_HRED), ("H_C", A.AAQ_OBS_HC)):
+        A.aaq_timing_read(reset=True)
+        A.aaq_timing_enable(True)
+        dt = _timed(lambda: est.energy(gam[0], bet[0], obs=obs), 2)
+        A.aaq_timing_enable(False)
+        tm = A.aaq_timing_read(reset=True)
+        errs = []
+        for k in range(len(gam)):
+            e = est.energy(gam[k], bet[k], obs=obs)[0]
+            ref = R.p1_energy(wp.n, wp.edges(), wp.terms(obs), gam[k, 0], bet[k, 0])
+            errs.append(abs(e - ref) / abs(ref))
+        res[oname] = {"s_per_eval": round(dt, 4), "max_rel_err_vs_closed_form": float(max(errs)),
+                      "sweep_GBps": {c: round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                                     for c, v in tm.items() if v["bytes"]}}
+    return {"workload": "c5a: random tree n=34 (seed 5) p=1, complex64 energy, 2^34 amplitudes", "results": res}
+
+
+def c5b(args):
+    from oracle import reduced as R
+
+    wp, p, gam, bet = C.config5b(2)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    res = {}
+    for oname, obs in (("H_red", A.AAQ_OBS_HRED), ("H_C", A.AAQ_OBS_HC)):
+        A.aaq_timing_read(reset=True)
+        A.aaq_timing_enable(True)
+        dt = _timed(lambda: est.energy_grad(gam[0], bet[0], obs=obs), 2)
+        A.aaq_timing_enable(False)
+        tm = A.aaq_timing_read(reset=True)
+        e, dg, db, nrm = est.energy_grad(gam[1], bet[1], obs=obs)
+        e_lc, dg_lc, db_lc, mb = R.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(obs), gam[1], bet[1])
+        g, gr = np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc])
+        res[oname] = {"s_per_eval": round(dt, 4), "rel_err_energy": abs(e - e_lc) / abs(e_lc),
+                      "rel_err_grad": float(np.linalg.norm(g - gr) / np.linalg.norm(gr)), "light_cone_max_ball": mb,
+                      "sweep_GBps": {c: round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
+                                     for c, v in tm.items() if v["bytes"]}}
+    return {"workload": "c5b: random tree n=33 (seed 5) p=2, complex64 energy + adjoint gradient", "results": res}
+
+
+def run(name, args):
+    torch.cuda.set_device(0)
+    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b}[name](args)

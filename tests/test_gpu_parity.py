@@ -230,3 +230,26 @@ def test_plan_energy_only_complex128_grid():
         out = plan.execute().cpu().numpy()
         assert np.max(np.abs(out[:, 0] - cf)) < 1e-11
         plan.close()
+
+
+# ------------------------------------------------------------------ autograd + Adam
+def test_autograd_function_and_adam():
+    from paper_2410_22247_amd.autograd import adam_maximize, qaoa_energy
+
+    g = G.prufer_tree(16, 2)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, 2, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    gam = torch.tensor([0.4, 0.9], dtype=torch.float64, requires_grad=True)
+    bet = torch.tensor([0.6, 0.3], dtype=torch.float64, requires_grad=True)
+    e = qaoa_energy(gam, bet, est)
+    (3.0 * e).backward()
+    e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(OBS_HRED), [0.4, 0.9], [0.6, 0.3])
+    check_energy(float(e), e_ref)
+    check_grad(np.concatenate([gam.grad.numpy(), bet.grad.numpy()]) / 3.0, np.concatenate([dg_ref, db_ref]))
+    # Adam maximises <H_red>: the expected cut increases and ends near the oracle value
+    gf, bf, hist = adam_maximize(est, [0.4, 0.9], [0.6, 0.3], steps=30, lr=0.05)
+    assert hist[-1] > hist[0] + 0.1
+    e_end = O.energy(g.n, g.edge_array(), wp.terms(OBS_HRED), gf, bf)
+    e_hc = O.energy(g.n, g.edge_array(), wp.terms(OBS_HC), gf, bf)
+    assert abs(e_end - e_hc) < 1e-9 and e_end > hist[-1] - 0.05
