@@ -556,6 +556,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   GraphDev g = make_graph(pr);
   std::vector<int4> terms = make_terms(pr, obs);
   g.T = S.T;
+  g.h_is_cut = obs == AAQ_OBS_HC;
   std::memcpy(up.data() + L.graph, &g, sizeof(g));
   if (!terms.empty()) std::memcpy(up.data() + L.terms, terms.data(), sizeof(int4) * terms.size());
   std::memcpy(up.data() + L.params, gamma, sizeof(double) * p);
@@ -636,6 +637,14 @@ struct aaq_plan {
   size_t units_off = 0, progs_off = 0, order_off = 0, counter_off = 0;
   int blocks = 0;
   int tabmax = 1;
+  int nsmall = 0;  // units run by the persistent kernel (state in one tile)
+  struct Group {
+    size_t list_off;          // device int32 list of unit indices
+    int nlist, max_tiles, nsweep;
+    std::vector<SweepProg> progs;  // the group's common program (for launch shapes)
+    std::vector<uint8_t> routes;   // route of the set of each step
+  };
+  std::vector<Group> groups;
   // captured graph
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -647,10 +656,11 @@ struct aaq_plan {
 namespace {
 
 struct PlanLayout {
-  size_t units = 0, progs = 0, order = 0, counter = 0, graphs = 0, total = 0;
+  size_t units = 0, progs = 0, order = 0, counter = 0, lists = 0, graphs = 0, total = 0;
   std::vector<UnitDesc> ud;
   std::vector<SweepProg> progs_v;
-  std::vector<int32_t> order_v;
+  std::vector<int32_t> order_v;       // small units (n <= L), largest first
+  std::vector<std::vector<int32_t>> group_units;  // large units grouped by tile-set count
   std::vector<unsigned char> blob;  // graphs + terms (uploaded), offsets relative to `graphs`
 };
 
@@ -688,6 +698,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     if (it == gmap.end()) {
       GraphDev g = make_graph(pr);
       g.T = D.T;
+      g.h_is_cut = obs == AAQ_OBS_HC;
       std::vector<int4> t = make_terms(pr, obs);
       int64_t goff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(GraphDev)));
@@ -720,6 +731,8 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   off = align_up(off + sizeof(int32_t) * count);
   PL.counter = off;
   off = align_up(off + sizeof(int32_t));
+  PL.lists = off;
+  off = align_up(off + sizeof(int32_t) * count);
   PL.graphs = off;
   off = align_up(off + PL.blob.size());
   for (int i = 0; i < count; ++i) {
@@ -731,20 +744,30 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.tab_off = (int64_t)off;
     off = align_up(off + amp * (size_t)p * (D.cmax + 1) + sizeof(SwScale) * (D.nsweep + 1));
   }
+  std::map<int, std::vector<int32_t>> by_k;
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];
     if (D.n > L) {
       D.state_off = (int64_t)off;
       off = align_up(off + amp * ((size_t)1 << D.n) * (grad ? 2 : 1));
+      D.ntiles = (int32_t)(1u << (D.n - L));
+      D.part_off = (int64_t)off;
+      off = align_up(off + sizeof(double) * 6 * (size_t)D.nsweep * D.ntiles);
+      by_k[D.nsets].push_back(i);
     } else {
       D.state_off = -1;
+      D.ntiles = 1;
+      D.part_off = -1;
     }
   }
   PL.total = off;
-  PL.order_v.resize(count);
-  for (int i = 0; i < count; ++i) PL.order_v[i] = i;
+  PL.order_v.clear();
+  for (int i = 0; i < count; ++i)
+    if (PL.ud[i].n <= L) PL.order_v.push_back(i);
   if (o.sort_units)
     std::stable_sort(PL.order_v.begin(), PL.order_v.end(), [&](int a, int b) { return PL.ud[a].n > PL.ud[b].n; });
+  PL.group_units.clear();
+  for (auto& kv : by_k) PL.group_units.push_back(kv.second);
   return AAQ_OK;
 }
 
@@ -761,10 +784,40 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
   U.out_stride = 2 + 2 * P->p;
   U.tabmax = P->tabmax;
   U.psi_io = nullptr;
-  HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));
-  TimedLaunch tl(KC_UNITS, 0.0, hs);
-  HIPCHK(launch_units(U, P->grad, P->dbl, P->blocks, hs));
-  tl.done();
+  {
+    TimedLaunch tl(KC_TABLES, 0.0, hs);
+    HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));  // every unit; also resets the counter
+    tl.done();
+  }
+  if (P->nsmall > 0) {
+    U.count = P->nsmall;
+    TimedLaunch tl(KC_UNITS, 0.0, hs);
+    HIPCHK(launch_units(U, P->grad, P->dbl, std::min(P->blocks, P->nsmall), hs));
+    tl.done();
+  }
+  for (const auto& Gp : P->groups) {
+    LaunchBatch B;
+    B.units = U.units;
+    B.progs = U.progs;
+    B.list = (const int32_t*)(P->ws + Gp.list_off);
+    B.ws = P->ws;
+    B.nlist = Gp.nlist;
+    B.max_tiles = Gp.max_tiles;
+    B.tabmax = P->tabmax;
+    for (int s = 0; s < Gp.nsweep; ++s) {
+      const SweepProg& pg = Gp.progs[s];
+      B.step = s;
+      B.route = Gp.routes[s];
+      B.two_states = P->grad && needs_two_states(pg);
+      B.energy = ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) != 0;
+      TimedLaunch tl(B.two_states ? KC_SWEEP2 : KC_SWEEP1, 0.0, hs);
+      HIPCHK(launch_bsweep(B, P->dbl, hs));
+      tl.done();
+    }
+    TimedLaunch tl(KC_REDUCE, 0.0, hs);
+    HIPCHK(launch_bsweep_out(B, d_out, 2 + 2 * P->p, P->grad, P->dbl, hs));
+    tl.done();
+  }
   return AAQ_OK;
 }
 
@@ -931,7 +984,14 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   std::vector<unsigned char> up(PL.graphs + PL.blob.size(), 0);
   std::memcpy(up.data() + PL.units, PL.ud.data(), sizeof(UnitDesc) * count);
   if (!PL.progs_v.empty()) std::memcpy(up.data() + PL.progs, PL.progs_v.data(), sizeof(SweepProg) * PL.progs_v.size());
-  std::memcpy(up.data() + PL.order, PL.order_v.data(), sizeof(int32_t) * count);
+  if (!PL.order_v.empty()) std::memcpy(up.data() + PL.order, PL.order_v.data(), sizeof(int32_t) * PL.order_v.size());
+  {
+    size_t lo = PL.lists;
+    for (auto& gl : PL.group_units) {
+      std::memcpy(up.data() + lo, gl.data(), sizeof(int32_t) * gl.size());
+      lo += sizeof(int32_t) * gl.size();
+    }
+  }
   if (!PL.blob.empty()) std::memcpy(up.data() + PL.graphs, PL.blob.data(), PL.blob.size());
   HIPCHK(hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, hs));
   HIPCHK(hipStreamSynchronize(hs));
@@ -948,6 +1008,23 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   P->order_off = PL.order;
   P->counter_off = PL.counter;
   for (int i = 0; i < count; ++i) P->tabmax = std::max(P->tabmax, PL.ud[i].cmax + 1);
+  P->nsmall = (int)PL.order_v.size();
+  {
+    size_t lo = PL.lists;
+    for (auto& gl : PL.group_units) {
+      aaq_plan::Group Gp;
+      Gp.list_off = lo;
+      lo += sizeof(int32_t) * gl.size();
+      Gp.nlist = (int)gl.size();
+      Gp.max_tiles = 0;
+      for (int u : gl) Gp.max_tiles = std::max(Gp.max_tiles, (int)PL.ud[u].ntiles);
+      const UnitDesc& D0 = PL.ud[gl[0]];
+      Gp.nsweep = D0.nsweep;
+      Gp.progs.assign(PL.progs_v.begin() + D0.prog_off, PL.progs_v.begin() + D0.prog_off + D0.nsweep);
+      for (const SweepProg& pg : Gp.progs) Gp.routes.push_back(D0.sets[pg.set].route);
+      P->groups.push_back(Gp);
+    }
+  }
   P->blocks = o.workgroups > 0 ? o.workgroups : 2 * device_cus();
   if (P->blocks > count) P->blocks = count;
   *out = P;

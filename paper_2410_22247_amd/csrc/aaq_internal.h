@@ -96,6 +96,8 @@ struct SwScale {
 // graph block in device memory (uniform, read with scalar loads)
 struct GraphDev {
   int32_t n, m, T, cmax;   // cmax = |E| = last phase-table index
+  int32_t h_is_cut;        // the observable is H_C: h(z) = C(z), computed from the adjacency masks
+  int32_t pad0;
   uint64_t adj[kMaxN];     // adjacency bitmasks
   int32_t deg[kMaxN];
   int32_t pad[2];
@@ -111,6 +113,9 @@ struct UnitDesc {
   int32_t prog_off;    // index of the first SweepProg
   int32_t row;         // row in d_params / d_out
   int32_t T, cmax;
+  int64_t part_off;    // byte offset of the per-tile partial sums [nsweep][6][ntiles] (n > L units)
+  int32_t ntiles;      // tiles per sweep
+  int32_t pad;
   SetSpec sets[kMaxSets];
 };
 

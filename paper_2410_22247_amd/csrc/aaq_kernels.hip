@@ -292,7 +292,10 @@ template <class R, int NS, bool EN = true> struct Tile {
     const uint64_t zb = zbase<K>(S, tile_base, F);
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
-      hvals<K>(S, zb, cx.terms, cx.T, hv);
+      if (cx.g->h_is_cut)
+        cuts<K>(S, zb, cx.g, hv);
+      else
+        hvals<K>(S, zb, cx.terms, cx.T, hv);
       double e = 0.0, nr = 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -806,6 +809,99 @@ template <class R, int NS> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A
 }
 
 // ---------------------------------------------------------------------------------
+// Batched sweeps for plan units larger than one tile: one launch per sweep step over
+// every tile of every unit of a group (units with the same program structure).  Block
+// (x, y) runs tile x of unit list[y]; blocks past the unit's tile count exit.
+template <class R> struct BatchArgs {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* list;  // unit indices of the group
+  unsigned char* ws;
+  int step;
+  int tabmax;
+};
+
+template <class R, int NS, bool EN, int RT> __global__ AAQ_TILE_BOUNDS void k_bsweep(BatchArgs<R> A) {
+  using G = Geo<R>;
+  using V = typename G::V;
+  __shared__ V lds_x[lds_slot(G::TILE)];
+  __shared__ double red[(kThreads / 64) * 6];
+  extern __shared__ unsigned char dyn_lds[];
+  const int u = A.list[blockIdx.y];
+  const UnitDesc* D = A.units + u;
+  const uint32_t tile = blockIdx.x;
+  if (tile >= (uint32_t)D->ntiles || A.step >= D->nsweep) return;
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + A.tabmax;
+  const int p = D->p;
+  const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
+  const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
+  const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
+  const SwScale& sc = unit_scales<R>(A.ws, D)[A.step];
+  const SweepProg pg = A.progs[D->prog_off + A.step];
+  const SetSpec& S = D->sets[pg.set];
+  if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+  if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  __syncthreads();
+  V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
+  V* lam = psi + ((size_t)1 << D->n);
+  Ctx<R> cx{g, terms, tab, psi, NS == 2 ? lam : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+  Tile<R, NS, EN> tl;
+  Acc acc;
+  acc.zero();
+  tl.template run<RT>(pg, S, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, nullptr);
+  scale_acc(acc, pg, sc);
+  double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+  block_sum<6>(v, red);
+  if (threadIdx.x == 0) {
+    double* part = reinterpret_cast<double*>(A.ws + D->part_off) + (size_t)A.step * 6 * D->ntiles;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) part[(size_t)i * D->ntiles + tile] = v[i];
+  }
+  (void)p;
+}
+
+// per-unit fixed-order sums of the batched sweeps' partials into d_out rows
+template <class R> __global__ void k_bsweep_out(BatchArgs<R> A, double* out, int out_stride, int grad) {
+  __shared__ double red[4];
+  const int u = A.list[blockIdx.x];
+  const UnitDesc* D = A.units + u;
+  const int p = D->p, nt = D->ntiles;
+  double* o = out + (size_t)D->row * out_stride;
+  const double* part = reinterpret_cast<const double*>(A.ws + D->part_off);
+  auto slot_sum = [&](int s, int slot) -> double {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) v += part[((size_t)s * 6 + slot) * nt + t];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return r;
+  };
+  for (int oi = 0; oi < 2 + 2 * p; ++oi) {
+    double tot = 0.0;
+    for (int s = 0; s < D->nsweep; ++s) {
+      const SweepProg pg = A.progs[D->prog_off + s];
+      if (oi < 2) {
+        if ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) tot += slot_sum(s, oi);
+      } else if (grad && oi < 2 + p) {
+        const int l = oi - 2;
+        if ((pg.pre_ops & OP_GRADG) && pg.pre_layer == l) tot += 2.0 * slot_sum(s, SLOT_GPRE);
+        if ((pg.mid_ops & OP_GRADG) && pg.mid_layer == l) tot += 2.0 * slot_sum(s, SLOT_GMID);
+      } else if (grad) {
+        const int l = oi - 2 - p;
+        if (pg.mixA_grad && pg.mixA_layer == l) tot += 2.0 * slot_sum(s, SLOT_BA);
+        if (pg.mixB_grad && pg.mixB_layer == l) tot += 2.0 * slot_sum(s, SLOT_BB);
+      }
+    }
+    if (threadIdx.x == 0) o[oi] = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // Phase tables exp(-i gamma_l c), c = 0..cmax (gamma_l * c formed and reduced in FP64,
 // rounded to R), then the sweep scale records.
 template <class R>
@@ -1021,6 +1117,45 @@ hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, h
       hipLaunchKernelGGL((k_units<float, 2>), dim3(blocks), dim3(kThreads), dyn, st, A);
     else
       hipLaunchKernelGGL((k_units<float, 1>), dim3(blocks), dim3(kThreads), dyn, st, A);
+  }
+  return hipGetLastError();
+}
+
+template <class R, int NS, bool EN>
+static void bsweep_launch_t(const BatchArgs<R>& A, int route, dim3 grid, size_t dyn, hipStream_t st) {
+  if (route == ROUTE_312)
+    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_312>), grid, dim3(kThreads), dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_3012>), grid, dim3(kThreads), dyn, st, A);
+}
+
+hipError_t launch_bsweep(const LaunchBatch& L, bool dbl, hipStream_t st) {
+  const dim3 grid(L.max_tiles, L.nlist);
+  if (dbl) {
+    BatchArgs<double> A{L.units, L.progs, L.list, L.ws, L.step, L.tabmax};
+    const size_t dyn = 2 * sizeof(double2) * (size_t)L.tabmax;
+    if (L.two_states)
+      (L.energy ? bsweep_launch_t<double, 2, true> : bsweep_launch_t<double, 2, false>)(A, L.route, grid, dyn, st);
+    else
+      (L.energy ? bsweep_launch_t<double, 1, true> : bsweep_launch_t<double, 1, false>)(A, L.route, grid, dyn, st);
+  } else {
+    BatchArgs<float> A{L.units, L.progs, L.list, L.ws, L.step, L.tabmax};
+    const size_t dyn = 2 * sizeof(float2) * (size_t)L.tabmax;
+    if (L.two_states)
+      (L.energy ? bsweep_launch_t<float, 2, true> : bsweep_launch_t<float, 2, false>)(A, L.route, grid, dyn, st);
+    else
+      (L.energy ? bsweep_launch_t<float, 1, true> : bsweep_launch_t<float, 1, false>)(A, L.route, grid, dyn, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st) {
+  if (dbl) {
+    BatchArgs<double> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
+    hipLaunchKernelGGL(k_bsweep_out<double>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
+  } else {
+    BatchArgs<float> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
+    hipLaunchKernelGGL(k_bsweep_out<float>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
   }
   return hipGetLastError();
 }

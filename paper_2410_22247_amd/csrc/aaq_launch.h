@@ -35,7 +35,18 @@ struct LaunchUnits {
   void* psi_io;
 };
 
+struct LaunchBatch {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* list;  // device list of the group's unit indices
+  unsigned char* ws;
+  int nlist, max_tiles, step, tabmax, route;
+  bool two_states, energy;
+};
+
 hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st);
+hipError_t launch_bsweep(const LaunchBatch& L, bool dbl, hipStream_t st);
+hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st);
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
                          int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);

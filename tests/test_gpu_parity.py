@@ -215,6 +215,36 @@ def test_plan_matches_single_calls_and_oracle():
         plan.close()
 
 
+@pytest.mark.parametrize("obs", [OBS_HC, OBS_HRED], ids=["H_C", "H_red"])
+@pytest.mark.parametrize("grad", [False, True], ids=["energy", "grad"])
+def test_plan_groups_of_tile_sets(obs, grad):
+    """Units of one, two and three tile sets in one plan (n = 8 ... 23): the large units
+    run as batched multi-workgroup sweeps, one group per tile-set count."""
+    graphs = [G.prufer_tree(8, 1), G.random_regular(3, 14, seed=2), G.star(16), G.prufer_tree(21, 5),
+              G.prufer_tree(22, 6), rand_graph(23, 0.12, 4), G.complete(12)]
+    wps = [make_problem(g) for g in graphs]
+    units = [A.Problem.from_workload(w) for w in wps]
+    assert {A.aaq_num_sets(w.n) for w in wps} == {1, 2, 3}
+    p = 2
+    rng = np.random.default_rng(23)
+    gam = rng.uniform(0, math.pi, (len(units), p))
+    bet = rng.uniform(0, math.pi / 2, (len(units), p))
+    plan = A.Plan(units, p, obs, with_grad=grad, use_graph=True)
+    plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
+    for rep in range(2):
+        out = plan.execute().cpu().numpy()
+        torch.cuda.synchronize()
+        for u, w in enumerate(wps):
+            if grad:
+                e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(obs), gam[u], bet[u])
+                check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
+            else:
+                e_ref = O.energy(w.n, w.edges(), w.terms(obs), gam[u], bet[u])
+            check_energy(out[u, 0], e_ref)
+            assert abs(out[u, 1] - 1) < 1e-5
+    plan.close()
+
+
 def test_plan_energy_only_complex128_grid():
     """Configuration-1 style: the 15-vertex binary tree, p = 1, a parameter grid,
     complex128, both observables equal to the closed form."""
