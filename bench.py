@@ -50,6 +50,50 @@ def load_traffic(kclass: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def kernel_class(name: str):
+    """Timing class of a kernel symbol (the classes aaq_timing_read reports)."""
+    for pre, two, one in (("aaq::k_sweep<", "sweep_2state", "sweep_1state"),
+                          ("aaq::k_bsweep<", "sweep_2state", "sweep_1state")):
+        if pre in name:
+            ns = name.split(pre, 1)[1].split(",")[1].strip()
+            return two if ns == "2" else one
+    for key, cls in (("k_units", "units"), ("k_reduce", "reduce"), ("k_bsweep_out", "reduce"),
+                     ("k_plan_tables", "tables"), ("k_tables", "tables"), ("k_zz_pass", "zz_pass")):
+        if key in name:
+            return cls
+    return None
+
+
+def write_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 512 << 20):
+    """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) of `bench.py --copy-calibration`: each counter is scaled by the ratio of the
+    algorithmic bytes of the 512 MiB calibration copy to what the counter reports for it."""
+    import csv
+
+    out = {"kernel_sha": kernel_hash(), "copy_bytes": copy_bytes, "kernels": {}, "factors": {}}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = list(csv.DictReader(open(path)))
+        copies = [float(r["Counter_Value"]) * 1024 for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref = max(copies)
+        factor = copy_bytes / ref
+        out["factors"][counter] = {"copy_counter_bytes": ref, "factor": factor}
+        for r in rows:
+            c = kernel_class(r["Kernel_Name"])
+            if c is None:
+                continue
+            per.setdefault(c, {}).setdefault(counter, []).append(float(r["Counter_Value"]) * 1024 * factor)
+    for c, d in per.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            f = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+            w = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+            out["kernels"][c] = {"launches": len(d["FETCH_SIZE"]), "fetch_bytes_per_launch": f,
+                                 "write_bytes_per_launch": w, "hbm_bytes_per_launch": f + w}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,7 +106,12 @@ def main():
                     help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b"],
                     help="c3 (default): the n=26 p=4 energy+gradient headline; the others print their own line")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files into profiles/traffic.json")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)

@@ -1,10 +1,10 @@
 // Internal data structures shared by the host planner and the HIP kernels.
 //
 // State layout: amplitude z (vertex v = bit v of z) at element z of a flat array of
-// complex64 (float2) or complex128 (double2).  A "tile" is 2^L amplitudes that one
-// 512-thread workgroup holds in registers (L = 14 for complex64, 13 for complex128):
-// tile bit j is global index bit pos[j]; the remaining global bits are enumerated by
-// the tile id (ascending).  Tile bits always include global bits 0..4 so that every
+// complex64 (float2) or complex128 (double2).  A "tile" is 2^L = 8192 amplitudes that
+// one 512-thread workgroup holds in registers (L = 13 for both precisions): tile bit j
+// is global index bit pos[j]; the remaining global bits are enumerated by the tile id
+// (ascending).  Tile bits always include global bits 0..4 so that every
 // global load/store touches >= 256 contiguous bytes.
 #pragma once
 #include <stdint.h>
@@ -17,7 +17,6 @@ constexpr int kMaxT = 34 * 33 / 2;  // max terms (complete graph on 34 vertices)
 constexpr int kMaxSets = 4;
 constexpr int kThreads = 512;
 constexpr int kMinContig = 5;       // low global bits every tile must contain
-constexpr int kSmallN = 14;         // n <= kSmallN: whole state in one tile (complex64)
 constexpr uint8_t kDummy = 0xFF;    // tile bit without a vertex (n < L)
 
 // mixer routes through the register arrangements (load arrangement 3 first, phase
