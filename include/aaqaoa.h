@@ -105,8 +105,8 @@ aaq_status aaq_workspace_size(const aaq_problem *prob, int p, int with_grad, aaq
 
 /* <H> of the QAOA state (F_p, QAOA section; aggregation eq. of the estimator-cost
  * section; H_red as in "Reducing the Hamiltonian").
- *   d_state      device buffer of >= aaq_state_bytes; overwritten (for n > 14 it holds
- *                intermediate states; its final contents are unspecified)
+ *   d_state      device buffer of >= aaq_state_bytes; overwritten (it holds intermediate
+ *                states; its final contents are unspecified)
  *   d_ws         device workspace of >= aaq_workspace_size bytes
  *   stream       hipStream_t (NULL = default stream)
  *   energy_out   host double
@@ -133,7 +133,8 @@ aaq_status aaq_energy_grad(const aaq_problem *prob, int p, const double *gamma, 
  * C(z) for AAQ_OBS_HC, h_red(z) = sum_m |S_m| [z_{i_m} != z_{j_m}] for AAQ_OBS_HRED
  * (the diagonal of H_C and H_red without the 1/2 (1 - ZZ) rewriting), computed by the
  * same device code that the cost layer and the expectation use.
- *   d_ws   device workspace of >= 512 + 16 * (number of terms) bytes
+ *   d_ws   device workspace of >= 512 + 16 * T * (1 + 2 * aaq_num_sets(n, prec)) bytes
+ *          (T = number of observable terms: the graph block and the term lists)
  *   d_out  device int32[2^n]; n <= 30.  Synchronises the stream. */
 aaq_status aaq_cut_values(const aaq_problem *prob, aaq_observable obs, void *d_ws, size_t ws_bytes, int32_t *d_out,
                           void *stream);
@@ -145,15 +146,35 @@ aaq_status aaq_cut_values(const aaq_problem *prob, aaq_observable obs, void *d_w
 aaq_status aaq_cut_values_layout(const aaq_problem *prob, aaq_observable obs, int set_index, int arrangement,
                                  aaq_precision prec, void *d_ws, size_t ws_bytes, int32_t *d_out, void *stream);
 
-/* Number of tile sets the sweep schedule uses for n qubits (1 when the whole state is
- * one tile: n <= 14 for complex64, n <= 13 for complex128). */
+/* Number of tile sets (groups of qubits mixed in one sweep) that the built-in tile-size
+ * rule gives for n qubits: 1 when the whole state is one tile (n <= 13); the
+ * diagnostic aaq_cut_values_layout uses the same rule.  Precision does not change it. */
 int aaq_num_sets(int n, aaq_precision prec);
 
+/* ---------------------------------------------------------------- tile size and autotuning
+ * The sweeps process the state in tiles of 2^12 or 2^13 amplitudes per workgroup (256 or
+ * 512 threads).  By default the size that gives the fewest sweeps is used, 12 on ties.
+ * aaq_set_tile_bits overrides the choice for one (n, precision, gradient) class of calls
+ * (0 restores the default); the setting is process-wide and guarded by a mutex.
+ * aaq_autotune times `reps` calls of aaq_energy (with_grad = 0) or aaq_energy_grad
+ * (with_grad = 1) at each tile size with the caller's buffers (as for those calls;
+ * d_lambda may be NULL without gradients), keeps the faster one for the problem's class
+ * and reports it; ms_per_call, if not NULL, receives the two timings (tile 12, tile 13).
+ * These calls choose launch shapes only (not a step of the paper's method): results
+ * differ between tile sizes by floating-point summation order at most. */
+aaq_status aaq_set_tile_bits(int n, aaq_precision prec, int with_grad, int tile_bits);
+int aaq_get_tile_bits(int n, aaq_precision prec, int with_grad);
+aaq_status aaq_autotune(const aaq_problem *prob, int p, int with_grad, aaq_observable obs, aaq_precision prec,
+                        void *d_state, size_t state_bytes, void *d_lambda, size_t lambda_bytes, void *d_ws,
+                        size_t ws_bytes, void *stream, int reps, int *best_tile_bits, double *ms_per_call);
+
 /* ---------------------------------------------------------------- batched plans
- * Many (instance, parameter point) units evaluated by one persistent kernel: each
- * workgroup takes the next unit from a device work counter (largest n first) and
- * runs that unit's whole forward (and backward) sweep sequence.  Replays are
- * captured once in a HIP graph.
+ * Many (instance, parameter point) units evaluated together.  Units whose state fits
+ * one tile (n <= 13) run in a persistent kernel: each workgroup takes the next unit from
+ * a device work counter (largest n first) and runs its whole forward (and backward)
+ * sweep sequence in registers, one launch per tile size.  Larger units are grouped by
+ * tile size and tile-set count, and each sweep step is one launch over every tile of
+ * every unit of the group.  Replays are captured once in a HIP graph.
  *   probs[count]  the instance of every unit (the same instance may repeat)
  *   d_params      device double[count][2p]: gamma_0..gamma_{p-1}, beta_0..beta_{p-1}
  *   d_out         device double[count][2 + 2p]: energy, norm, dE/dgamma[p], dE/dbeta[p]
@@ -162,9 +183,13 @@ typedef struct aaq_plan aaq_plan;
 
 typedef struct {
   int use_graph;      /* capture the launches in a HIP graph and replay it (default 1) */
-  int workgroups;     /* persistent workgroups; 0 = one per compute unit x occupancy */
+  int workgroups;     /* persistent workgroups per unit-kernel launch; 0 = automatic */
   int sort_units;     /* 1 = largest n first (default) */
   aaq_precision prec; /* amplitude precision (default AAQ_PREC_C64) */
+  int tile_bits_large;     /* tile size (log2 amplitudes per workgroup tile: 12 or 13) of the units
+                              with n > 13; 0 = fewest sweeps, then 12 (default) */
+  int min_tile_bits_small; /* units with n <= 13 run on the smallest compiled tile (10, 12 or 13
+                              amplitude bits) that is >= max(n, this); 0 = 10 (default) */
 } aaq_plan_opts;
 
 /* Fills opts with the defaults above. */
@@ -174,7 +199,7 @@ aaq_status aaq_plan_workspace_size(const aaq_problem *probs, int count, int p, a
                                    const aaq_plan_opts *opts, size_t *bytes);
 
 /* Validates every unit, lays out the workspace (descriptors, phase tables, per-unit
- * state buffers for n > 14) and uploads descriptors on `stream`. */
+ * state buffers for n > 13) and uploads descriptors on `stream`. */
 aaq_status aaq_plan_create(const aaq_problem *probs, int count, int p, aaq_observable obs, int with_grad,
                            const aaq_plan_opts *opts, void *d_ws, size_t ws_bytes, void *stream,
                            aaq_plan **out);
@@ -185,6 +210,18 @@ aaq_status aaq_plan_create(const aaq_problem *probs, int count, int p, aaq_obser
 aaq_status aaq_plan_execute(aaq_plan *plan, const double *d_params, double *d_out, void *stream);
 
 void aaq_plan_destroy(aaq_plan *plan);
+
+/* Plan autotuner: builds the plan with every candidate of tile_bits_large (12, 13; when
+ * some unit has n > 13), min_tile_bits_small (10, 12, 13; when some unit has n <= 12)
+ * and workgroups (automatic, one and four per compute unit; when some unit has
+ * n <= 13) on top of `base` (NULL = defaults), times `reps` executions of each with HIP
+ * events on `stream` (after one warm-up execution) and returns the fastest options in
+ * *best and their time per execution in *best_ms (may be NULL).  Candidates whose
+ * workspace exceeds ws_bytes are skipped.  d_params / d_out as for aaq_plan_execute;
+ * d_out is overwritten.  Synchronises the stream. */
+aaq_status aaq_plan_autotune(const aaq_problem *probs, int count, int p, aaq_observable obs, int with_grad,
+                             const aaq_plan_opts *base, void *d_ws, size_t ws_bytes, const double *d_params,
+                             double *d_out, void *stream, int reps, aaq_plan_opts *best, double *best_ms);
 
 /* ---------------------------------------------------------------- diagnostics */
 /* Per-kernel timing.  While enabled, every kernel launch of the library is bracketed

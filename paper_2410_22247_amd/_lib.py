@@ -35,6 +35,8 @@ class CPlanOpts(ctypes.Structure):
         ("workgroups", ctypes.c_int),
         ("sort_units", ctypes.c_int),
         ("prec", ctypes.c_int),
+        ("tile_bits_large", ctypes.c_int),
+        ("min_tile_bits_small", ctypes.c_int),
     ]
 
 
@@ -42,7 +44,8 @@ EXPORTS = (
     "aaq_validate", "aaq_state_bytes", "aaq_workspace_size", "aaq_energy", "aaq_energy_grad", "aaq_cut_values",
     "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
     "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
-    "aaq_timing_enable", "aaq_timing_read",
+    "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
+    "aaq_plan_autotune",
 )
 
 
@@ -77,8 +80,12 @@ def lib():
         "aaq_last_error_message": (ctypes.c_char_p, []),
         "aaq_version": (ctypes.c_char_p, []),
         "aaq_timing_enable": (i, [i]),
-
         "aaq_timing_read": (i, [ctypes.POINTER(CKernelTiming), i, ctypes.POINTER(i), i]),
+        "aaq_set_tile_bits": (i, [i, i, i, i]),
+        "aaq_get_tile_bits": (i, [i, i, i]),
+        "aaq_autotune": (i, [P, i, i, i, i, vp, sz, vp, sz, vp, sz, vp, i, ctypes.POINTER(i), dp]),
+        "aaq_plan_autotune": (i, [P, i, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, vp, vp, i,
+                                  ctypes.POINTER(CPlanOpts), dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

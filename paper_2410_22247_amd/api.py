@@ -179,11 +179,56 @@ def aaq_num_sets(n: int, prec: int = AAQ_PREC_C64) -> int:
     return int(_lib.lib().aaq_num_sets(int(n), int(prec)))
 
 
-def _opts(use_graph=True, workgroups=0, sort_units=True, prec=AAQ_PREC_C64):
+def _opts(use_graph=True, workgroups=0, sort_units=True, prec=AAQ_PREC_C64, tile_bits_large=0,
+          min_tile_bits_small=0):
     o = _lib.CPlanOpts()
     _lib.lib().aaq_plan_default_opts(ctypes.byref(o))
     o.use_graph, o.workgroups, o.sort_units, o.prec = int(use_graph), int(workgroups), int(sort_units), int(prec)
+    o.tile_bits_large, o.min_tile_bits_small = int(tile_bits_large), int(min_tile_bits_small)
     return o
+
+
+def _opts_dict(o) -> dict:
+    return {"use_graph": bool(o.use_graph), "workgroups": int(o.workgroups), "sort_units": bool(o.sort_units),
+            "prec": int(o.prec), "tile_bits_large": int(o.tile_bits_large),
+            "min_tile_bits_small": int(o.min_tile_bits_small)}
+
+
+def aaq_set_tile_bits(n: int, prec: int, with_grad: bool, tile_bits: int) -> None:
+    _check(_lib.lib().aaq_set_tile_bits(int(n), int(prec), int(bool(with_grad)), int(tile_bits)))
+
+
+def aaq_get_tile_bits(n: int, prec: int, with_grad: bool) -> int:
+    return int(_lib.lib().aaq_get_tile_bits(int(n), int(prec), int(bool(with_grad))))
+
+
+def aaq_autotune(prob: Problem, p: int, with_grad: bool, obs: int, prec: int, d_state, d_lam, d_ws, reps: int = 3,
+                 stream=None):
+    """Times both tile sizes for this problem class, keeps the faster; returns (tile_bits, {12: ms, 13: ms})."""
+    sp, sb = _dev(d_state)
+    lp, lb = _dev(d_lam) if d_lam is not None else (None, 0)
+    wp, wb = _dev(d_ws)
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * 2)()
+    _check(_lib.lib().aaq_autotune(prob.ref(), int(p), int(bool(with_grad)), int(obs), int(prec), sp, sb, lp, lb, wp,
+                                   wb, _stream(stream), int(reps), ctypes.byref(best), ms))
+    return best.value, {12: ms[0], 13: ms[1]}
+
+
+def aaq_plan_autotune(probs: Sequence[Problem], p: int, obs: int, with_grad: bool, d_ws, d_params, d_out,
+                      reps: int = 3, stream=None, **base):
+    """Fastest plan options for these units (dict for Plan(**opts)) and its ms per execution."""
+    arr = _problem_array(probs)
+    o = _opts(**base)
+    best = _lib.CPlanOpts()
+    ms = ctypes.c_double()
+    wp, wb = _dev(d_ws)
+    pp, _ = _dev(d_params)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_plan_autotune(arr, len(probs), int(p), int(obs), int(bool(with_grad)), ctypes.byref(o), wp,
+                                        wb, pp, op, _stream(stream), int(reps), ctypes.byref(best),
+                                        ctypes.byref(ms)))
+    return _opts_dict(best), ms.value
 
 
 def _problem_array(probs: Sequence[Problem]):
@@ -278,6 +323,31 @@ class Plan:
         self.handle = aaq_plan_create(self._probs, p, obs, with_grad, self.ws, stream, **opts)
         self.params = torch.zeros(self.count, 2 * self.p, dtype=torch.float64, device=device)
         self.out = torch.zeros(self.count, 2 + 2 * self.p, dtype=torch.float64, device=device)
+
+    @staticmethod
+    def autotuned(probs: Sequence[Problem], p: int, obs: int = AAQ_OBS_HRED, with_grad: bool = True, params=None,
+                  reps: int = 3, device: str = "cuda", **base) -> "Plan":
+        """A plan built with the options aaq_plan_autotune measures fastest for these units
+        (parameters: a [count][2p] float64 tensor or array, default all 0.5)."""
+        import itertools
+
+        import torch
+
+        probs = list(probs)
+        cands = itertools.product((12, 13), (10, 12, 13))
+        wb = max(aaq_plan_workspace_size(probs, p, obs, with_grad, **dict(base, tile_bits_large=tl,
+                                                                          min_tile_bits_small=ts))
+                 for tl, ts in cands)
+        ws = torch.empty(wb, dtype=torch.uint8, device=device)
+        prm = torch.full((len(probs), 2 * p), 0.5, dtype=torch.float64, device=device)
+        if params is not None:
+            prm.copy_(torch.as_tensor(params, dtype=torch.float64))
+        out = torch.zeros(len(probs), 2 + 2 * p, dtype=torch.float64, device=device)
+        opts, ms = aaq_plan_autotune(probs, p, obs, with_grad, ws, prm, out, reps=reps, **base)
+        del ws
+        plan = Plan(probs, p, obs, with_grad, device=device, **opts)
+        plan.tuned_opts, plan.tuned_ms = opts, ms
+        return plan
 
     def execute(self, stream=None, params=None, out=None):
         aaq_plan_execute(self.handle, self.params if params is None else params, self.out if out is None else out,

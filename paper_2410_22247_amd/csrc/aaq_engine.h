@@ -1,0 +1,917 @@
+// Device engine (gfx950) of the p-layer MaxCut QAOA statevector estimator: the tile
+// engine and the sweep kernels, templated on the amplitude type R (float: complex64,
+// double: complex128) and the tile size LT (a tile of 2^LT amplitudes held by a
+// workgroup of 2^(LT-4) threads, 16 amplitudes per thread).
+//
+// The tile's register bits are switched between "arrangements" through an LDS
+// transpose so that every mixer butterfly is a register-to-register operation:
+// arrangement k keeps tile bits [b0(k), b0(k)+4) in registers and spreads the other
+// tile bits over the threads.  The last arrangement (high tile bits in registers) is
+// the one used for global loads and stores: consecutive lanes then touch consecutive
+// amplitudes.  The one before it is the "phase" arrangement.
+//
+// A sweep = load (or synthesise |+>) -> ops at the load arrangement -> mixer A
+// through the arrangements -> ops at the phase arrangement -> mixer B back -> store.
+// The ops are the cost phase exp(-i gamma C(z)) (QAOA section, U_P), its inverse,
+// the energy / lambda step and the gradient accumulations of the adjoint method.
+// C(z) and h(z) are exact integers recomputed per amplitude from uint64 adjacency
+// masks and the term lists.
+//
+// Included by one translation unit per (R, LT) instantiation and by the common one.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "aaq_internal.h"
+#include "aaq_launch.h"
+
+namespace aaq {
+
+template <class R> struct Cx;
+template <> struct Cx<float> {
+  using V = float2;
+};
+template <> struct Cx<double> {
+  using V = double2;
+};
+
+template <class R, int LT> struct Geo {
+  using V = typename Cx<R>::V;
+  static constexpr int L = LT, RB = kRegBits, NR = 1 << RB;
+  static constexpr int NA = geo_na(L);
+  static constexpr int LAST = NA - 1, P = NA - 2;
+  static constexpr int TILE = 1 << L;
+  static constexpr int LB = L - RB;  // thread bits
+  static constexpr int NT = 1 << LB; // threads per workgroup
+  __host__ __device__ static constexpr int b0(int k) { return geo_b0(k, L); }
+  static_assert(NA >= 3, "a tile needs a load, a phase and a third arrangement");
+};
+
+template <class R> __device__ __forceinline__ typename Cx<R>::V mkv(R x, R y) {
+  typename Cx<R>::V v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+// tile index of register r of thread t in an arrangement whose register bits start at B0
+template <int B0, int RB> __device__ __forceinline__ uint32_t tidx(uint32_t t, uint32_t r) {
+  return (t & ((1u << B0) - 1u)) | (r << B0) | ((t >> B0) << (B0 + RB));
+}
+// LDS slot of tile index j: one padding slot per 16 entries.  P is additive over
+// disjoint bit sets, P(a | b) = P(a) + P(b), so the slot of (thread part | register
+// part) is a per-thread base plus a compile-time offset.
+__host__ __device__ constexpr uint32_t lds_slot(uint32_t j) { return j + (j >> 4); }
+// thread part of the tile index in an arrangement whose register bits start at B0
+template <int B0, int RB> __device__ __forceinline__ uint32_t tpart(uint32_t t) {
+  return (t & ((1u << B0) - 1u)) | ((t >> B0) << (B0 + RB));
+}
+
+// e^{-i theta X} on an amplitude pair with c = cos(theta), s = sin(theta):
+// (x, y) -> (c x - i s y, -i s x + c y)
+template <class V, class R> __device__ __forceinline__ void bfly(V& x, V& y, R c, R s) {
+  const V x0 = x, y0 = y;
+  x.x = c * x0.x + s * y0.y;
+  x.y = c * x0.y - s * y0.x;
+  y.x = c * y0.x + s * x0.y;
+  y.y = c * y0.y - s * x0.x;
+}
+// (I - i k X) on a pair: (x, y) -> (x - i k y, y - i k x)
+template <class V, class R> __device__ __forceinline__ void bflyk(V& x, V& y, R k) {
+  const V x0 = x, y0 = y;
+  x.x = x0.x + k * y0.y;
+  x.y = x0.y - k * y0.x;
+  y.x = y0.x + k * x0.y;
+  y.y = y0.y - k * x0.x;
+}
+// Im(conj(u) v)
+template <class V> __device__ __forceinline__ auto imcm(const V& u, const V& v) { return u.x * v.y - u.y * v.x; }
+
+__device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
+  uint64_t r = 0;
+  for (uint64_t bit = 1; mask; bit <<= 1) {
+    const uint64_t low = mask & (~mask + 1);
+    if (x & bit) r |= low;
+    mask &= mask - 1;
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------
+// Per-sweep context (all uniform across the workgroup).
+template <class R> struct Ctx {
+  using V = typename Cx<R>::V;
+  const GraphDev* g;
+  const int4* terms;
+  const V* tab;    // [p][cmax+1]
+  V* psi;          // global state (nullptr when the tile never leaves registers)
+  V* lam;
+  R amp;           // 2^{-n/2}
+  int T;
+  int cmax;
+};
+
+// Per-thread accumulators for one sweep.
+struct Acc {
+  double e, nrm, gpre, gmid, ba, bb;
+  __device__ void zero() { e = nrm = gpre = gmid = ba = bb = 0.0; }
+};
+
+// EN: the energy / lambda step is compiled in (only the last forward sweep needs it)
+template <class R, int NS, bool EN, int LT> struct Tile {
+  using G = Geo<R, LT>;
+  using V = typename G::V;
+  static constexpr int NR = G::NR, RB = G::RB, L = G::L, LB = G::LB, NA = G::NA, LAST = G::LAST, P = G::P;
+
+  V a[NS][NR];
+  bool lam_live;
+
+  // -------------------------------------------------------------- LDS transpose
+  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
+    constexpr int BF = G::b0(KF), BT = G::b0(KT);
+    const uint32_t t = threadIdx.x;
+    V* wb = lds + lds_slot(tpart<BF, RB>(t));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) wb[lds_slot((uint32_t)r << BF)] = x[r];
+    __syncthreads();
+    const V* rb = lds + lds_slot(tpart<BT, RB>(t));
+#pragma unroll
+    for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
+    __syncthreads();
+  }
+  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds) {
+    xchg1<KF, KT>(a[0], lds);
+    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
+  }
+
+  // -------------------------------------------------------------- mixer butterflies
+  // (I - i k X_q) on every tile bit of `todo` held in registers by arrangement K:
+  // (x, y) -> (x - i k y, y - i k x), two FMAs per amplitude.  With `grad`, the pair's
+  // Im <lam|X_q|psi> is accumulated with weight wcur, which tracks the scale change of
+  // the preceding gates of the same mixer (wcur *= w after every qubit).
+  template <int K> __device__ __forceinline__ void mix_at(uint32_t& todo, R k, R w, R& wcur, bool grad, R& gsum) {
+    constexpr int B0 = G::b0(K);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if ((todo >> (B0 + b)) & 1u) {
+        R gq = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r & (1 << b)) continue;
+          const int r1 = r | (1 << b);
+          if (NS == 2) {
+            if (grad) gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
+            if (lam_live) bflyk(a[NS - 1][r], a[NS - 1][r1], k);
+          }
+          bflyk(a[0][r], a[0][r1], k);
+        }
+        if (NS == 2 && grad) gsum += wcur * gq;
+        wcur *= w;
+      }
+    }
+    todo &= ~(((1u << RB) - 1u) << B0);
+  }
+
+  // -------------------------------------------------------------- z of register 0
+  // index z of register 0 at arrangement K, XOR the flip mask F: the register-0
+  // amplitude is the one of basis state zbase ^ F (register bits set where F has them)
+  template <int K> __device__ __forceinline__ uint64_t zbase(const SetSpec& S, uint64_t tile_base, uint64_t F) const {
+    constexpr int B0 = G::b0(K);
+    const uint32_t t = threadIdx.x;
+    uint64_t z = tile_base;
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int tb = (i < B0) ? i : i + RB;
+      const uint32_t p = S.pos[tb];
+      if (p != kDummy) z |= (uint64_t)((t >> i) & 1u) << p;
+    }
+    return z ^ F;
+  }
+
+  // C(z) for every register amplitude at arrangement K.  With base b = zb and m the
+  // register bits flipped relative to it: C(b ^ m) = C(b) + sum_{v in m} d_v
+  //   + sum_{edges (v, w) inside m} 2 (2 [b_v != b_w] - 1),
+  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.
+  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, const GraphDev* g, int (&cv)[NR]) const {
+    constexpr int B0 = G::b0(K);
+    const int n = g->n;
+    int c0 = 0;
+    for (int v = 0; v < n; ++v) {
+      const uint64_t av = g->adj[v];
+      c0 += (int)((zb >> v) & 1u) * __popcll(av & ~zb);
+    }
+    int d[RB];
+    uint32_t rr[RB], df[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const uint32_t v = S.pos[B0 + b];
+      d[b] = 0;
+      rr[b] = 0;
+      df[b] = 0;
+      if (v != kDummy) {
+        const uint64_t av = g->adj[v];
+        const uint64_t bv = (zb >> v) & 1u;
+        d[b] = g->deg[v] - 2 * __popcll(av & (zb ^ (0ull - bv)));
+#pragma unroll
+        for (int b2 = 0; b2 < RB; ++b2) {
+          const uint32_t w = S.pos[B0 + b2];
+          if (w != kDummy && ((av >> w) & 1u)) {
+            rr[b] |= 1u << b2;
+            if (((zb >> w) & 1u) != bv) df[b] |= 1u << b2;  // register bits of zb are uniform
+          }
+        }
+      }
+    }
+    cv[0] = c0;
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+      const int hb = 31 - __builtin_clz(r);
+      const int rest = r ^ (1 << hb);
+      const int npair = __popc(rr[hb] & (uint32_t)rest), ndiff = __popc(df[hb] & (uint32_t)rest);
+      cv[r] = cv[rest] + d[hb] + 2 * (2 * ndiff - npair);
+    }
+  }
+
+  // h(z) = sum_t w_t [z_i != z_j] for every register amplitude at arrangement K (the
+  // load or the phase arrangement), from the set's term lists sorted by how many
+  // endpoints sit in register bits: with base zb (register bits 0) and x_t the term's
+  // value there, h(zb ^ m) = h0 + sum_{b in m} dh_b + sum over both-endpoint terms of
+  // the pair correction -2 w (1 - 2x) when m holds both endpoints.
+  template <int K> __device__ __forceinline__ void hvals(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR]) const {
+    static_assert(K == LAST || K == P, "term lists exist for the load and phase arrangements");
+    constexpr int KI = (K == LAST) ? 0 : 1;
+    const int4* tp = terms + S.toff[KI];
+    auto xbit = [&](const int4& tm) -> int { return (int)(((uint32_t)(zb >> tm.x) ^ (uint32_t)(zb >> tm.y)) & 1u); };
+    int h0 = 0;
+    int dh[RB];
+#pragma unroll
+    for (int b = 0; b < RB; ++b) dh[b] = 0;
+    {
+      const int c = S.tcnt[KI][0];
+      for (int t = 0; t < c; ++t) {
+        const int4 tm = tp[t];
+        h0 += tm.z * xbit(tm);
+      }
+      tp += c;
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int c = S.tcnt[KI][1 + b];
+      for (int t = 0; t < c; ++t) {
+        const int4 tm = tp[t];
+        const int x = xbit(tm);
+        h0 += tm.z * x;
+        dh[b] += tm.z - 2 * tm.z * x;
+      }
+      tp += c;
+    }
+    int corr[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) corr[r] = 0;
+    for (int t = 0, c = S.tcnt[KI][5]; t < c; ++t) {
+      const int4 tm = tp[t];
+      const int x = xbit(tm);
+      const int ri = tm.w & 15, rj = tm.w >> 4;
+      const int dv = tm.z - 2 * tm.z * x;
+      h0 += tm.z * x;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+        if (ri == b || rj == b) dh[b] += dv;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (((r >> ri) & 1) && ((r >> rj) & 1)) corr[r] -= 2 * dv;
+    }
+    int lin[NR];
+    lin[0] = h0;
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+      const int hb = 31 - __builtin_clz(r);
+      lin[r] = lin[r ^ (1 << hb)] + dh[hb];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) hv[r] = lin[r] + corr[r];
+  }
+
+  // -------------------------------------------------------------- ops at one position
+  template <int K>
+  __device__ __forceinline__ void ops_at(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, uint64_t F,
+                                         const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
+    if (!ops) return;
+    const uint64_t zb = zbase<K>(S, tile_base, F);
+    if (EN && (ops & OP_ENERGY)) {
+      int hv[NR];
+      if (cx.g->h_is_cut)
+        cuts<K>(S, zb, cx.g, hv);
+      else
+        hvals<K>(S, zb, cx.terms, hv);
+      double e = 0.0, nr = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const R p2 = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
+        e += (double)p2 * (double)hv[r];
+        nr += (double)p2;
+      }
+      acc.e += e;
+      acc.nrm += nr;
+      if (ops & OP_PERTERM) perterm<K>(S, zb, cx, zz_lds);
+      if (NS == 2 && make_lam) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const R h = (R)hv[r];
+          a[NS - 1][r] = mkv<R>(h * a[0][r].x, h * a[0][r].y);
+        }
+        lam_live = true;
+      }
+    }
+    if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
+      int cv[NR];
+      cuts<K>(S, zb, cx.g, cv);
+      if (NS == 2 && (ops & OP_GRADG)) {
+        R gs = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+        gacc += (double)gs;
+      }
+      if (ops & (OP_PHASE | OP_UNPHASE)) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const V tv = ltab[cv[r]];  // exp(-+i gamma C) times the scale correction
+          const R tc = tv.x, ts = tv.y;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            if (s == 0 || lam_live) {
+              const V x = a[s][r];
+              a[s][r] = mkv<R>(x.x * tc - x.y * ts, x.x * ts + x.y * tc);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // <Z_i Z_j> partial sums per term, reduced per wave and added into LDS
+  template <int K> __device__ __forceinline__ void perterm(const SetSpec& S, uint64_t zb, const Ctx<R>& cx, double* zz_lds) const {
+    constexpr int B0 = G::b0(K);
+    R p2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) p2[r] = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
+    for (int t = 0; t < cx.T; ++t) {
+      const int4 tm = cx.terms[t];
+      int ri = -1, rj = -1;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (S.pos[B0 + b] == (uint32_t)tm.x) ri = b;
+        if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
+      }
+      const uint32_t sm = (ri >= 0 ? (1u << ri) : 0u) ^ (rj >= 0 ? (1u << rj) : 0u);
+      R acc = R(0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc += (__popc((uint32_t)r & sm) & 1) ? -p2[r] : p2[r];
+      const int odd = (int)(((zb >> tm.x) ^ (zb >> tm.y)) & 1u);
+      double v = odd ? -(double)acc : (double)acc;
+      v = wave_sum(v);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&zz_lds[t], v);
+    }
+  }
+
+  // -------------------------------------------------------------- global I/O
+  // Loads and stores happen at the load arrangement LAST: the top tile bits in
+  // registers, tile bits 0..8 over the threads, so 32 lanes touch >= 32 consecutive
+  // amplitudes (>= 256 bytes).  Dummy tile bits (whole state smaller than a tile) have no
+  // global position: amplitudes with a dummy bit set are neither loaded (they are zero)
+  // nor stored.
+  template <int K> __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const {
+    constexpr int B0 = G::b0(K);
+    const uint32_t t = threadIdx.x;
+    uint64_t toff = 0;
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int tb = (i < B0) ? i : i + RB;
+      if (S.pos[tb] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[tb];
+    }
+    return toff;
+  }
+  // element offset of register r at the load arrangement (host-computed table)
+  template <int K, int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    return S.roff[r];
+  }
+  template <int K> __device__ __forceinline__ bool is_dummy(const SetSpec& S, int r) const {
+    return S.dummy && (tidx<G::b0(K), RB>(threadIdx.x, r) & S.dummy);
+  }
+  template <int K, int r = 0> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
+    if constexpr (r < NR) {
+      a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[reg_off<K, r>(S)];
+      load_all<K, r + 1>(s, p, S);
+    }
+  }
+  template <int K, int r = 0> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
+    if constexpr (r < NR) {
+      if (!is_dummy<K>(S, r)) p[reg_off<K, r>(S)] = a[s][r];
+      store_all<K, r + 1>(s, p, S);
+    }
+  }
+  template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) a[0][r] = mkv<R>(is_dummy<K>(S, r) ? R(0) : amp, R(0));
+  }
+
+  // -------------------------------------------------------------- one sweep on one tile
+  // Mixer routes (both start at the load arrangement LAST): ROUTE_FULL visits LAST, 0,
+  // 1, ..., P; ROUTE_HIGH, for sets whose active qubits are all tile bits >= 4, skips
+  // arrangement 0.  Mixer A walks the route forward and ends at the phase arrangement
+  // P, mixer B walks it back to LAST.  A qubit is mixed at the first arrangement of the
+  // walk that holds it in registers.
+  template <int K, int PREV>
+  __device__ __forceinline__ void fwd_steps(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    if constexpr (K <= P) {
+      xchg<PREV, K>(lds);
+      mix_at<K>(todo, k, w, wcur, gr, gs);
+      fwd_steps<K + 1, K>(todo, k, w, wcur, gr, gs, lds);
+    }
+  }
+  template <int K, int FIRST>
+  __device__ __forceinline__ void bwd_steps(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    if constexpr (K >= FIRST) {
+      xchg<K + 1, K>(lds);
+      mix_at<K>(todo, k, w, wcur, gr, gs);
+      bwd_steps<K - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
+    }
+  }
+  template <int RT> __device__ __forceinline__ void mix_fwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    mix_at<LAST>(todo, k, w, wcur, gr, gs);
+    fwd_steps<(RT == ROUTE_FULL ? 0 : 1), LAST>(todo, k, w, wcur, gr, gs, lds);
+  }
+  template <int RT> __device__ __forceinline__ void mix_bwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    constexpr int FIRST = (RT == ROUTE_FULL) ? 0 : 1;
+    mix_at<P>(todo, k, w, wcur, gr, gs);
+    bwd_steps<P - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
+    xchg<(FIRST < P ? FIRST : P), LAST>(lds);
+    mix_at<LAST>(todo, k, w, wcur, gr, gs);
+  }
+
+  // Executes program `pg` on the tile with id `tile` of set S (whose route is RT).
+  // With `io` false the state stays in registers (whole state in one tile); stores still
+  // happen when the program asks for them and a destination exists.
+  template <int RT>
+  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+                                      const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
+                                      double* zz_lds) {
+    constexpr int KL = LAST;
+    const uint64_t tile_base = pdep64(tile, S.fixmask);
+    if (pg.flags & F_INIT) {
+      init_at<KL>(S, cx.amp);
+      lam_live = false;
+    } else if (io) {
+      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
+      lam_live = (pg.flags & F_LAM_LIVE) != 0;
+      if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
+        load_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
+        if (sc.fix_lam) {
+          const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const V x = a[NS - 1][r];
+            a[NS - 1][r] = mkv<R>(x.x * fr - x.y * fi, x.x * fi + x.y * fr);
+          }
+        }
+      }
+    }
+    const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
+    ops_at<KL>(pg.pre_ops, make_lam, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    bool at_p = false;
+    if (pg.mixA_dir) {
+      R wcur = R(1), gs = R(0);
+      uint32_t todo = S.act;
+      mix_fwd<RT>(todo, (R)sc.kA, (R)sc.wA, wcur, pg.mixA_grad != 0, gs, lds_x);
+      acc.ba += (double)gs;
+      at_p = true;
+    }
+    if ((pg.mid_ops || pg.mixB_dir) && !at_p) {
+      xchg<KL, P>(lds_x);
+      at_p = true;
+    }
+    ops_at<P>(pg.mid_ops, make_lam, S, tile_base, sc.F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
+    if (pg.mixB_dir) {
+      R wcur = R(1), gs = R(0);
+      uint32_t todo = S.act;
+      mix_bwd<RT>(todo, (R)sc.kB, (R)sc.wB, wcur, pg.mixB_grad != 0, gs, lds_x);
+      acc.bb += (double)gs;
+      at_p = false;
+    }
+    const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
+    const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
+    if ((st_psi || st_lam) && at_p) xchg<P, KL>(lds_x);
+    if (st_psi) store_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
+    if (st_lam) store_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
+  }
+  __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+                                          const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,
+                                          Acc& acc, double* zz_lds) {
+    if (S.route == ROUTE_HIGH)
+      run<ROUTE_HIGH>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
+    else
+      run<ROUTE_FULL>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
+  }
+};
+
+// ---------------------------------------------------------------------------------
+// workgroup reduction of a few doubles; result valid in thread 0
+template <int N, int NT> __device__ __forceinline__ void block_sum(double (&v)[N], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[wave * N + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w * N + i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// phase-table multipliers of one position into LDS: exp(-i gamma_l c) (conjugated for
+// the inverse gate) times the complex scale correction rho
+template <class R>
+__device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename Cx<R>::V* tab, int layer, int cmax,
+                                         bool conj, const double* rho) {
+  if (layer < 0) return;
+  const typename Cx<R>::V* src = tab + (size_t)layer * (cmax + 1);
+  const double rr = rho[0], ri = rho[1];
+  for (int c = threadIdx.x; c <= cmax; c += blockDim.x) {
+    const double tr = (double)src[c].x, ti = conj ? -(double)src[c].y : (double)src[c].y;
+    ltab[c] = mkv<R>((R)(tr * rr - ti * ri), (R)(tr * ri + ti * rr));
+  }
+}
+
+// apply a sweep's scale corrections to the per-thread sums
+__device__ __forceinline__ void scale_acc(Acc& acc, const SweepProg& pg, const SwScale& sc) {
+  const double se = (pg.pre_ops & OP_ENERGY) ? sc.s_pre : sc.s_mid;
+  acc.e *= se;
+  acc.nrm *= se;
+  acc.gpre *= sc.s_pre;
+  acc.gmid *= sc.s_mid;
+  acc.ba *= sc.s_A;
+  acc.bb *= sc.s_B;
+}
+
+// Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
+
+// ---------------------------------------------------------------------------------
+// One sweep of a large state: one workgroup per tile.
+template <class R> struct SweepArgs {
+  typename Cx<R>::V* psi;
+  typename Cx<R>::V* lam;
+  const GraphDev* g;
+  const int4* terms;
+  const typename Cx<R>::V* tab;
+  const SwScale* scale;  // this sweep's scale record
+  double* partial;       // [nslot][ntiles]
+  int nslot;
+  int T;
+  int cmax;
+  R amp;
+  SetSpec set;
+  SweepProg prog;
+};
+
+#define AAQ_TILE_BOUNDS __launch_bounds__(1 << (LT - kRegBits))
+
+// One workgroup per tile; partial sums per tile: partial[slot][tile].
+template <class R, int NS, bool PT, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
+  using G = Geo<R, LT>;
+  using V = typename G::V;
+  __shared__ V lds_x[lds_slot(G::TILE)];
+  __shared__ double red[(G::NT / 64) * 6];
+  __shared__ double zz[PT ? kMaxT : 1];
+  extern __shared__ unsigned char dyn_lds[];  // two phase tables of cmax+1 entries
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + (A.cmax + 1);
+  const SwScale& sc = *A.scale;
+  if (A.prog.pre_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax, (A.prog.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+  if (A.prog.mid_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax, (A.prog.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  if (PT)
+    for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
+  __syncthreads();
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax};
+  Tile<R, NS, EN, LT> tl;
+  Acc acc;
+  acc.zero();
+  const uint32_t tile = blockIdx.x;
+  tl.template run<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  scale_acc(acc, A.prog, sc);
+  double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+  block_sum<6, G::NT>(v, red);
+  const uint32_t nt = A.set.ntiles;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) A.partial[(size_t)i * nt + tile] = v[i];
+  }
+  if (PT) {
+    __syncthreads();
+    const double se = (A.prog.pre_ops & OP_ENERGY) ? sc.s_pre : sc.s_mid;
+    for (int t = threadIdx.x; t < A.T; t += G::NT) A.partial[(size_t)(SLOT_TERMS + t) * nt + tile] = se * zz[t];
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Batched units: each workgroup takes the next unit from a counter and runs all of
+// its sweeps.  Units with n <= L keep their state in registers; larger units sweep
+// tile by tile over their own slice of the workspace.
+template <class R> struct UnitArgs {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* order;      // unit indices in processing order
+  unsigned char* ws;         // workspace base (graphs, terms, tables, states)
+  const double* params;      // [rows][2p] (only used by the table kernel)
+  double* out;               // [rows][2 + 2p]
+  int32_t* counter;
+  int count;
+  int out_stride;
+  int tabmax;                 // max cmax+1 over the units (dynamic LDS sizing)
+  typename Cx<R>::V* psi_io;  // optional external state for single-unit calls (n <= L): final psi store
+};
+
+template <class R> __device__ __forceinline__ const SwScale* unit_scales(const unsigned char* ws, const UnitDesc* D) {
+  const size_t amp = sizeof(typename Cx<R>::V);
+  return reinterpret_cast<const SwScale*>(ws + D->tab_off + amp * (size_t)D->p * (D->cmax + 1));
+}
+
+template <class R, int NS, int LT> __global__ AAQ_TILE_BOUNDS void k_units(UnitArgs<R> A) {
+  using G = Geo<R, LT>;
+  using V = typename G::V;
+  __shared__ V lds_x[lds_slot(G::TILE)];
+  __shared__ double red[(G::NT / 64) * 6];
+  __shared__ double outacc[2 + 2 * kMaxP];
+  __shared__ int s_idx;
+  extern __shared__ unsigned char dyn_lds[];  // two phase tables of up to A.tabmax entries
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + A.tabmax;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(A.counter, 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+    if (idx >= A.count) break;
+    const int u = __builtin_amdgcn_readfirstlane(A.order[idx]);
+    const UnitDesc* D = A.units + u;
+    const int p = D->p;
+    for (int i = threadIdx.x; i < 2 + 2 * p; i += G::NT) outacc[i] = 0.0;
+    const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
+    const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
+    const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
+    const SwScale* scales = unit_scales<R>(A.ws, D);
+    const bool big = D->state_off >= 0;
+    V* psi = big ? reinterpret_cast<V*>(A.ws + D->state_off) : A.psi_io;
+    V* lam = big ? psi + ((size_t)1 << D->n) : nullptr;
+    Ctx<R> cx{g, terms, tab, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+    Tile<R, NS, true, LT> tl;
+    tl.lam_live = false;
+    const int ns = D->nsweep;
+    for (int si = 0; si < ns; ++si) {
+      const SweepProg pg = A.progs[D->prog_off + si];
+      const SetSpec& S = D->sets[pg.set];
+      const SwScale& sc = scales[si];
+      __syncthreads();  // previous sweep's table readers are done
+      if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+        load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+      if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+        load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+      __syncthreads();
+      Acc acc;
+      acc.zero();
+      const uint32_t nt = big ? S.ntiles : 1u;
+      for (uint32_t t = 0; t < nt; ++t) tl.run_any(pg, S, sc, t, cx, big, lds_x, ltab0, ltab1, acc, nullptr);
+      scale_acc(acc, pg, sc);
+      double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+      block_sum<6, G::NT>(v, red);
+      if (threadIdx.x == 0) {
+        if (pg.pre_ops & OP_ENERGY || pg.mid_ops & OP_ENERGY) {
+          outacc[0] += v[0];
+          outacc[1] += v[1];
+        }
+        if (NS == 2) {
+          if (pg.pre_ops & OP_GRADG) outacc[2 + pg.pre_layer] += 2.0 * v[2];
+          if (pg.mid_ops & OP_GRADG) outacc[2 + pg.mid_layer] += 2.0 * v[3];
+          if (pg.mixA_grad) outacc[2 + p + pg.mixA_layer] += 2.0 * v[4];
+          if (pg.mixB_grad) outacc[2 + p + pg.mixB_layer] += 2.0 * v[5];
+        }
+      }
+    }
+    __syncthreads();
+    double* o = A.out + (size_t)D->row * A.out_stride;
+    for (int i = threadIdx.x; i < 2 + 2 * p; i += G::NT) o[i] = outacc[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Batched sweeps for plan units larger than one tile: one launch per sweep step over
+// every tile of every unit of a group (units with the same program structure).  Block
+// (x, y) runs tile x of unit list[y]; blocks past the unit's tile count exit.
+template <class R> struct BatchArgs {
+  const UnitDesc* units;
+  const SweepProg* progs;
+  const int32_t* list;  // unit indices of the group
+  unsigned char* ws;
+  int step;
+  int tabmax;
+};
+
+template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS void k_bsweep(BatchArgs<R> A) {
+  using G = Geo<R, LT>;
+  using V = typename G::V;
+  __shared__ V lds_x[lds_slot(G::TILE)];
+  __shared__ double red[(G::NT / 64) * 6];
+  extern __shared__ unsigned char dyn_lds[];
+  const int u = A.list[blockIdx.y];
+  const UnitDesc* D = A.units + u;
+  const uint32_t tile = blockIdx.x;
+  if (tile >= (uint32_t)D->ntiles || A.step >= D->nsweep) return;
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + A.tabmax;
+  const int p = D->p;
+  const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
+  const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
+  const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
+  const SwScale& sc = unit_scales<R>(A.ws, D)[A.step];
+  const SweepProg pg = A.progs[D->prog_off + A.step];
+  const SetSpec& S = D->sets[pg.set];
+  if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+  if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  __syncthreads();
+  V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
+  V* lam = psi + ((size_t)1 << D->n);
+  Ctx<R> cx{g, terms, tab, psi, NS == 2 ? lam : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+  Tile<R, NS, EN, LT> tl;
+  Acc acc;
+  acc.zero();
+  tl.template run<RT>(pg, S, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, nullptr);
+  scale_acc(acc, pg, sc);
+  double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+  block_sum<6, G::NT>(v, red);
+  if (threadIdx.x == 0) {
+    double* part = reinterpret_cast<double*>(A.ws + D->part_off) + (size_t)A.step * 6 * D->ntiles;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) part[(size_t)i * D->ntiles + tile] = v[i];
+  }
+  (void)p;
+}
+
+// per-unit fixed-order sums of the batched sweeps' partials into d_out rows
+
+template <class R, int K, int LT>
+__global__ __launch_bounds__(1 << (LT - kRegBits)) void k_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, SetSpec S,
+                                                   int32_t* __restrict__ out) {
+  using G = Geo<R, LT>;
+  constexpr int KK = (K == 0) ? G::LAST : G::P;
+  const uint64_t tile_base = pdep64(blockIdx.x, S.fixmask);
+  Tile<R, 1, true, LT> tl;
+  const uint64_t zb = tl.template zbase<KK>(S, tile_base, 0ull);
+  int v[G::NR];
+  if (use_terms)
+    tl.template hvals<KK>(S, zb, terms, v);
+  else
+    tl.template cuts<KK>(S, zb, g, v);
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < G::NR; ++r) {
+    const uint32_t j = tidx<G::b0(KK), G::RB>(t, r);
+    if (j & S.dummy) continue;
+    uint64_t z = tile_base;
+    for (int b = 0; b < G::L; ++b)
+      if ((j >> b) & 1u) z |= (uint64_t)1 << S.pos[b];
+    out[z] = v[r];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Launch templates, instantiated once per (R, LT) by AAQ_INSTANTIATE_* in their own
+// translation units (see aaq_launch.h for the host-facing declarations).
+template <class R, int RT, int LT>
+static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t dyn, hipStream_t st) {
+  const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
+  const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
+  const dim3 grid(L.set.ntiles), blk(Geo<R, LT>::NT);
+  if (pt)
+    hipLaunchKernelGGL((k_sweep<R, 1, true, true, RT, LT>), grid, blk, dyn, st, A);
+  else if (L.two_states && en)
+    hipLaunchKernelGGL((k_sweep<R, 2, false, true, RT, LT>), grid, blk, dyn, st, A);
+  else if (L.two_states)
+    hipLaunchKernelGGL((k_sweep<R, 2, false, false, RT, LT>), grid, blk, dyn, st, A);
+  else if (en)
+    hipLaunchKernelGGL((k_sweep<R, 1, false, true, RT, LT>), grid, blk, dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_sweep<R, 1, false, false, RT, LT>), grid, blk, dyn, st, A);
+}
+
+template <class R, int LT> hipError_t sweep_launch_impl(const LaunchSweep& L, hipStream_t st) {
+  SweepArgs<R> A;
+  A.psi = reinterpret_cast<typename Cx<R>::V*>(L.psi);
+  A.lam = reinterpret_cast<typename Cx<R>::V*>(L.lam);
+  A.g = L.g;
+  A.terms = L.terms;
+  A.tab = reinterpret_cast<const typename Cx<R>::V*>(L.tab);
+  A.scale = L.scale;
+  A.partial = L.partial;
+  A.nslot = L.nslot;
+  A.T = L.T;
+  A.cmax = L.cmax;
+  A.amp = (R)L.amp;
+  A.set = L.set;
+  A.prog = L.prog;
+  const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);
+  if (L.set.route == ROUTE_HIGH)
+    sweep_launch_rt<R, ROUTE_HIGH, LT>(A, L, dyn, st);
+  else
+    sweep_launch_rt<R, ROUTE_FULL, LT>(A, L, dyn, st);
+  return hipGetLastError();
+}
+
+template <class R> UnitArgs<R> unit_args(const LaunchUnits& L) {
+  UnitArgs<R> A;
+  A.units = L.units;
+  A.progs = L.progs;
+  A.order = L.order;
+  A.ws = L.ws;
+  A.params = L.params;
+  A.out = L.out;
+  A.counter = L.counter;
+  A.count = L.count;
+  A.out_stride = L.out_stride;
+  A.tabmax = L.tabmax;
+  A.psi_io = reinterpret_cast<typename Cx<R>::V*>(L.psi_io);
+  return A;
+}
+
+template <class R, int LT> hipError_t units_launch_impl(const LaunchUnits& L, bool grad, int blocks, hipStream_t st) {
+  auto A = unit_args<R>(L);
+  const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)L.tabmax;
+  if (grad)
+    hipLaunchKernelGGL((k_units<R, 2, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_units<R, 1, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
+  return hipGetLastError();
+}
+
+template <class R, int NS, bool EN, int LT>
+static void bsweep_launch_t(const BatchArgs<R>& A, int route, dim3 grid, size_t dyn, hipStream_t st) {
+  if (route == ROUTE_HIGH)
+    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_HIGH, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
+  else
+    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_FULL, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
+}
+
+template <class R, int LT> hipError_t bsweep_launch_impl(const LaunchBatch& L, hipStream_t st) {
+  const dim3 grid(L.max_tiles, L.nlist);
+  BatchArgs<R> A{L.units, L.progs, L.list, L.ws, L.step, L.tabmax};
+  const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)L.tabmax;
+  if (L.two_states)
+    (L.energy ? bsweep_launch_t<R, 2, true, LT> : bsweep_launch_t<R, 2, false, LT>)(A, L.route, grid, dyn, st);
+  else
+    (L.energy ? bsweep_launch_t<R, 1, true, LT> : bsweep_launch_t<R, 1, false, LT>)(A, L.route, grid, dyn, st);
+  return hipGetLastError();
+}
+
+template <class R, int LT>
+hipError_t cuts_launch_impl(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
+                            int32_t* out, hipStream_t st) {
+  if (arr == 0)
+    hipLaunchKernelGGL((k_cuts<R, 0, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
+  else
+    hipLaunchKernelGGL((k_cuts<R, 1, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
+  return hipGetLastError();
+}
+
+}  // namespace aaq
+
+#define AAQ_INSTANTIATE_UNITS(R, LT, SUF)                                                                   \
+  namespace aaq {                                                                                           \
+  hipError_t launch_units_##SUF(const LaunchUnits& L, bool grad, int blocks, hipStream_t st) {              \
+    return units_launch_impl<R, LT>(L, grad, blocks, st);                                                   \
+  }                                                                                                         \
+  }
+#define AAQ_INSTANTIATE_SWEEPS(R, LT, SUF)                                                                  \
+  namespace aaq {                                                                                           \
+  hipError_t launch_sweep_##SUF(const LaunchSweep& L, hipStream_t st) { return sweep_launch_impl<R, LT>(L, st); } \
+  hipError_t launch_bsweep_##SUF(const LaunchBatch& L, hipStream_t st) { return bsweep_launch_impl<R, LT>(L, st); } \
+  hipError_t launch_cuts_##SUF(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr, \
+                               int32_t* out, hipStream_t st) {                                              \
+    return cuts_launch_impl<R, LT>(g, terms, T, use_terms, S, arr, out, st);                                \
+  }                                                                                                         \
+  }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -175,34 +176,69 @@ std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
   return t;
 }
 
+// Appends to `ext` (which starts with the plain term list) the term lists of set s
+// sorted for its load and phase arrangements (see SetSpec::toff).
+void add_term_lists(SetSpec& s, int L, const std::vector<int4>& terms, std::vector<int4>& ext) {
+  const int na = geo_na(L);
+  for (int ki = 0; ki < 2; ++ki) {
+    const int b0 = geo_b0(ki == 0 ? na - 1 : na - 2, L);
+    int regbit[64];
+    for (int v = 0; v < 64; ++v) regbit[v] = -1;
+    for (int b = 0; b < kRegBits; ++b)
+      if (s.pos[b0 + b] != kDummy) regbit[s.pos[b0 + b]] = b;
+    std::vector<int4> grp[6];
+    for (const int4& t : terms) {
+      const int ri = regbit[t.x], rj = regbit[t.y];
+      if (ri < 0 && rj < 0)
+        grp[0].push_back(t);
+      else if (ri >= 0 && rj >= 0)
+        grp[5].push_back(make_int4(t.x, t.y, t.z, ri | (rj << 4)));
+      else
+        grp[1 + (ri >= 0 ? ri : rj)].push_back(t);
+    }
+    s.toff[ki] = (uint16_t)ext.size();
+    for (int g = 0; g < 6; ++g) {
+      s.tcnt[ki][g] = (uint16_t)grp[g].size();
+      ext.insert(ext.end(), grp[g].begin(), grp[g].end());
+    }
+  }
+}
+
+// plain term list followed by every set's sorted lists (the device term array)
+std::vector<int4> term_array(const aaq_problem* pr, aaq_observable obs, int L, std::vector<SetSpec>& sets) {
+  std::vector<int4> terms = make_terms(pr, obs), ext = terms;
+  for (SetSpec& s : sets) add_term_lists(s, L, terms, ext);
+  return ext;
+}
+
 // ------------------------------------------------------------------ sweep planner
 // Split the n qubits into k tile sets.  Set 0 is a contiguous block of L global bits
 // (its low a_0 bits mixed); every later set mixes a_s <= L - 5 qubits and fills its
 // tile with the lowest remaining global bits, so that every tile holds global bits
 // 0..4 (>= 256 contiguous bytes per access).  k is the smallest possible, sizes as
 // even as the caps allow.
-// Register layouts ("arrangements"), L = 13 and 4 register bits per thread:
-// arrangement k keeps tile bits [b0(k), b0(k)+4) in registers, b0 = 0, 4, 8, 9.
-constexpr int kNA = 4, kRB = 4, kP = 2;
-uint32_t arr_regs(int k) { return 0xFu << (k == 3 ? 9 : 4 * k); }
+// Register layouts ("arrangements"): arrangement k keeps tile bits
+// [geo_b0(k, L), geo_b0(k, L) + 4) in registers (L = 13: b0 = 0, 4, 8, 9; L = 12:
+// 0, 4, 8; L = 10: 0, 4, 6).
 
 // Load arrangement, mixer route, active-qubit mask and register offsets of a set.
-// Every set loads and stores with the top tile bits in registers (arrangement 3, the
-// element offsets of its registers are tabulated).  Set 0 mixes along 3 -> 0 -> 1 -> 2;
-// the later sets hold only tile bits >= 5 active and skip arrangement 0: 3 -> 1 -> 2.
-void finish_set(SetSpec& s, int n, bool first) {
-  s.kl = 3;
-  s.route = first ? ROUTE_3012 : ROUTE_312;
+// Every set loads and stores with the top tile bits in registers (the last
+// arrangement; the element offsets of its registers are tabulated).  Set 0 mixes
+// through every arrangement; the later sets hold only tile bits >= 5 active and skip
+// arrangement 0.
+void finish_set(SetSpec& s, int L, bool first) {
+  const int last = geo_na(L) - 1, b0 = geo_b0(last, L);
+  s.kl = (uint8_t)last;
+  s.route = first ? ROUTE_FULL : ROUTE_HIGH;
   s.gact = 0;
   for (int j = 0; j < 16; ++j)
     if (((s.act >> j) & 1u) && s.pos[j] != kDummy) s.gact |= 1ull << s.pos[j];
   for (int r = 0; r < 16; ++r) {
     uint64_t o = 0;
-    for (int b = 0; b < kRB; ++b)
-      if (((r >> b) & 1) && s.pos[9 + b] != kDummy) o |= 1ull << s.pos[9 + b];
+    for (int b = 0; b < kRegBits; ++b)
+      if (((r >> b) & 1) && s.pos[b0 + b] != kDummy) o |= 1ull << s.pos[b0 + b];
     s.roff[r] = o;
   }
-  (void)n;
 }
 
 std::vector<SetSpec> make_sets(int n, int L) {
@@ -215,7 +251,7 @@ std::vector<SetSpec> make_sets(int n, int L) {
     s.dummy = ((1u << L) - 1u) & ~s.act;
     s.fixmask = 0;
     s.ntiles = 1;
-    finish_set(s, n, true);
+    finish_set(s, L, true);
     sets.push_back(s);
     return sets;
   }
@@ -263,10 +299,29 @@ std::vector<SetSpec> make_sets(int n, int L) {
     const uint64_t all = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     S.fixmask = all & ~tilemask;
     S.ntiles = 1u << (n - L);
-    finish_set(S, n, s == 0);
+    finish_set(S, L, s == 0);
     sets.push_back(S);
   }
   return sets;
+}
+
+// ------------------------------------------------------------------ tile size choice
+// Tile sizes (log2 amplitudes per workgroup tile) with compiled sweep kernels: 12
+// (256-thread workgroups) and 13 (512 threads).  Built-in rule: the fewest tile sets
+// (= sweeps per layer); on ties the 12-bit tile, whose workgroups are smaller (more of
+// them resident per compute unit) and whose mixer needs one LDS transpose fewer.
+int sets_for(int n, int L) { return (int)make_sets(n, L).size(); }
+int auto_tile_bits(int n) {
+  if (n <= 12) return 12;
+  return sets_for(n, 12) <= sets_for(n, 13) ? 12 : 13;
+}
+bool sweep_tile_ok(int L) { return L == 12 || L == 13; }
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;  // (n, complex128, gradient) -> tile bits
+int chosen_tile_bits(int n, bool dbl, bool grad) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(n, (int)dbl, (int)grad));
+  return it == g_tune.end() ? auto_tile_bits(n) : it->second;
 }
 
 int zig(int i, int k) {
@@ -435,6 +490,7 @@ struct Single {
   bool dbl, grad;
   aaq_aggregation agg;
   std::vector<SetSpec> sets;
+  std::vector<int4> terms;  // plain term list, then the per-set sorted lists
   std::vector<SweepProg> progs;
   std::vector<RedSrcHost> src;
   std::vector<int32_t> srcb;
@@ -445,7 +501,7 @@ struct Single {
 // grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
 // sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
 aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
-                       aaq_precision prec, Single& S, bool with_grids = false) {
+                       aaq_precision prec, int tile, Single& S, bool with_grids = false) {
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
     return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
@@ -458,8 +514,9 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.agg = agg;
   S.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
   S.cmax = pr->num_edges;
-  S.L = tile_bits(S.dbl);
+  S.L = tile;
   S.sets = make_sets(S.n, S.L);
+  S.terms = term_array(pr, obs, S.L, S.sets);
   S.k = (int)S.sets.size();
   uint8_t eops = OP_ENERGY | (agg == AAQ_AGG_PER_TERM ? OP_PERTERM : 0);
   S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM);
@@ -493,7 +550,7 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   L.graph = off;
   off = align_up(off + sizeof(GraphDev));
   L.terms = off;
-  off = align_up(off + sizeof(int4) * std::max(S.T, 1));
+  off = align_up(off + sizeof(int4) * std::max<size_t>(S.terms.size(), 1));
   L.params = off;
   off = align_up(off + sizeof(double) * 2 * p);
   // the zz-pass partial area starts after the sweep partials
@@ -532,13 +589,15 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
 
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
-                      void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res) {
+                      void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
+                      int tile = 0) {
   aaq_status st = validate_problem(pr);
   if (st) return st;
   if ((st = validate_p(p))) return st;
   if ((st = validate_params(p, gamma, beta))) return st;
   Single S;
-  if ((st = plan_single(pr, p, grad, obs, agg, prec, S, true))) return st;
+  if (!tile) tile = chosen_tile_bits(pr->n, prec == AAQ_PREC_C128, grad);
+  if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, S, true))) return st;
   const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
   if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
   if (state_bytes < need_state) return fail(AAQ_ERR_BUFFER, "state buffer smaller than 2^n amplitudes");
@@ -554,7 +613,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   // host staging of everything that is uploaded
   std::vector<unsigned char> up(L.upload_end, 0);
   GraphDev g = make_graph(pr);
-  std::vector<int4> terms = make_terms(pr, obs);
+  const std::vector<int4>& terms = S.terms;
   g.T = S.T;
   g.h_is_cut = obs == AAQ_OBS_HC;
   std::memcpy(up.data() + L.graph, &g, sizeof(g));
@@ -593,7 +652,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
                       !!(pg.flags & F_STORE_LAM);
     TimedLaunch tl(A.two_states ? KC_SWEEP2 : KC_SWEEP1, (double)moves * (double)need_state, hs);
-    HIPCHK(launch_sweep(A, S.dbl, hs));
+    HIPCHK(launch_sweep(A, S.dbl, S.L, hs));
     tl.done();
   }
   if (agg == AAQ_AGG_PASS_PER_TERM) {
@@ -634,12 +693,19 @@ struct aaq_plan {
   aaq_plan_opts opts;
   unsigned char* ws = nullptr;
   size_t ws_bytes = 0;
-  size_t units_off = 0, progs_off = 0, order_off = 0, counter_off = 0;
-  int blocks = 0;
+  size_t units_off = 0, progs_off = 0, counter_off = 0;
   int tabmax = 1;
-  int nsmall = 0;  // units run by the persistent kernel (state in one tile)
+  // units whose state fits one tile: one persistent launch per tile size
+  struct Small {
+    int L;
+    size_t order_off;  // device int32 list of unit indices, largest n first
+    int count, blocks, counter;
+  };
+  std::vector<Small> small;
+  // larger units: batched sweeps, one group per (tile size, tile-set count)
   struct Group {
-    size_t list_off;          // device int32 list of unit indices
+    int L;
+    size_t list_off;  // device int32 list of unit indices
     int nlist, max_tiles, nsweep;
     std::vector<SweepProg> progs;  // the group's common program (for launch shapes)
     std::vector<uint8_t> routes;   // route of the set of each step
@@ -655,23 +721,48 @@ struct aaq_plan {
 
 namespace {
 
+constexpr int kUnitTiles[3] = {10, 12, 13};  // tile sizes of the persistent unit kernel
+constexpr int kMaxUnitTile = 13;
+constexpr int kNumCounters = 4;
+
 struct PlanLayout {
   size_t units = 0, progs = 0, order = 0, counter = 0, lists = 0, graphs = 0, total = 0;
   std::vector<UnitDesc> ud;
   std::vector<SweepProg> progs_v;
-  std::vector<int32_t> order_v;       // small units (n <= L), largest first
-  std::vector<std::vector<int32_t>> group_units;  // large units grouped by tile-set count
+  std::vector<std::pair<int, std::vector<int32_t>>> small;        // (tile bits, units)
+  std::vector<std::pair<int, std::vector<int32_t>>> group_units;  // (tile bits, units of one tile-set count)
   std::vector<unsigned char> blob;  // graphs + terms (uploaded), offsets relative to `graphs`
 };
+
+// tile size of a unit under the plan options
+int unit_tile_bits(int n, const aaq_plan_opts& o) {
+  if (n <= kMaxUnitTile) {
+    const int lo = std::max(n, o.min_tile_bits_small > 0 ? o.min_tile_bits_small : kUnitTiles[0]);
+    for (int L : kUnitTiles)
+      if (L >= lo) return L;
+    return kMaxUnitTile;
+  }
+  return o.tile_bits_large > 0 ? o.tile_bits_large : auto_tile_bits(n);
+}
+
+aaq_status check_opts(const aaq_plan_opts& o) {
+  if (o.prec != AAQ_PREC_C64 && o.prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  if (o.tile_bits_large != 0 && !sweep_tile_ok(o.tile_bits_large))
+    return fail(AAQ_ERR_INVALID_ARG, "tile_bits_large must be 0, 12 or 13");
+  if (o.min_tile_bits_small < 0 || o.min_tile_bits_small > kMaxUnitTile)
+    return fail(AAQ_ERR_INVALID_ARG, "min_tile_bits_small must be in 0..13");
+  if (o.workgroups < 0) return fail(AAQ_ERR_INVALID_ARG, "workgroups must be >= 0");
+  return AAQ_OK;
+}
 
 aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observable obs, bool grad, const aaq_plan_opts& o,
                        PlanLayout& PL) {
   if (!probs || count < 1) return fail(AAQ_ERR_INVALID_ARG, "probs is NULL or count < 1");
   aaq_status st = validate_p(p);
   if (st) return st;
+  if ((st = check_opts(o))) return st;
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   const bool dbl = o.prec == AAQ_PREC_C128;
-  const int L = tile_bits(dbl);
   const size_t amp = dbl ? 16 : 8;
   for (int i = 0; i < count; ++i) {
     if ((st = validate_problem(&probs[i]))) {
@@ -679,8 +770,12 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
       return st;
     }
   }
-  // shared graph blocks: identical instance arrays are stored once
-  std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*>, std::pair<int64_t, int64_t>> gmap;
+  // shared graph blocks: identical instance arrays (at the same tile size) are stored once
+  struct GraphEntry {
+    int64_t goff, toff;
+    std::vector<SetSpec> sets;
+  };
+  std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*, int>, GraphEntry> gmap;
   PL.ud.assign(count, UnitDesc{});
   PL.blob.clear();
   std::vector<std::vector<SweepProg>> progs(count);
@@ -693,24 +788,26 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.row = i;
     D.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
     D.cmax = pr->num_edges;
-    auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size);
+    D.L = unit_tile_bits(pr->n, o);
+    auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size, (int)D.L);
     auto it = gmap.find(key);
     if (it == gmap.end()) {
       GraphDev g = make_graph(pr);
       g.T = D.T;
       g.h_is_cut = obs == AAQ_OBS_HC;
-      std::vector<int4> t = make_terms(pr, obs);
+      std::vector<SetSpec> sets = make_sets(pr->n, D.L);
+      std::vector<int4> t = term_array(pr, obs, D.L, sets);
       int64_t goff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(GraphDev)));
       std::memcpy(PL.blob.data() + goff, &g, sizeof(g));
       int64_t toff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(int4) * std::max<size_t>(t.size(), 1)));
       if (!t.empty()) std::memcpy(PL.blob.data() + toff, t.data(), sizeof(int4) * t.size());
-      it = gmap.emplace(key, std::make_pair(goff, toff)).first;
+      it = gmap.emplace(key, GraphEntry{goff, toff, sets}).first;
     }
-    D.graph_off = it->second.first;  // relative to the graph area; fixed up below
-    D.terms_off = it->second.second;
-    std::vector<SetSpec> sets = make_sets(pr->n, L);
+    D.graph_off = it->second.goff;  // relative to the graph area; fixed up below
+    D.terms_off = it->second.toff;
+    const std::vector<SetSpec>& sets = it->second.sets;
     D.nsets = (int)sets.size();
     for (int s = 0; s < D.nsets; ++s) D.sets[s] = sets[s];
     progs[i] = build_progs(D.nsets, p, grad, OP_ENERGY, false);
@@ -730,7 +827,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   PL.order = off;
   off = align_up(off + sizeof(int32_t) * count);
   PL.counter = off;
-  off = align_up(off + sizeof(int32_t));
+  off = align_up(off + sizeof(int32_t) * kNumCounters);
   PL.lists = off;
   off = align_up(off + sizeof(int32_t) * count);
   PL.graphs = off;
@@ -744,30 +841,33 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.tab_off = (int64_t)off;
     off = align_up(off + amp * (size_t)p * (D.cmax + 1) + sizeof(SwScale) * (D.nsweep + 1));
   }
-  std::map<int, std::vector<int32_t>> by_k;
+  std::map<std::pair<int, int>, std::vector<int32_t>> by_group;  // (tile bits, sets)
+  std::map<int, std::vector<int32_t>> by_small;                  // tile bits
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];
-    if (D.n > L) {
+    if (D.n > D.L) {
       D.state_off = (int64_t)off;
       off = align_up(off + amp * ((size_t)1 << D.n) * (grad ? 2 : 1));
-      D.ntiles = (int32_t)(1u << (D.n - L));
+      D.ntiles = (int32_t)(1u << (D.n - D.L));
       D.part_off = (int64_t)off;
       off = align_up(off + sizeof(double) * 6 * (size_t)D.nsweep * D.ntiles);
-      by_k[D.nsets].push_back(i);
+      by_group[std::make_pair((int)D.L, D.nsets)].push_back(i);
     } else {
       D.state_off = -1;
       D.ntiles = 1;
       D.part_off = -1;
+      by_small[D.L].push_back(i);
     }
   }
   PL.total = off;
-  PL.order_v.clear();
-  for (int i = 0; i < count; ++i)
-    if (PL.ud[i].n <= L) PL.order_v.push_back(i);
-  if (o.sort_units)
-    std::stable_sort(PL.order_v.begin(), PL.order_v.end(), [&](int a, int b) { return PL.ud[a].n > PL.ud[b].n; });
+  PL.small.clear();
+  for (auto& kv : by_small) {
+    std::vector<int32_t> v = kv.second;
+    if (o.sort_units) std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return PL.ud[a].n > PL.ud[b].n; });
+    PL.small.emplace_back(kv.first, v);
+  }
   PL.group_units.clear();
-  for (auto& kv : by_k) PL.group_units.push_back(kv.second);
+  for (auto& kv : by_group) PL.group_units.emplace_back(kv.first.first, kv.second);
   return AAQ_OK;
 }
 
@@ -775,7 +875,7 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
   LaunchUnits U;
   U.units = (const UnitDesc*)(P->ws + P->units_off);
   U.progs = (const SweepProg*)(P->ws + P->progs_off);
-  U.order = (const int32_t*)(P->ws + P->order_off);
+  U.order = nullptr;
   U.ws = P->ws;
   U.params = d_params;
   U.out = d_out;
@@ -786,13 +886,16 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
   U.psi_io = nullptr;
   {
     TimedLaunch tl(KC_TABLES, 0.0, hs);
-    HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));  // every unit; also resets the counter
+    HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));  // every unit; also resets the counters
     tl.done();
   }
-  if (P->nsmall > 0) {
-    U.count = P->nsmall;
+  for (const auto& sc : P->small) {
+    LaunchUnits V = U;
+    V.order = (const int32_t*)(P->ws + sc.order_off);
+    V.counter = (int32_t*)(P->ws + P->counter_off) + sc.counter;
+    V.count = sc.count;
     TimedLaunch tl(KC_UNITS, 0.0, hs);
-    HIPCHK(launch_units(U, P->grad, P->dbl, std::min(P->blocks, P->nsmall), hs));
+    HIPCHK(launch_units(V, P->grad, P->dbl, sc.L, sc.blocks, hs));
     tl.done();
   }
   for (const auto& Gp : P->groups) {
@@ -811,7 +914,7 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
       B.two_states = P->grad && needs_two_states(pg);
       B.energy = ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) != 0;
       TimedLaunch tl(B.two_states ? KC_SWEEP2 : KC_SWEEP1, 0.0, hs);
-      HIPCHK(launch_bsweep(B, P->dbl, hs));
+      HIPCHK(launch_bsweep(B, P->dbl, Gp.L, hs));
       tl.done();
     }
     TimedLaunch tl(KC_REDUCE, 0.0, hs);
@@ -865,9 +968,13 @@ aaq_status aaq_workspace_size(const aaq_problem* prob, int p, int with_grad, aaq
   if (s) return s;
   if ((s = validate_p(p))) return s;
   if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
-  Single S;
-  if ((s = plan_single(prob, p, with_grad != 0, obs, agg, prec, S))) return s;
-  *bytes = S.lay.total;
+  size_t mx = 0;
+  for (int tile : {12, 13}) {  // any tile choice fits
+    Single S;
+    if ((s = plan_single(prob, p, with_grad != 0, obs, agg, prec, tile, S))) return s;
+    mx = std::max(mx, S.lay.total);
+  }
+  *bytes = mx;
   return AAQ_OK;
 }
 
@@ -915,23 +1022,24 @@ aaq_status aaq_cut_values_layout(const aaq_problem* prob, aaq_observable obs, in
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
   const bool dbl = prec == AAQ_PREC_C128;
-  std::vector<SetSpec> sets = make_sets(prob->n, tile_bits(dbl));
+  const int tile = auto_tile_bits(prob->n);
+  std::vector<SetSpec> sets = make_sets(prob->n, tile);
   if (set_index < 0 || set_index >= (int)sets.size()) return fail(AAQ_ERR_INVALID_ARG, "set_index out of range");
   if (arrangement != 0 && arrangement != 1) return fail(AAQ_ERR_INVALID_ARG, "arrangement must be 0 or 1");
   const int T = (obs == AAQ_OBS_HC) ? prob->num_edges : prob->num_orbits;
-  const size_t need = align_up(sizeof(GraphDev)) + sizeof(int4) * std::max(T, 1);
-  if (ws_bytes < need) return fail(AAQ_ERR_BUFFER, "workspace too small for the graph block");
+  std::vector<int4> terms = term_array(prob, obs, tile, sets);
+  const size_t need = align_up(sizeof(GraphDev)) + sizeof(int4) * std::max<size_t>(terms.size(), 1);
+  if (ws_bytes < need) return fail(AAQ_ERR_BUFFER, "workspace too small for the graph block and term lists");
   std::vector<unsigned char> up(need, 0);
   GraphDev g = make_graph(prob);
   g.T = T;
-  std::vector<int4> terms = make_terms(prob, obs);
   std::memcpy(up.data(), &g, sizeof(g));
   if (!terms.empty()) std::memcpy(up.data() + align_up(sizeof(GraphDev)), terms.data(), sizeof(int4) * terms.size());
   hipStream_t hs = (hipStream_t)stream;
   unsigned char* ws = (unsigned char*)d_ws;
   HIPCHK(hipMemcpyAsync(ws, up.data(), need, hipMemcpyHostToDevice, hs));
   HIPCHK(launch_cuts((const GraphDev*)ws, (const int4*)(ws + align_up(sizeof(GraphDev))), T, obs == AAQ_OBS_HRED ? 1 : 0,
-                     sets[set_index], arrangement, d_out, dbl, hs));
+                     sets[set_index], arrangement, d_out, dbl, tile, hs));
   HIPCHK(hipStreamSynchronize(hs));
   return AAQ_OK;
 }
@@ -943,7 +1051,8 @@ aaq_status aaq_cut_values(const aaq_problem* prob, aaq_observable obs, void* d_w
 
 int aaq_num_sets(int n, aaq_precision prec) {
   if (n < 1 || n > AAQ_MAX_N) return 0;
-  return (int)make_sets(n, tile_bits(prec == AAQ_PREC_C128)).size();
+  (void)prec;
+  return sets_for(n, auto_tile_bits(n));
 }
 
 void aaq_plan_default_opts(aaq_plan_opts* o) {
@@ -952,6 +1061,8 @@ void aaq_plan_default_opts(aaq_plan_opts* o) {
   o->workgroups = 0;
   o->sort_units = 1;
   o->prec = AAQ_PREC_C64;
+  o->tile_bits_large = 0;
+  o->min_tile_bits_small = 0;
 }
 
 aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
@@ -973,7 +1084,6 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   aaq_plan_opts o;
   aaq_plan_default_opts(&o);
   if (opts) o = *opts;
-  if (o.prec != AAQ_PREC_C64 && o.prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
   PlanLayout PL;
   aaq_status s = plan_layout(probs, count, p, obs, with_grad != 0, o, PL);
   if (s) return s;
@@ -984,18 +1094,47 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   std::vector<unsigned char> up(PL.graphs + PL.blob.size(), 0);
   std::memcpy(up.data() + PL.units, PL.ud.data(), sizeof(UnitDesc) * count);
   if (!PL.progs_v.empty()) std::memcpy(up.data() + PL.progs, PL.progs_v.data(), sizeof(SweepProg) * PL.progs_v.size());
-  if (!PL.order_v.empty()) std::memcpy(up.data() + PL.order, PL.order_v.data(), sizeof(int32_t) * PL.order_v.size());
+  aaq_plan* P = new aaq_plan();
   {
+    size_t so = PL.order;
+    int ci = 0;
+    for (auto& sm : PL.small) {
+      std::memcpy(up.data() + so, sm.second.data(), sizeof(int32_t) * sm.second.size());
+      aaq_plan::Small c;
+      c.L = sm.first;
+      c.order_off = so;
+      c.count = (int)sm.second.size();
+      c.counter = ci++;
+      const int auto_blocks = 2 * device_cus() * (1 << (kMaxUnitTile - c.L));
+      c.blocks = std::min(c.count, o.workgroups > 0 ? o.workgroups : auto_blocks);
+      P->small.push_back(c);
+      so += sizeof(int32_t) * sm.second.size();
+    }
     size_t lo = PL.lists;
     for (auto& gl : PL.group_units) {
-      std::memcpy(up.data() + lo, gl.data(), sizeof(int32_t) * gl.size());
-      lo += sizeof(int32_t) * gl.size();
+      const std::vector<int32_t>& units = gl.second;
+      std::memcpy(up.data() + lo, units.data(), sizeof(int32_t) * units.size());
+      aaq_plan::Group Gp;
+      Gp.L = gl.first;
+      Gp.list_off = lo;
+      lo += sizeof(int32_t) * units.size();
+      Gp.nlist = (int)units.size();
+      Gp.max_tiles = 0;
+      for (int u : units) Gp.max_tiles = std::max(Gp.max_tiles, (int)PL.ud[u].ntiles);
+      const UnitDesc& D0 = PL.ud[units[0]];
+      Gp.nsweep = D0.nsweep;
+      Gp.progs.assign(PL.progs_v.begin() + D0.prog_off, PL.progs_v.begin() + D0.prog_off + D0.nsweep);
+      for (const SweepProg& pg : Gp.progs) Gp.routes.push_back(D0.sets[pg.set].route);
+      P->groups.push_back(Gp);
     }
   }
   if (!PL.blob.empty()) std::memcpy(up.data() + PL.graphs, PL.blob.data(), PL.blob.size());
-  HIPCHK(hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, hs));
-  HIPCHK(hipStreamSynchronize(hs));
-  aaq_plan* P = new aaq_plan();
+  hipError_t e = hipMemcpyAsync(ws, up.data(), up.size(), hipMemcpyHostToDevice, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(AAQ_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
   P->count = count;
   P->p = p;
   P->grad = with_grad != 0;
@@ -1005,28 +1144,8 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   P->ws_bytes = ws_bytes;
   P->units_off = PL.units;
   P->progs_off = PL.progs;
-  P->order_off = PL.order;
   P->counter_off = PL.counter;
   for (int i = 0; i < count; ++i) P->tabmax = std::max(P->tabmax, PL.ud[i].cmax + 1);
-  P->nsmall = (int)PL.order_v.size();
-  {
-    size_t lo = PL.lists;
-    for (auto& gl : PL.group_units) {
-      aaq_plan::Group Gp;
-      Gp.list_off = lo;
-      lo += sizeof(int32_t) * gl.size();
-      Gp.nlist = (int)gl.size();
-      Gp.max_tiles = 0;
-      for (int u : gl) Gp.max_tiles = std::max(Gp.max_tiles, (int)PL.ud[u].ntiles);
-      const UnitDesc& D0 = PL.ud[gl[0]];
-      Gp.nsweep = D0.nsweep;
-      Gp.progs.assign(PL.progs_v.begin() + D0.prog_off, PL.progs_v.begin() + D0.prog_off + D0.nsweep);
-      for (const SweepProg& pg : Gp.progs) Gp.routes.push_back(D0.sets[pg.set].route);
-      P->groups.push_back(Gp);
-    }
-  }
-  P->blocks = o.workgroups > 0 ? o.workgroups : 2 * device_cus();
-  if (P->blocks > count) P->blocks = count;
   *out = P;
   return AAQ_OK;
 }
@@ -1060,6 +1179,134 @@ aaq_status aaq_plan_execute(aaq_plan* P, const double* d_params, double* d_out, 
     P->g_stream = hs;
   }
   HIPCHK(hipGraphLaunch(P->exec, hs));
+  return AAQ_OK;
+}
+
+// ====================================================================== tuning
+aaq_status aaq_set_tile_bits(int n, aaq_precision prec, int with_grad, int tile_bits) {
+  if (n < 1 || n > AAQ_MAX_N) return fail(AAQ_ERR_INVALID_ARG, "n out of range");
+  if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");
+  if (tile_bits != 0 && !sweep_tile_ok(tile_bits)) return fail(AAQ_ERR_INVALID_ARG, "tile_bits must be 0, 12 or 13");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const auto key = std::make_tuple(n, (int)(prec == AAQ_PREC_C128), (int)(with_grad != 0));
+  if (tile_bits == 0)
+    g_tune.erase(key);
+  else
+    g_tune[key] = tile_bits;
+  return AAQ_OK;
+}
+
+int aaq_get_tile_bits(int n, aaq_precision prec, int with_grad) {
+  if (n < 1 || n > AAQ_MAX_N) return 0;
+  return chosen_tile_bits(n, prec == AAQ_PREC_C128, with_grad != 0);
+}
+
+aaq_status aaq_autotune(const aaq_problem* prob, int p, int with_grad, aaq_observable obs, aaq_precision prec,
+                        void* d_state, size_t state_bytes, void* d_lambda, size_t lambda_bytes, void* d_ws,
+                        size_t ws_bytes, void* stream, int reps, int* best_tile_bits, double* ms_per_call) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if ((s = validate_p(p))) return s;
+  if (reps < 1) return fail(AAQ_ERR_INVALID_ARG, "reps must be >= 1");
+  std::vector<double> gamma(p), beta(p), res;
+  for (int l = 0; l < p; ++l) {
+    gamma[l] = 0.4 + 0.1 * l;
+    beta[l] = 0.3 - 0.02 * l;
+  }
+  const bool grad = with_grad != 0;
+  const aaq_aggregation agg = AAQ_AGG_FUSED;
+  const int cand[2] = {12, 13};
+  double best = 0.0;
+  int bestL = 0;
+  for (int c = 0; c < 2; ++c) {
+    const int L = cand[c];
+    auto one = [&]() {
+      return run_single(prob, p, gamma.data(), beta.data(), obs, agg, prec, grad, d_state, state_bytes, d_lambda,
+                        lambda_bytes, d_ws, ws_bytes, stream, res, L);
+    };
+    if ((s = one())) return s;  // warm-up (and argument checks)
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < reps; ++r)
+      if ((s = one())) return s;
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / reps;
+    if (ms_per_call) ms_per_call[c] = ms;
+    if (bestL == 0 || ms < best) {
+      best = ms;
+      bestL = L;
+    }
+  }
+  if ((s = aaq_set_tile_bits(prob->n, prec, with_grad, bestL))) return s;
+  if (best_tile_bits) *best_tile_bits = bestL;
+  return AAQ_OK;
+}
+
+aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
+                             const aaq_plan_opts* base, void* d_ws, size_t ws_bytes, const double* d_params,
+                             double* d_out, void* stream, int reps, aaq_plan_opts* best, double* best_ms) {
+  if (!probs || count < 1 || !best) return fail(AAQ_ERR_INVALID_ARG, "probs / best is NULL or count < 1");
+  if (!d_ws || !d_params || !d_out) return fail(AAQ_ERR_INVALID_ARG, "d_ws / d_params / d_out is NULL");
+  if (reps < 1) return fail(AAQ_ERR_INVALID_ARG, "reps must be >= 1");
+  aaq_plan_opts b0;
+  aaq_plan_default_opts(&b0);
+  if (base) b0 = *base;
+  bool any_large = false, any_small = false, any_tiny = false;
+  for (int i = 0; i < count; ++i) {
+    if (probs[i].n > kMaxUnitTile) any_large = true;
+    else any_small = true;
+    if (probs[i].n <= 12) any_tiny = true;
+  }
+  std::vector<int> larges = any_large ? std::vector<int>{12, 13} : std::vector<int>{b0.tile_bits_large};
+  std::vector<int> smalls = any_tiny ? std::vector<int>{10, 12, 13} : std::vector<int>{b0.min_tile_bits_small};
+  std::vector<int> wgs = any_small ? std::vector<int>{0, device_cus(), 4 * device_cus()} : std::vector<int>{b0.workgroups};
+  hipStream_t hs = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(AAQ_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+  }
+  aaq_status st = AAQ_OK;
+  double bms = -1.0;
+  aaq_plan_opts bo = b0;
+  for (int tl : larges)
+    for (int ts : smalls)
+      for (int wg : wgs) {
+        aaq_plan_opts o = b0;
+        o.tile_bits_large = tl;
+        o.min_tile_bits_small = ts;
+        o.workgroups = wg;
+        size_t need = 0;
+        if ((st = aaq_plan_workspace_size(probs, count, p, obs, with_grad, &o, &need))) goto done;
+        if (need > ws_bytes) continue;  // this candidate does not fit the caller's workspace
+        aaq_plan* P = nullptr;
+        if ((st = aaq_plan_create(probs, count, p, obs, with_grad, &o, d_ws, ws_bytes, stream, &P))) goto done;
+        float ms = 0.0f;
+        st = aaq_plan_execute(P, d_params, d_out, stream);  // warm-up (captures the graph)
+        if (!st) {
+          hipError_t e = hipEventRecord(e0, hs);
+          for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = aaq_plan_execute(P, d_params, d_out, stream);
+          if (e == hipSuccess) e = hipEventRecord(e1, hs);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (!st && e != hipSuccess) st = fail(AAQ_ERR_HIP, std::string("tuning events: ") + hipGetErrorString(e));
+        }
+        aaq_plan_destroy(P);
+        if (st) goto done;
+        const double per = ms / reps;
+        if (bms < 0.0 || per < bms) {
+          bms = per;
+          bo = o;
+        }
+      }
+  if (bms < 0.0) st = fail(AAQ_ERR_BUFFER, "no candidate configuration fits the workspace");
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  *best = bo;
+  if (best_ms) *best_ms = bms;
   return AAQ_OK;
 }
 

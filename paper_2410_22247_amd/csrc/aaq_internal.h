@@ -1,9 +1,9 @@
 // Internal data structures shared by the host planner and the HIP kernels.
 //
 // State layout: amplitude z (vertex v = bit v of z) at element z of a flat array of
-// complex64 (float2) or complex128 (double2).  A "tile" is 2^L = 8192 amplitudes that
-// one 512-thread workgroup holds in registers (L = 13 for both precisions): tile bit j
-// is global index bit pos[j]; the remaining global bits are enumerated by the tile id
+// complex64 (float2) or complex128 (double2).  A "tile" is 2^L amplitudes that one
+// workgroup of 2^(L-4) threads holds in registers (L = 10, 12 or 13): tile bit j is
+// global index bit pos[j]; the remaining global bits are enumerated by the tile id
 // (ascending).  Tile bits always include global bits 0..4 so that every
 // global load/store touches >= 256 contiguous bytes.
 #pragma once
@@ -14,14 +14,22 @@ namespace aaq {
 constexpr int kMaxN = 34;
 constexpr int kMaxP = 64;
 constexpr int kMaxT = 34 * 33 / 2;  // max terms (complete graph on 34 vertices)
-constexpr int kMaxSets = 4;
-constexpr int kThreads = 512;
+constexpr int kMaxSets = 5;
 constexpr int kMinContig = 5;       // low global bits every tile must contain
 constexpr uint8_t kDummy = 0xFF;    // tile bit without a vertex (n < L)
+constexpr int kRegBits = 4;         // register bits per thread: 16 amplitudes
 
-// mixer routes through the register arrangements (load arrangement 3 first, phase
-// arrangement 2 last)
-enum : uint8_t { ROUTE_3012 = 0, ROUTE_312 = 1 };
+// Register arrangements of a tile of L bits: arrangement k keeps tile bits
+// [geo_b0(k), geo_b0(k) + 4) in registers; geo_na(L) arrangements, the last one (top
+// tile bits in registers) is used for global loads and stores, the one before it is
+// where phases and the energy are applied.
+constexpr int geo_na(int L) { return (L + kRegBits - 1) / kRegBits; }
+constexpr int geo_b0(int k, int L) { return (k * kRegBits < L - kRegBits) ? k * kRegBits : L - kRegBits; }
+
+// mixer routes through the register arrangements, from the load arrangement to the
+// phase arrangement: every arrangement, or all but arrangement 0 (sets whose active
+// qubits are all tile bits >= 4)
+enum : uint8_t { ROUTE_FULL = 0, ROUTE_HIGH = 1 };
 
 // per-position operations inside a sweep
 enum : uint8_t {
@@ -52,11 +60,18 @@ struct SetSpec {
   uint32_t dummy;    // tile-bit mask of dummy bits
   uint64_t fixmask;  // global bits enumerated by the tile id
   uint32_t ntiles;
-  uint8_t kl;         // load/store arrangement (3: register bits = the top tile bits)
-  uint8_t route;      // mixer route: ROUTE_3012 or ROUTE_312 (arrangements visited)
+  uint8_t kl;         // load/store arrangement (the last one: register bits = the top tile bits)
+  uint8_t route;      // mixer route: ROUTE_FULL or ROUTE_HIGH (arrangements visited)
   uint8_t pad[6];
   uint64_t gact;      // global bits of the active (mixed) qubits
   uint64_t roff[16];  // element offset of register r at the load/store arrangement
+  // Observable terms sorted for the two arrangements where h(z) is evaluated (index 0:
+  // load arrangement, 1: phase arrangement): first the terms with no endpoint among the
+  // register bits, then those with one endpoint at register bit 0, 1, 2, 3, then those
+  // with both endpoints in registers (int4 .w = ri | rj << 4).  toff is the offset in
+  // int4 entries from the start of the unit's term array, tcnt the six group sizes.
+  uint16_t toff[2];
+  uint16_t tcnt[2][6];
 };
 
 struct SweepProg {
@@ -114,7 +129,7 @@ struct UnitDesc {
   int32_t T, cmax;
   int64_t part_off;    // byte offset of the per-tile partial sums [nsweep][6][ntiles] (n > L units)
   int32_t ntiles;      // tiles per sweep
-  int32_t pad;
+  int32_t L;           // tile size (log2 amplitudes) of the unit's kernels
   SetSpec sets[kMaxSets];
 };
 

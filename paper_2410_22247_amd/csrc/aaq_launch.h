@@ -44,20 +44,39 @@ struct LaunchBatch {
   bool two_states, energy;
 };
 
-hipError_t launch_sweep(const LaunchSweep& L, bool dbl, hipStream_t st);
-hipError_t launch_bsweep(const LaunchBatch& L, bool dbl, hipStream_t st);
+// Tile sizes (log2 amplitudes per workgroup tile) with compiled kernels: sweeps and
+// cut dumps for 12 and 13, the persistent unit kernel also for 10.
+hipError_t launch_sweep(const LaunchSweep& L, bool dbl, int tile_bits, hipStream_t st);
+hipError_t launch_bsweep(const LaunchBatch& L, bool dbl, int tile_bits, hipStream_t st);
+hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int tile_bits, int blocks, hipStream_t st);
+hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
+                       int32_t* out, bool dbl, int tile_bits, hipStream_t st);
 hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st);
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
                          int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
-hipError_t launch_units(const LaunchUnits& L, bool grad, bool dbl, int blocks, hipStream_t st);
 hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
                          hipStream_t st);
 hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, const uint64_t* flips,
                           double* partial, int blocks, bool dbl, hipStream_t st);
-hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
-                       int32_t* out, bool dbl, hipStream_t st);
-int tile_bits(bool dbl);
+
+// per-instantiation entry points (defined by AAQ_INSTANTIATE_* in aaq_inst_*.hip)
+#define AAQ_DECLARE_UNITS(SUF) hipError_t launch_units_##SUF(const LaunchUnits& L, bool grad, int blocks, hipStream_t st);
+#define AAQ_DECLARE_SWEEPS(SUF)                                                                            \
+  hipError_t launch_sweep_##SUF(const LaunchSweep& L, hipStream_t st);                                     \
+  hipError_t launch_bsweep_##SUF(const LaunchBatch& L, hipStream_t st);                                    \
+  hipError_t launch_cuts_##SUF(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr, \
+                               int32_t* out, hipStream_t st);
+AAQ_DECLARE_UNITS(f10)
+AAQ_DECLARE_UNITS(f12)
+AAQ_DECLARE_UNITS(f13)
+AAQ_DECLARE_UNITS(d10)
+AAQ_DECLARE_UNITS(d12)
+AAQ_DECLARE_UNITS(d13)
+AAQ_DECLARE_SWEEPS(f12)
+AAQ_DECLARE_SWEEPS(f13)
+AAQ_DECLARE_SWEEPS(d12)
+AAQ_DECLARE_SWEEPS(d13)
 
 // RedSrc layout mirrored on the host
 struct RedSrcHost {

@@ -188,6 +188,51 @@ def test_energy_grad_n26_config3_point():
     check_energy(est.energy(gams[0], bets[0])[0], e_full)
 
 
+# ------------------------------------------------------------------ tile sizes and autotuning
+@pytest.mark.parametrize("g,p", [(G.prufer_tree(14, 2), 2), (G.star(17), 2), (G.prufer_tree(21, 3), 2),
+                                 (rand_graph(22, 0.15, 5), 1), (G.random_regular(3, 24, seed=4), 2)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_both_tile_sizes_match_oracle(g, p):
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(g.n + 100 * p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(OBS_HRED), gam, bet)
+    e_hc = O.energy(g.n, g.edge_array(), wp.terms(OBS_HC), gam, bet)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    try:
+        for tile in (12, 13):
+            A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, True, tile)
+            A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, False, tile)
+            assert A.aaq_get_tile_bits(g.n, A.AAQ_PREC_C64, True) == tile
+            e, dg, db, nrm = est.energy_grad(gam, bet)
+            check_energy(e, e_ref)
+            check_grad(np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref]))
+            assert abs(nrm - 1) < 1e-5
+            check_energy(est.energy(gam, bet, obs=OBS_HC)[0], e_hc)
+    finally:
+        A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, True, 0)
+        A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, False, 0)
+
+
+def test_autotune_single_keeps_a_tile_size_and_stays_correct():
+    g = G.prufer_tree(22, 9)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, 2, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    try:
+        best, ms = A.aaq_autotune(pr, 2, True, OBS_HRED, A.AAQ_PREC_C64, est.state, est.lam, est.ws, reps=2)
+        assert best in (12, 13) and ms[12] > 0 and ms[13] > 0
+        assert A.aaq_get_tile_bits(22, A.AAQ_PREC_C64, True) == best
+        gam, bet = np.array([0.3, 1.1]), np.array([0.9, 0.2])
+        e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(OBS_HRED), gam, bet)
+        e, dg, db, _ = est.energy_grad(gam, bet)
+        check_energy(e, e_ref)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref]))
+    finally:
+        A.aaq_set_tile_bits(22, A.AAQ_PREC_C64, True, 0)
+
+
 # ------------------------------------------------------------------ batched plans
 def test_plan_matches_single_calls_and_oracle():
     graphs = [G.star(7), G.complete(9), G.prufer_tree(12, 1), G.binary_tree(13), G.prufer_tree(15, 2),
@@ -242,6 +287,46 @@ def test_plan_groups_of_tile_sets(obs, grad):
                 e_ref = O.energy(w.n, w.edges(), w.terms(obs), gam[u], bet[u])
             check_energy(out[u, 0], e_ref)
             assert abs(out[u, 1] - 1) < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("tl,ts,wg", [(12, 10, 0), (13, 13, 0), (12, 12, 7), (13, 10, 1)])
+def test_plan_tile_options_match_oracle(tl, ts, wg):
+    graphs = [G.prufer_tree(9, 1), G.star(11), G.complete(12), G.binary_tree(13), G.prufer_tree(16, 2),
+              G.random_regular(3, 20, seed=5)]
+    wps = [make_problem(g) for g in graphs]
+    units = [A.Problem.from_workload(w) for w in wps] * 2
+    p = 2
+    rng = np.random.default_rng(tl * 100 + ts + wg)
+    gam = rng.uniform(0, math.pi, (len(units), p))
+    bet = rng.uniform(0, math.pi / 2, (len(units), p))
+    plan = A.Plan(units, p, OBS_HRED, with_grad=True, tile_bits_large=tl, min_tile_bits_small=ts, workgroups=wg)
+    plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
+    out = plan.execute().cpu().numpy()
+    for u in range(len(units)):
+        w = wps[u % len(wps)]
+        e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+        check_energy(out[u, 0], e_ref)
+        check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
+    plan.close()
+
+
+def test_plan_autotuned():
+    graphs = [G.prufer_tree(10, 3), G.star(12), G.prufer_tree(15, 4), G.random_regular(3, 16, seed=1)]
+    wps = [make_problem(g) for g in graphs]
+    units = [A.Problem.from_workload(w) for w in wps] * 4
+    p = 2
+    rng = np.random.default_rng(5)
+    prm = np.concatenate([rng.uniform(0, math.pi, (len(units), p)), rng.uniform(0, math.pi / 2, (len(units), p))], 1)
+    plan = A.Plan.autotuned(units, p, OBS_HRED, True, params=prm, reps=2)
+    assert plan.tuned_opts["tile_bits_large"] in (12, 13) and plan.tuned_ms > 0
+    plan.params.copy_(torch.from_numpy(prm))
+    out = plan.execute().cpu().numpy()
+    for u in range(len(units)):
+        w = wps[u % len(wps)]
+        e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), prm[u, :p], prm[u, p:])
+        check_energy(out[u, 0], e_ref)
+        check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
     plan.close()
 
 
