@@ -106,6 +106,9 @@ def main():
                     help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b"],
                     help="c3 (default): the n=26 p=4 energy+gradient headline; the others print their own line")
+    ap.add_argument("--grad-mode", default="checkpoint", choices=["checkpoint", "uncompute"],
+                    help="checkpoint: forward states kept in HBM, backward sweeps read them (default); "
+                         "uncompute: backward sweeps recompute psi in place (two state buffers)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files into profiles/traffic.json")
     args = ap.parse_args()
@@ -139,7 +142,7 @@ def main():
     wp, p, gams, bets = config3(32)
     pr = A.Problem.from_workload(wp)
     torch.cuda.set_device(0)
-    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=args.grad_mode == "checkpoint")
     stream = torch.cuda.current_stream()
 
     for k in range(args.warmup):
@@ -194,6 +197,8 @@ def main():
                         "complex64, 32 seeded (gamma, beta) points cycled",
             "n": 26, "p": 4, "observable": "H_red", "edges": int(wp.m), "orbits": int(wp.orbits.count),
             "tile_sets": A.aaq_num_sets(26),
+            "tile_bits": A.aaq_get_tile_bits(26, A.AAQ_PREC_C64, True),
+            "gradient_mode": args.grad_mode,
         },
         "roofline": {
             "bound": "hbm",

@@ -129,6 +129,20 @@ aaq_status aaq_energy_grad(const aaq_problem *prob, int p, const double *gamma, 
                            void *d_lambda, size_t lambda_bytes, void *d_ws, size_t ws_bytes, void *stream,
                            double *energy_out, double *dgamma_out, double *dbeta_out, double *norm_out);
 
+/* Forward-state checkpoints (memory for bandwidth): aaq_energy_grad_checkpointed computes
+ * the same energy and gradient as aaq_energy_grad (up to floating-point summation order),
+ * but every forward sweep keeps its output state in its own slot of d_ckpt, so each
+ * backward sweep reads psi from there instead of uncomputing it and writing it back: one
+ * state pass fewer per backward sweep.  d_ckpt needs aaq_checkpoint_bytes (a few states;
+ * 8 x 512 MiB at n = 26, p = 4); d_lambda, d_ws and the outputs are as for
+ * aaq_energy_grad.  Problems whose state is one tile (n <= 13) need one state. */
+aaq_status aaq_checkpoint_bytes(const aaq_problem *prob, int p, aaq_precision prec, size_t *bytes);
+aaq_status aaq_energy_grad_checkpointed(const aaq_problem *prob, int p, const double *gamma, const double *beta,
+                                        aaq_observable obs, aaq_precision prec, void *d_ckpt, size_t ckpt_bytes,
+                                        void *d_lambda, size_t lambda_bytes, void *d_ws, size_t ws_bytes,
+                                        void *stream, double *energy_out, double *dgamma_out, double *dbeta_out,
+                                        double *norm_out);
+
 /* Exact integer values of the observable's diagonal for every z in [0, 2^n):
  * C(z) for AAQ_OBS_HC, h_red(z) = sum_m |S_m| [z_{i_m} != z_{j_m}] for AAQ_OBS_HRED
  * (the diagonal of H_C and H_red without the 1/2 (1 - ZZ) rewriting), computed by the

@@ -10,5 +10,5 @@ from .api import (  # noqa: F401
     AAQError, Problem, aaq_cut_values, aaq_cut_values_layout, aaq_energy, aaq_energy_grad, aaq_num_sets,
     aaq_plan_create, aaq_plan_destroy, aaq_plan_execute, aaq_plan_workspace_size, aaq_state_bytes, aaq_validate,
     aaq_version, aaq_workspace_size, aaq_timing_enable, aaq_timing_read, aaq_set_tile_bits, aaq_get_tile_bits,
-    aaq_autotune, aaq_plan_autotune, Estimator, Plan,
+    aaq_autotune, aaq_plan_autotune, aaq_checkpoint_bytes, aaq_energy_grad_checkpointed, Estimator, Plan,
 )

@@ -45,7 +45,7 @@ EXPORTS = (
     "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
     "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
     "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
-    "aaq_plan_autotune",
+    "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed",
 )
 
 
@@ -82,6 +82,8 @@ def lib():
         "aaq_timing_enable": (i, [i]),
         "aaq_timing_read": (i, [ctypes.POINTER(CKernelTiming), i, ctypes.POINTER(i), i]),
         "aaq_set_tile_bits": (i, [i, i, i, i]),
+        "aaq_checkpoint_bytes": (i, [P, i, i, szp]),
+        "aaq_energy_grad_checkpointed": (i, [P, i, dp, dp, i, i, vp, sz, vp, sz, vp, sz, vp, dp, dp, dp, dp]),
         "aaq_get_tile_bits": (i, [i, i, i]),
         "aaq_autotune": (i, [P, i, i, i, i, vp, sz, vp, sz, vp, sz, vp, i, ctypes.POINTER(i), dp]),
         "aaq_plan_autotune": (i, [P, i, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, vp, vp, i,

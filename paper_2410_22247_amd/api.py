@@ -161,6 +161,28 @@ def aaq_energy_grad(prob: Problem, gamma, beta, obs: int, prec: int, d_state, d_
     return e.value, dg, db, nrm.value
 
 
+def aaq_checkpoint_bytes(prob: Problem, p: int, prec: int = AAQ_PREC_C64) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_checkpoint_bytes(prob.ref(), int(p), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def aaq_energy_grad_checkpointed(prob: Problem, gamma, beta, obs: int, prec: int, d_ckpt, d_lambda, d_ws,
+                                 stream=None):
+    """aaq_energy_grad with forward-state checkpoints in d_ckpt; returns (energy, dE/dgamma, dE/dbeta, norm)."""
+    g, b = _params(gamma, beta)
+    p = g.size
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    dg, db = np.zeros(p), np.zeros(p)
+    cp, cb = _dev(d_ckpt)
+    lp, lb = _dev(d_lambda)
+    wp, wb = _dev(d_ws)
+    _check(_lib.lib().aaq_energy_grad_checkpointed(prob.ref(), p, _dp(g), _dp(b), int(obs), int(prec), cp, cb, lp, lb,
+                                                   wp, wb, _stream(stream), ctypes.byref(e), _dp(dg), _dp(db),
+                                                   ctypes.byref(nrm)))
+    return e.value, dg, db, nrm.value
+
+
 def aaq_cut_values(prob: Problem, obs: int, d_ws, d_out, stream=None) -> None:
     wp, wb = _dev(d_ws)
     op, _ = _dev(d_out)
@@ -286,11 +308,16 @@ class Estimator:
     """Owns the device buffers (torch) for repeated evaluations of one instance."""
 
     def __init__(self, prob: Problem, p: int, obs: int = AAQ_OBS_HRED, prec: int = AAQ_PREC_C64, grad: bool = True,
-                 agg: int = AAQ_AGG_FUSED, device: str = "cuda"):
+                 agg: int = AAQ_AGG_FUSED, device: str = "cuda", checkpoint: bool = False):
+        """checkpoint=True: gradients use aaq_energy_grad_checkpointed (the state buffer then
+        holds the forward states, aaq_checkpoint_bytes)."""
         import torch
 
         self.prob, self.p, self.obs, self.prec, self.agg = prob, int(p), obs, prec, agg
+        self.checkpoint = bool(checkpoint and grad)
         sb = aaq_state_bytes(prob, prec)
+        if self.checkpoint:
+            sb = max(sb, aaq_checkpoint_bytes(prob, p, prec))
         # large enough for either observable, so one Estimator serves H_C and H_red
         wb = max(max(aaq_workspace_size(prob, p, grad, o, AAQ_AGG_FUSED, prec),
                      aaq_workspace_size(prob, p, False, o, agg, prec)) for o in (AAQ_OBS_HC, AAQ_OBS_HRED))
@@ -305,6 +332,9 @@ class Estimator:
     def energy_grad(self, gamma, beta, obs: Optional[int] = None, stream=None):
         if self.lam is None:
             raise ValueError("Estimator was built without gradient buffers")
+        if self.checkpoint:
+            return aaq_energy_grad_checkpointed(self.prob, gamma, beta, self.obs if obs is None else obs, self.prec,
+                                                self.state, self.lam, self.ws, stream)
         return aaq_energy_grad(self.prob, gamma, beta, self.obs if obs is None else obs, self.prec, self.state,
                                self.lam, self.ws, stream)
 

@@ -114,6 +114,7 @@ template <class R> struct Ctx {
   R amp;           // 2^{-n/2}
   int T;
   int cmax;
+  uint64_t N = 0;  // amplitudes per state (stride between checkpoint buffers)
 };
 
 // Per-thread accumulators for one sweep.
@@ -468,7 +469,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
+      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N + tile_base + thread_off<KL>(S), S);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
         load_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
@@ -507,7 +508,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
     if ((st_psi || st_lam) && at_p) xchg<P, KL>(lds_x);
-    if (st_psi) store_all<KL>(0, cx.psi + tile_base + thread_off<KL>(S), S);
+    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N + tile_base + thread_off<KL>(S), S);
     if (st_lam) store_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
   }
   __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
@@ -583,6 +584,7 @@ template <class R> struct SweepArgs {
   int T;
   int cmax;
   R amp;
+  uint64_t N;  // amplitudes per state
   SetSpec set;
   SweepProg prog;
 };
@@ -607,7 +609,7 @@ template <class R, int NS, bool PT, bool EN, int RT, int LT> __global__ AAQ_TILE
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax};
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
@@ -833,6 +835,7 @@ template <class R, int LT> hipError_t sweep_launch_impl(const LaunchSweep& L, hi
   A.T = L.T;
   A.cmax = L.cmax;
   A.amp = (R)L.amp;
+  A.N = L.N;
   A.set = L.set;
   A.prog = L.prog;
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);

@@ -346,7 +346,7 @@ SweepProg blank() {
 //  part on both states; the backward sweeps mirror the forward ones.
 //  single set (k == 1): the whole state is one tile; a sweep strings together
 //  [ops, mixer, ops, mixer] and the program is the plain gate sequence.
-std::vector<SweepProg> build_progs(int k, int p, bool grad, uint8_t energy_ops, bool store_final) {
+std::vector<SweepProg> build_progs(int k, int p, bool grad, uint8_t energy_ops, bool store_final, bool ckpt = false) {
   std::vector<SweepProg> out;
   if (k == 1) {
     struct Step {
@@ -469,7 +469,31 @@ std::vector<SweepProg> build_progs(int k, int p, bool grad, uint8_t energy_ops, 
       out.push_back(s);
     }
   }
+  if (ckpt && grad) {
+    // forward-state checkpoints: forward sweep i (< F - 1) stores psi into buffer i and
+    // sweep i + 1 reads it; backward sweep i reads psi from buffer i and stores only
+    // lambda, since the state before it is already in buffer i - 1
+    for (int i = 0; i < F; ++i) {
+      out[i].ld_buf = (uint8_t)(i > 0 ? i - 1 : 0);
+      out[i].st_buf = (uint8_t)i;
+    }
+    for (int j = F; j < (int)out.size(); ++j) {
+      const int i = F - 2 - (j - F);
+      out[j].ld_buf = (uint8_t)i;
+      out[j].flags &= (uint8_t)~F_STORE_PSI;
+    }
+  }
   return out;
+}
+
+// number of psi buffers a program reads or writes
+int prog_buffers(const std::vector<SweepProg>& progs) {
+  int nb = 1;
+  for (const SweepProg& s : progs) {
+    if (s.flags & F_LOAD_PSI) nb = std::max(nb, s.ld_buf + 1);
+    if (s.flags & F_STORE_PSI) nb = std::max(nb, s.st_buf + 1);
+  }
+  return nb;
 }
 
 bool needs_two_states(const SweepProg& s) {
@@ -479,14 +503,14 @@ bool needs_two_states(const SweepProg& s) {
 // ------------------------------------------------------------------ single-instance layout
 struct Layout {
   size_t graph = 0, terms = 0, params = 0, src = 0, srcb = 0, progs = 0, sets = 0, upload_end = 0;
-  size_t tab = 0, scales = 0, partial = 0, zzpart = 0, out = 0, total = 0;
+  size_t tab = 0, scales = 0, partial = 0, zzpart = 0, stage = 0, out = 0, total = 0;
   int nsweep = 0, nslot = 0, ntiles = 0, nout = 0, nsrc = 0, T = 0;
 };
 
 constexpr int kZZBlocks = 1024;
 
 struct Single {
-  int n, p, T, cmax, L, k;
+  int n, p, T, cmax, L, k, nbuf;
   bool dbl, grad;
   aaq_aggregation agg;
   std::vector<SetSpec> sets;
@@ -501,7 +525,7 @@ struct Single {
 // grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
 // sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
 aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
-                       aaq_precision prec, int tile, Single& S, bool with_grids = false) {
+                       aaq_precision prec, int tile, Single& S, bool with_grids = false, bool ckpt = false) {
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
     return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
@@ -519,7 +543,9 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.terms = term_array(pr, obs, S.L, S.sets);
   S.k = (int)S.sets.size();
   uint8_t eops = OP_ENERGY | (agg == AAQ_AGG_PER_TERM ? OP_PERTERM : 0);
-  S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM);
+  S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM, ckpt && grad && S.k >= 2);
+  S.nbuf = prog_buffers(S.progs);
+  if (S.nbuf > kMaxCkpt) return fail(AAQ_ERR_UNSUPPORTED, "too many checkpoint states for this depth (max 32)");
   Layout& L = S.lay;
   L.nsweep = (int)S.progs.size();
   L.T = S.T;
@@ -581,6 +607,8 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   off = align_up(off + sizeof(SwScale) * (L.nsweep + 1));
   L.partial = off;
   off = align_up(off + sizeof(double) * (size_t)(sweep_part + (zzp ? (int64_t)S.T * kZZBlocks : 0)));
+  L.stage = off;
+  off = align_up(off + sizeof(double) * (size_t)L.nout * kReduceChunks);
   L.out = off;
   off = align_up(off + sizeof(double) * L.nout);
   L.total = off;
@@ -590,17 +618,19 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
                       void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
-                      int tile = 0) {
+                      int tile = 0, bool ckpt = false) {
   aaq_status st = validate_problem(pr);
   if (st) return st;
   if ((st = validate_p(p))) return st;
   if ((st = validate_params(p, gamma, beta))) return st;
   Single S;
   if (!tile) tile = chosen_tile_bits(pr->n, prec == AAQ_PREC_C128, grad);
-  if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, S, true))) return st;
+  if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, S, true, ckpt))) return st;
   const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
   if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
-  if (state_bytes < need_state) return fail(AAQ_ERR_BUFFER, "state buffer smaller than 2^n amplitudes");
+  if (state_bytes < need_state * S.nbuf)
+    return fail(AAQ_ERR_BUFFER, S.nbuf > 1 ? "checkpoint buffer smaller than the forward states it holds"
+                                           : "state buffer smaller than 2^n amplitudes");
   if (grad) {
     if (!d_lam) return fail(AAQ_ERR_INVALID_ARG, "d_lambda is NULL");
     if (lam_bytes < need_state) return fail(AAQ_ERR_BUFFER, "lambda buffer smaller than 2^n amplitudes");
@@ -645,6 +675,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     A.T = S.T;
     A.cmax = S.cmax;
     A.amp = std::exp2(-0.5 * S.n);
+    A.N = (uint64_t)1 << S.n;
     A.set = S.sets[S.progs[sw].set];
     A.prog = S.progs[sw];
     A.two_states = needs_two_states(S.progs[sw]);
@@ -669,7 +700,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   {
     TimedLaunch tl(KC_REDUCE, 0.0, hs);
     HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb),
-                         (double*)(ws + L.out), L.nout, hs));
+                         (double*)(ws + L.stage), (double*)(ws + L.out), L.nout, hs));
     tl.done();
   }
   res.assign(L.nout, 0.0);
@@ -1003,6 +1034,39 @@ aaq_status aaq_energy_grad(const aaq_problem* prob, int p, const double* gamma, 
   std::vector<double> res;
   aaq_status s = run_single(prob, p, gamma, beta, obs, AAQ_AGG_FUSED, prec, true, d_state, state_bytes, d_lambda,
                             lambda_bytes, d_ws, ws_bytes, stream, res);
+  if (s) return s;
+  *energy_out = res[0];
+  if (norm_out) *norm_out = res[1];
+  for (int l = 0; l < p; ++l) {
+    dgamma_out[l] = res[2 + l];
+    dbeta_out[l] = res[2 + p + l];
+  }
+  return AAQ_OK;
+}
+
+aaq_status aaq_checkpoint_bytes(const aaq_problem* prob, int p, aaq_precision prec, size_t* bytes) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if ((s = validate_p(p))) return s;
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  size_t mx = 0;
+  for (int tile : {12, 13}) {  // any tile choice fits
+    Single S;
+    if ((s = plan_single(prob, p, true, AAQ_OBS_HC, AAQ_AGG_FUSED, prec, tile, S, false, true))) return s;
+    mx = std::max(mx, (size_t)S.nbuf * ((size_t)1 << prob->n) * (prec == AAQ_PREC_C128 ? 16 : 8));
+  }
+  *bytes = mx;
+  return AAQ_OK;
+}
+
+aaq_status aaq_energy_grad_checkpointed(const aaq_problem* prob, int p, const double* gamma, const double* beta,
+                                        aaq_observable obs, aaq_precision prec, void* d_ckpt, size_t ckpt_bytes,
+                                        void* d_lambda, size_t lambda_bytes, void* d_ws, size_t ws_bytes, void* stream,
+                                        double* energy_out, double* dgamma_out, double* dbeta_out, double* norm_out) {
+  if (!energy_out || !dgamma_out || !dbeta_out) return fail(AAQ_ERR_INVALID_ARG, "output pointer is NULL");
+  std::vector<double> res;
+  aaq_status s = run_single(prob, p, gamma, beta, obs, AAQ_AGG_FUSED, prec, true, d_ckpt, ckpt_bytes, d_lambda,
+                            lambda_bytes, d_ws, ws_bytes, stream, res, 0, true);
   if (s) return s;
   *energy_out = res[0];
   if (norm_out) *norm_out = res[1];

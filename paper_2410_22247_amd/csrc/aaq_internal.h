@@ -87,7 +87,10 @@ struct SweepProg {
   int8_t mixB_layer;
   int8_t mixB_dir;
   uint8_t mixB_grad;
+  uint8_t ld_buf;  // psi buffer (in units of one state) loaded / stored: 0 except with
+  uint8_t st_buf;  // forward-state checkpoints, where sweep i stores buffer i
 };
+constexpr int kMaxCkpt = 32;  // max psi buffers of a checkpointed program
 
 // Per-sweep scale record.  Mixer gates are applied as (I - i k X) per qubit, with
 // |k| <= 1; the dropped scalar factor phi per qubit (cos b, or +-i sin b together with

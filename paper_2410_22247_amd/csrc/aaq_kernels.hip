@@ -19,7 +19,7 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       si = 0.0;
     }
   };
-  uint64_t F = 0, mF = 0;  // flip mask in registers / of the buffers in memory
+  uint64_t F = 0;  // flip mask in registers
   auto mixer = [&](int layer, int dir, uint32_t act, uint64_t gact, double& k, double& w, double& sx) {
     k = 0.0;
     w = 1.0;
@@ -52,8 +52,15 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
     si = ni;
   };
   // scales of the buffers in memory: psi and lambda differ after a sweep that stores
-  // only lambda (the last forward sweep leaves psi untouched in memory)
-  double mpr = 1.0, mpi = 0.0, mlr = 1.0, mli = 0.0;
+  // only lambda (the last forward sweep leaves psi untouched in memory); with
+  // checkpoints every psi buffer keeps the scale and flips it was stored with
+  double mpr[kMaxCkpt], mpi[kMaxCkpt], mlr = 1.0, mli = 0.0;
+  uint64_t mF[kMaxCkpt];
+  for (int b = 0; b < kMaxCkpt; ++b) {
+    mpr[b] = 1.0;
+    mpi[b] = 0.0;
+    mF[b] = 0;
+  }
   for (int i = 0; i < nsweep; ++i) {
     const SweepProg pg = progs[i];
     SwScale r;
@@ -66,9 +73,9 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       si = 0.0;
       F = 0;
     } else if (pg.flags & F_LOAD_PSI) {
-      sr = mpr;
-      si = mpi;
-      F = mF;
+      sr = mpr[pg.ld_buf];
+      si = mpi[pg.ld_buf];
+      F = mF[pg.ld_buf];
     }
     if (pg.flags & F_LOAD_LAM) {  // lambda <- lambda * sigma_psi / sigma_lam
       const double d = mlr * mlr + mli * mli;
@@ -86,9 +93,9 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
     position(pg.mid_ops, r.rho_mid, r.s_mid);
     mixer(pg.mixB_layer, pg.mixB_dir, act, gact, r.kB, r.wB, r.s_B);
     if (pg.flags & F_STORE_PSI) {
-      mpr = sr;
-      mpi = si;
-      mF = F;
+      mpr[pg.st_buf] = sr;
+      mpi[pg.st_buf] = si;
+      mF[pg.st_buf] = F;
     }
     if (pg.flags & F_STORE_LAM) {
       mlr = sr;
@@ -191,26 +198,32 @@ struct RedSrc {
   int32_t out;   // output index
   double scale;
 };
-__global__ void k_reduce(const double* __restrict__ partial, const RedSrc* __restrict__ src, const int32_t* __restrict__ src_begin,
-                         double* __restrict__ out) {
-  __shared__ double red[16];  // up to 1024 threads
-  const int o = blockIdx.x;
+// Two fixed-order stages: block (o, c) sums chunk c (of kRedChunks equal slices) of
+// every source of output o into stage[o][c]; k_reduce_final adds the chunks in order.
+constexpr int kRedChunks = kReduceChunks;
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, const RedSrc* __restrict__ src,
+                                                const int32_t* __restrict__ src_begin, double* __restrict__ stage) {
+  __shared__ double red[4];
+  const int o = blockIdx.x, c = blockIdx.y;
   double tot = 0.0;
   for (int k = src_begin[o]; k < src_begin[o + 1]; ++k) {
     const RedSrc s = src[k];
+    const int64_t lo = (int64_t)s.count * c / kRedChunks, hi = (int64_t)s.count * (c + 1) / kRedChunks;
     double v = 0.0;
-    for (int i = threadIdx.x; i < s.count; i += blockDim.x) v += partial[s.off + i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v += partial[s.off + i];
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x / 64); ++w) t += red[w];
-      tot += s.scale * t;
-    }
+    if (threadIdx.x == 0) tot += s.scale * (red[0] + red[1] + red[2] + red[3]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[o] = tot;
+  if (threadIdx.x == 0) stage[(size_t)o * kRedChunks + c] = tot;
+}
+__global__ __launch_bounds__(64) void k_reduce_final(const double* __restrict__ stage, double* __restrict__ out) {
+  const int o = blockIdx.x;
+  double v = threadIdx.x < kRedChunks ? stage[(size_t)o * kRedChunks + threadIdx.x] : 0.0;
+  v = wave_sum(v);
+  if (threadIdx.x == 0) out[o] = v;
 }
 
 // one <Z_i Z_j> pass over the final state (per-term estimator structure)
@@ -271,9 +284,11 @@ hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, 
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(nout), dim3(256), 0, st, partial, reinterpret_cast<const RedSrc*>(src), src_begin, out);
+hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* stage, double* out,
+                         int nout, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce, dim3(nout, kRedChunks), dim3(256), 0, st, partial, reinterpret_cast<const RedSrc*>(src),
+                     src_begin, stage);
+  hipLaunchKernelGGL(k_reduce_final, dim3(nout), dim3(64), 0, st, stage, out);
   return hipGetLastError();
 }
 

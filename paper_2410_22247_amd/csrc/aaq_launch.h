@@ -16,6 +16,7 @@ struct LaunchSweep {
   double* partial;
   int nslot, T, cmax;
   double amp;
+  uint64_t N;  // amplitudes per state (stride between checkpoint buffers)
   SetSpec set;
   SweepProg prog;
   bool two_states;
@@ -55,8 +56,10 @@ hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, 
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
                          int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
-hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* out, int nout,
-                         hipStream_t st);
+// fixed-order sums of per-tile partials; stage holds nout * kReduceChunks doubles
+constexpr int kReduceChunks = 32;
+hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* stage, double* out,
+                         int nout, hipStream_t st);
 hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, const uint64_t* flips,
                           double* partial, int blocks, bool dbl, hipStream_t st);
 

@@ -154,6 +154,31 @@ def test_energy_grad_matches_oracle_adjoint(g, p):
         assert abs(nrm - 1) < 1e-5
 
 
+@pytest.mark.parametrize("g,p,prec", [(G.prufer_tree(12, 4), 2, A.AAQ_PREC_C64), (G.prufer_tree(15, 2), 3, A.AAQ_PREC_C64),
+                                      (G.star(19), 2, A.AAQ_PREC_C128), (G.prufer_tree(23, 6), 3, A.AAQ_PREC_C64),
+                                      (G.random_regular(3, 20, seed=9), 2, A.AAQ_PREC_C64)],
+                         ids=["n12", "n15", "star19-c128", "n23", "3reg20"])
+def test_checkpointed_gradient(g, p, prec):
+    """Forward-state checkpoints give the oracle's energy and gradient, for both tile sizes."""
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(g.n * 13 + p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(OBS_HRED), gam, bet)
+    tol = 1e-10 if prec == A.AAQ_PREC_C128 else EREL
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, prec, grad=True, checkpoint=True)
+    assert est.state.numel() == A.aaq_checkpoint_bytes(pr, p, prec)
+    try:
+        for tile in (12, 13):
+            A.aaq_set_tile_bits(g.n, prec, True, tile)
+            e, dg, db, nrm = est.energy_grad(gam, bet)
+            check_energy(e, e_ref, tol)
+            check_grad(np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref]), tol)
+            assert abs(nrm - 1) < (1e-12 if prec == A.AAQ_PREC_C128 else 1e-5)
+    finally:
+        A.aaq_set_tile_bits(g.n, prec, True, 0)
+
+
 def test_energy_grad_complex128():
     g = G.prufer_tree(15, 4)
     wp = make_problem(g)
