@@ -22,7 +22,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "<H>+adjoint-grad evals/s (n=26,p=4), % HBM roofline, H_red vs H_C"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-KERNEL_SOURCES = ["paper_2410_22247_amd/csrc/aaq_kernels.hip", "paper_2410_22247_amd/csrc/aaq_internal.h"]
+KERNEL_SOURCES = ["paper_2410_22247_amd/csrc/aaq_engine.h", "paper_2410_22247_amd/csrc/aaq_kernels.hip",
+                  "paper_2410_22247_amd/csrc/aaq_internal.h"]
 
 
 def kernel_hash() -> str:

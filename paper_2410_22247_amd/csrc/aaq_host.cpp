@@ -324,11 +324,14 @@ int chosen_tile_bits(int n, bool dbl, bool grad) {
   return it == g_tune.end() ? auto_tile_bits(n) : it->second;
 }
 
+// Set of sweep i: a zig-zag k-1, ..., 1, 0, 1, ..., k-1, ... that starts at the last set,
+// so the first sweep (which synthesises |+>) and the last forward sweep (the turnaround)
+// fall on a set of high qubits, whose mixer needs one LDS transpose fewer than set 0's.
 int zig(int i, int k) {
   if (k == 1) return 0;
   const int per = 2 * (k - 1);
   const int m = i % per;
-  return (m <= k - 1) ? m : per - m;
+  return (k - 1) - ((m <= k - 1) ? m : per - m);
 }
 
 SweepProg blank() {
@@ -659,7 +662,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   {
     TimedLaunch tl(KC_TABLES, 0.0, hs);
     HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, (const SweepProg*)(ws + L.progs), L.nsweep,
-                         (const SetSpec*)(ws + L.sets), (SwScale*)(ws + L.scales), S.dbl, hs));
+                         (const SetSpec*)(ws + L.sets), (int)S.sets.size(), (SwScale*)(ws + L.scales), S.dbl, hs));
     tl.done();
   }
   for (int sw = 0; sw < L.nsweep; ++sw) {

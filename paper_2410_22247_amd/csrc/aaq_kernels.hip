@@ -4,8 +4,21 @@
 #include "aaq_engine.h"
 
 namespace aaq {
+
+// A unit's sweep programs, set masks and sin/cos(beta) staged in LDS by the whole
+// workgroup, so the sequential walk below reads no global memory.
+constexpr int kMaxSweeps = 2 * (kMaxP * (kMaxSets - 1) + 1);
+struct ScaleStage {
+  SweepProg progs[kMaxSweeps];
+  uint64_t gact[kMaxSets];
+  uint32_t act[kMaxSets];
+  double sb[kMaxP], cb[kMaxP];
+};
+
+// Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
 // the scale corrections (see SwScale).  out[nsweep].s_pre is 1/|sigma|^2 at the end.
-__device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* sets, const double* beta, SwScale* out) {
+__device__ void build_scales(const ScaleStage& S, int nsweep, SwScale* out) {
+  const SweepProg* progs = S.progs;
   double sr = 1.0, si = 0.0;  // sigma
   auto position = [&](uint8_t ops, double* rho, double& sx) {
     const double a2 = sr * sr + si * si;
@@ -25,8 +38,7 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
     w = 1.0;
     sx = 1.0 / (sr * sr + si * si);
     if (!dir) return;
-    double sn, cs;
-    sincos(beta[layer], &sn, &cs);
+    const double sn = S.sb[layer], cs = S.cb[layer];
     double pr, pi;  // phi
     if (fabs(cs) >= fabs(sn)) {
       k = dir * sn / cs;
@@ -84,8 +96,8 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
       r.lam_fix[1] = fi;
       r.fix_lam = (fr != 1.0 || fi != 0.0) ? 1u : 0u;
     }
-    const uint32_t act = sets[pg.set].act;
-    const uint64_t gact = sets[pg.set].gact;
+    const uint32_t act = S.act[pg.set];
+    const uint64_t gact = S.gact[pg.set];
     r.F_pre = F;
     position(pg.pre_ops, r.rho_pre, r.s_pre);
     mixer(pg.mixA_layer, pg.mixA_dir, act, gact, r.kA, r.wA, r.s_A);
@@ -115,6 +127,19 @@ __device__ void build_scales(const SweepProg* progs, int nsweep, const SetSpec* 
   f.lam_fix[1] = 0.0;
   f.fix_lam = f.pad = 0;
   out[nsweep] = f;
+}
+
+// whole-workgroup entry: stage, then thread 0 walks the sweeps
+__device__ void stage_and_build_scales(ScaleStage& S, const SweepProg* progs, int nsweep, const SetSpec* sets, int nsets,
+                                       const double* beta, int p, SwScale* out) {
+  for (int i = threadIdx.x; i < nsweep; i += blockDim.x) S.progs[i] = progs[i];
+  for (int s = threadIdx.x; s < nsets; s += blockDim.x) {
+    S.act[s] = sets[s].act;
+    S.gact[s] = sets[s].gact;
+  }
+  for (int l = threadIdx.x; l < p; l += blockDim.x) sincos(beta[l], &S.sb[l], &S.cb[l]);
+  __syncthreads();
+  if (threadIdx.x == 0) build_scales(S, nsweep, out);
 }
 
 
@@ -162,7 +187,8 @@ template <class R> __global__ void k_bsweep_out(BatchArgs<R> A, double* out, int
 template <class R>
 __global__ void k_tables(const double* __restrict__ gamma, const double* __restrict__ beta, int p, int cmax,
                          typename Cx<R>::V* __restrict__ tab, const SweepProg* progs, int nsweep, const SetSpec* sets,
-                         SwScale* scales) {
+                         int nsets, SwScale* scales) {
+  __shared__ ScaleStage stage;
   const int tot = p * (cmax + 1);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
     const int l = i / (cmax + 1), c = i % (cmax + 1);
@@ -170,12 +196,13 @@ __global__ void k_tables(const double* __restrict__ gamma, const double* __restr
     sincos(gamma[l] * (double)c, &sn, &cs);
     tab[i] = mkv<R>((R)cs, (R)(-sn));
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) build_scales(progs, nsweep, sets, beta, scales);
+  if (blockIdx.x == 0) stage_and_build_scales(stage, progs, nsweep, sets, nsets, beta, p, scales);
 }
 
 // per-unit tables for a plan; block b handles unit b; also resets the work counter
 template <class R> __global__ void k_plan_tables(UnitArgs<R> A, int p, int pstride) {
   using V = typename Cx<R>::V;
+  __shared__ ScaleStage stage;
   if (blockIdx.x == 0 && threadIdx.x < 4) A.counter[threadIdx.x] = 0;  // one work counter per unit kernel launch
   const UnitDesc* D = A.units + blockIdx.x;
   const double* prm = A.params + (size_t)D->row * pstride;
@@ -187,8 +214,8 @@ template <class R> __global__ void k_plan_tables(UnitArgs<R> A, int p, int pstri
     sincos(prm[l] * (double)c, &sn, &cs);
     tab[i] = mkv<R>((R)cs, (R)(-sn));
   }
-  if (threadIdx.x == 0)
-    build_scales(A.progs + D->prog_off, D->nsweep, D->sets, prm + p, const_cast<SwScale*>(unit_scales<R>(A.ws, D)));
+  stage_and_build_scales(stage, A.progs + D->prog_off, D->nsweep, D->sets, D->nsets, prm + p, p,
+                         const_cast<SwScale*>(unit_scales<R>(A.ws, D)));
 }
 
 // fixed-order sums of per-tile partials: out[o] = scale_o * sum_{sources of o} sum_tiles
@@ -253,15 +280,15 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
 // ------------------------------------------------------------------------------------
 // launch functions used by the host code
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
-                         int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st) {
+                         int nsweep, const SetSpec* sets, int nsets, SwScale* scales, bool dbl, hipStream_t st) {
   const int tot = p * (cmax + 1);
   const int blocks = (tot + 255) / 256;
   if (dbl)
     hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
-                       reinterpret_cast<double2*>(tab), progs, nsweep, sets, scales);
+                       reinterpret_cast<double2*>(tab), progs, nsweep, sets, nsets, scales);
   else
     hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
-                       reinterpret_cast<float2*>(tab), progs, nsweep, sets, scales);
+                       reinterpret_cast<float2*>(tab), progs, nsweep, sets, nsets, scales);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ hipError_t launch_cuts(const GraphDev* g, const int4* terms, int T, int use_term
                        int32_t* out, bool dbl, int tile_bits, hipStream_t st);
 hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st);
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
-                         int nsweep, const SetSpec* sets, SwScale* scales, bool dbl, hipStream_t st);
+                         int nsweep, const SetSpec* sets, int nsets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
 // fixed-order sums of per-tile partials; stage holds nout * kReduceChunks doubles
 constexpr int kReduceChunks = 32;
