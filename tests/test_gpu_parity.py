@@ -213,6 +213,77 @@ def test_energy_grad_n26_config3_point():
     check_energy(est.energy(gams[0], bets[0])[0], e_full)
 
 
+def _release(*objs):
+    for o in objs:
+        del o
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def test_energy_grad_n26_config3_checkpointed():
+    """The launch configuration the benchmark times (n = 26, p = 4, forward-state
+    checkpoints, 4 GiB of checkpoint slots): energy and gradient against the
+    light-cone FP64 adjoint at three points, and equal to the uncompute mode within the
+    sum of the two modes' tolerances (their complex64 rounding differs)."""
+    from workloads.configs import config3
+
+    wp, p, gams, bets = config3(3)
+    pr = A.Problem.from_workload(wp)
+    terms = wp.terms(OBS_HRED)
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=True)
+    res = []
+    for k in range(3):
+        e, dg, db, nrm = est.energy_grad(gams[k], bets[k])
+        e_lc, dg_lc, db_lc, _ = Rd.light_cone_energy_grad(wp.n, wp.edges(), terms, gams[k], bets[k])
+        check_energy(e, e_lc)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc]))
+        assert abs(nrm - 1) < 1e-5
+        res.append(np.concatenate([[e], dg, db]))
+    _release(est)
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=False)
+    for k in range(3):
+        e, dg, db, _ = est.energy_grad(gams[k], bets[k])
+        check_energy(e, res[k][0], 2 * EREL)
+        check_grad(np.concatenate([dg, db]), res[k][1:], 2 * GREL)
+    _release(est)
+
+
+def test_energy_n34_config5a_full_size():
+    """n = 34, p = 1: one 128 GiB complex64 state on 13-bit tiles in 4 tile sets.
+    Energies of both observables against the p = 1 closed form at four points."""
+    from workloads.configs import config5a
+
+    wp, p, gams, bets = config5a(4)
+    pr = A.Problem.from_workload(wp)
+    assert A.aaq_state_bytes(pr) == 8 << 34
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=False)
+    for k in range(4):
+        for obs in (OBS_HRED, OBS_HC):
+            e, _, nrm = est.energy(gams[k], bets[k], obs=obs)
+            ref = Rd.p1_energy(wp.n, wp.edges(), wp.terms(obs), gams[k, 0], bets[k, 0])
+            check_energy(e, ref)
+            assert abs(nrm - 1) < 1e-5
+    _release(est)
+
+
+def test_energy_grad_n33_config5b_full_size():
+    """n = 33, p = 2: energy + adjoint gradient with two 64 GiB states, against the
+    light-cone FP64 adjoint (cones of at most 16 qubits) for both observables."""
+    from workloads.configs import config5b
+
+    wp, p, gams, bets = config5b(2)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    for k, obs in ((0, OBS_HRED), (1, OBS_HC)):
+        e, dg, db, nrm = est.energy_grad(gams[k], bets[k], obs=obs)
+        e_lc, dg_lc, db_lc, mb = Rd.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(obs), gams[k], bets[k])
+        assert mb <= 16
+        check_energy(e, e_lc)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc]))
+        assert abs(nrm - 1) < 1e-5
+    _release(est)
+
+
 # ------------------------------------------------------------------ tile sizes and autotuning
 @pytest.mark.parametrize("g,p", [(G.prufer_tree(14, 2), 2), (G.star(17), 2), (G.prufer_tree(21, 3), 2),
                                  (rand_graph(22, 0.15, 5), 1), (G.random_regular(3, 24, seed=4), 2)],
