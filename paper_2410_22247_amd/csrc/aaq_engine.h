@@ -132,6 +132,46 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   V a[NS][NR];
   bool lam_live;
 
+  // ------------------------------------------------ compile-time qubit masks of the routes
+  // tile bits held in registers by arrangement K
+  __host__ __device__ static constexpr uint32_t regmask(int K) { return ((1u << RB) - 1u) << G::b0(K); }
+  // first arrangement after the load arrangement on route RT
+  __host__ __device__ static constexpr int first_arr(int RT) { return RT == ROUTE_FULL ? 0 : 1; }
+  // tile bits a route may mix: all of them, or (sets of high qubits) all but the low
+  // kMinContig bits, which such a set always holds passively
+  __host__ __device__ static constexpr uint32_t route_bits(int RT) {
+    return RT == ROUTE_FULL ? ((1u << L) - 1u) : (((1u << L) - 1u) & ~((1u << kMinContig) - 1u));
+  }
+  // tile bits mixed at arrangement K when a mixer walks the route forward (LAST, first,
+  // ..., P) or backward (P, ..., first, LAST): a qubit is mixed at the first arrangement
+  // of the walk that holds it in registers
+  __host__ __device__ static constexpr uint32_t fwd_mask(int RT, int K) {
+    uint32_t t = route_bits(RT);
+    if (K == LAST) return t & regmask(LAST);
+    t &= ~regmask(LAST);
+    for (int j = first_arr(RT); j < K; ++j) t &= ~regmask(j);
+    return t & regmask(K);
+  }
+  __host__ __device__ static constexpr uint32_t bwd_mask(int RT, int K) {
+    uint32_t t = route_bits(RT);
+    if (K == LAST) {
+      for (int j = first_arr(RT); j <= P; ++j) t &= ~regmask(j);
+      return t & regmask(LAST);
+    }
+    for (int j = K + 1; j <= P; ++j) t &= ~regmask(j);
+    return t & regmask(K);
+  }
+  __host__ __device__ static constexpr bool walks_cover(int RT) {
+    uint32_t f = fwd_mask(RT, LAST), b = bwd_mask(RT, LAST);
+    for (int j = first_arr(RT); j <= P; ++j) {
+      if ((f & fwd_mask(RT, j)) || (b & bwd_mask(RT, j))) return false;  // no bit twice
+      f |= fwd_mask(RT, j);
+      b |= bwd_mask(RT, j);
+    }
+    return f == route_bits(RT) && b == route_bits(RT);
+  }
+  static_assert(walks_cover(ROUTE_FULL) && walks_cover(ROUTE_HIGH), "every route bit is mixed exactly once");
+
   // -------------------------------------------------------------- LDS transpose
   template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
     constexpr int BF = G::b0(KF), BT = G::b0(KT);
@@ -145,37 +185,62 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
     __syncthreads();
   }
-  template <int KF, int KT> __device__ __forceinline__ void xchg(V* lds) {
+  // LAM: lambda is live (compile-time, so no per-register branch)
+  template <int KF, int KT, bool LAM> __device__ __forceinline__ void xchg(V* lds) {
     xchg1<KF, KT>(a[0], lds);
-    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
+    if constexpr (NS == 2 && LAM) xchg1<KF, KT>(a[NS - 1], lds);
   }
 
   // -------------------------------------------------------------- mixer butterflies
-  // (I - i k X_q) on every tile bit of `todo` held in registers by arrangement K:
-  // (x, y) -> (x - i k y, y - i k x), two FMAs per amplitude.  With `grad`, the pair's
-  // Im <lam|X_q|psi> is accumulated with weight wcur, which tracks the scale change of
-  // the preceding gates of the same mixer (wcur *= w after every qubit).
-  template <int K> __device__ __forceinline__ void mix_at(uint32_t& todo, R k, R w, R& wcur, bool grad, R& gsum) {
+  // (I - i k X_q) on the tile bits of MASK, a compile-time subset of arrangement K's
+  // register bits: (x, y) -> (x - i k y, y - i k x), two FMAs per amplitude.  A qubit
+  // that the set does not mix (not in `act`) gets k = 0 by a uniform select, so the
+  // unrolled butterflies carry no branches.  With LAM, lambda gets the same gates and
+  // the mixer's gradient terms Im <lam|X_q|psi> are accumulated.  Every gate (I - i k X)
+  // applied to both states multiplies each such term by 1 + k^2 = 1/w (the X's commute),
+  // so the terms of the qubits mixed here are evaluated once after this arrangement's
+  // butterflies and weighted by wcur = w^(gates of the mixer applied so far): that is
+  // the term at the start of the mixer.  Evaluating after the butterflies keeps no
+  // pre-gate values alive.
+  template <int K, uint32_t MASK, bool LAM>
+  __device__ __forceinline__ void mix_at(uint32_t act, R k, R w, R& wcur, R& gsum) {
     constexpr int B0 = G::b0(K);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      if ((todo >> (B0 + b)) & 1u) {
+      if (!((MASK >> (B0 + b)) & 1u)) continue;
+      const bool on = ((act >> (B0 + b)) & 1u) != 0;
+      const R kk = on ? k : R(0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r & (1 << b)) continue;
+        const int r1 = r | (1 << b);
+        if constexpr (NS == 2 && LAM) bflyk(a[NS - 1][r], a[NS - 1][r1], kk);
+        bflyk(a[0][r], a[0][r1], kk);
+      }
+      wcur *= on ? w : R(1);
+      // keep the scheduler from interleaving the butterflies of different qubits, which
+      // holds pre- and post-gate values at once (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (NS == 2 && LAM) {
+      R gt = R(0);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (!((MASK >> (B0 + b)) & 1u)) continue;
         R gq = R(0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r & (1 << b)) continue;
           const int r1 = r | (1 << b);
-          if (NS == 2) {
-            if (grad) gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
-            if (lam_live) bflyk(a[NS - 1][r], a[NS - 1][r1], k);
-          }
-          bflyk(a[0][r], a[0][r1], k);
+          gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
         }
-        if (NS == 2 && grad) gsum += wcur * gq;
-        wcur *= w;
+        gt += ((act >> (B0 + b)) & 1u) ? gq : R(0);
       }
+      gsum += wcur * gt;
+      // the terms are formed here, before a following transpose: the empty volatile asm
+      // is ordered with the LDS stores, so the pre-transpose values are not kept alive
+      asm volatile("" : "+v"(gsum));
     }
-    todo &= ~(((1u << RB) - 1u) << B0);
   }
 
   // -------------------------------------------------------------- z of register 0
@@ -299,11 +364,20 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   }
 
   // -------------------------------------------------------------- ops at one position
-  template <int K>
-  __device__ __forceinline__ void ops_at(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, uint64_t F,
-                                         const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
-    if (!ops) return;
-    const uint64_t zb = zbase<K>(S, tile_base, F);
+  // LAM: lambda is live on entry (compile-time).  Returns with lam_live set when the
+  // energy step created lambda.
+  // COPS: the ops at this position, a compile-time mask (the program's own ops are
+  // passed for reference only).
+  template <int K, bool LAM, uint32_t COPS>
+  __device__ __forceinline__ void ops_at(uint8_t /*ops_rt*/, bool make_lam, const SetSpec& S, uint64_t tile_base,
+                                         uint64_t F, const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc,
+                                         double* zz_lds) {
+    constexpr uint8_t ops = (uint8_t)COPS;
+    if constexpr (ops == 0) return;
+    uint64_t zb = zbase<K>(S, tile_base, F);
+    // opaque here: the integer work below stays at this position instead of being
+    // hoisted above the mixer, where its values would add to the register pressure
+    asm volatile("" : "+v"(zb));
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
       if (cx.g->h_is_cut)
@@ -317,6 +391,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
         e += (double)p2 * (double)hv[r];
         nr += (double)p2;
       }
+      // the sums are formed here, before the steps after this position change the state
+      asm volatile("" : "+v"(e), "+v"(nr));
       acc.e += e;
       acc.nrm += nr;
       if (ops & OP_PERTERM) perterm<K>(S, zb, cx, zz_lds);
@@ -332,11 +408,16 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
       cuts<K>(S, zb, cx.g, cv);
-      if (NS == 2 && (ops & OP_GRADG)) {
-        R gs = R(0);
+      if constexpr (NS == 2 && LAM) {
+        if (ops & OP_GRADG) {
+          R gs = R(0);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
-        gacc += (double)gs;
+          for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+          // formed before the phase step below overwrites the states (ordered with its
+          // table reads), so the pre-phase values are not kept alive
+          asm volatile("" : "+v"(gs));
+          gacc += (double)gs;
+        }
       }
       if (ops & (OP_PHASE | OP_UNPHASE)) {
 #pragma unroll
@@ -345,7 +426,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
           const R tc = tv.x, ts = tv.y;
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            if (s == 0 || lam_live) {
+            if (s == 0 || (NS == 2 && LAM)) {
               const V x = a[s][r];
               a[s][r] = mkv<R>(x.x * tc - x.y * ts, x.x * ts + x.y * tc);
             }
@@ -397,24 +478,28 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     return toff;
   }
-  // element offset of register r at the load arrangement (host-computed table)
-  template <int K, int r> __device__ __forceinline__ static uint64_t reg_off(const SetSpec& S) {
-    static_assert(K == LAST, "global I/O happens at the load arrangement");
-    return S.roff[r];
-  }
   template <int K> __device__ __forceinline__ bool is_dummy(const SetSpec& S, int r) const {
     return S.dummy && (tidx<G::b0(K), RB>(threadIdx.x, r) & S.dummy);
   }
-  template <int K, int r = 0> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
-    if constexpr (r < NR) {
-      a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[reg_off<K, r>(S)];
-      load_all<K, r + 1>(s, p, S);
+  template <int K> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    if (!S.dummy) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[S.roff[r]];
     }
   }
-  template <int K, int r = 0> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
-    if constexpr (r < NR) {
-      if (!is_dummy<K>(S, r)) p[reg_off<K, r>(S)] = a[s][r];
-      store_all<K, r + 1>(s, p, S);
+  template <int K> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    if (!S.dummy) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) p[S.roff[r]] = a[s][r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (!is_dummy<K>(S, r)) p[S.roff[r]] = a[s][r];
     }
   }
   template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
@@ -424,43 +509,238 @@ template <class R, int NS, bool EN, int LT> struct Tile {
 
   // -------------------------------------------------------------- one sweep on one tile
   // Mixer routes (both start at the load arrangement LAST): ROUTE_FULL visits LAST, 0,
+  // 1, ..., P; ROUTE_HIGH, for sets whose mixed qubits are all tile bits >= kMinContig,
+  // skips arrangement 0.  Mixer A walks the route forward and ends at the phase
+  // arrangement P, mixer B walks it back to LAST.  The qubits mixed at each stop are
+  // compile-time masks (fwd_mask, bwd_mask).
+  template <int RT, int K, int PREV, bool LAM>
+  __device__ __forceinline__ void fwd_steps(uint32_t act, R k, R w, R& wcur, R& gs, V* lds) {
+    if constexpr (K <= P) {
+      xchg<PREV, K, LAM>(lds);
+      mix_at<K, fwd_mask(RT, K), LAM>(act, k, w, wcur, gs);
+      fwd_steps<RT, K + 1, K, LAM>(act, k, w, wcur, gs, lds);
+    }
+  }
+  template <int RT, int K, bool LAM>
+  __device__ __forceinline__ void bwd_steps(uint32_t act, R k, R w, R& wcur, R& gs, V* lds) {
+    if constexpr (K >= first_arr(RT)) {
+      xchg<K + 1, K, LAM>(lds);
+      mix_at<K, bwd_mask(RT, K), LAM>(act, k, w, wcur, gs);
+      bwd_steps<RT, K - 1, LAM>(act, k, w, wcur, gs, lds);
+    }
+  }
+  template <int RT, bool LAM> __device__ __forceinline__ void mix_fwd(uint32_t act, R k, R w, R& gs, V* lds) {
+    R wcur = R(1);
+    mix_at<LAST, fwd_mask(RT, LAST), LAM>(act, k, w, wcur, gs);
+    fwd_steps<RT, first_arr(RT), LAST, LAM>(act, k, w, wcur, gs, lds);
+  }
+  template <int RT, bool LAM> __device__ __forceinline__ void mix_bwd(uint32_t act, R k, R w, R& gs, V* lds) {
+    constexpr int FIRST = first_arr(RT);
+    R wcur = R(1);
+    mix_at<P, bwd_mask(RT, P), LAM>(act, k, w, wcur, gs);
+    bwd_steps<RT, P - 1, LAM>(act, k, w, wcur, gs, lds);
+    xchg<(FIRST < P ? FIRST : P), LAST, LAM>(lds);
+    mix_at<LAST, bwd_mask(RT, LAST), LAM>(act, k, w, wcur, gs);
+  }
+
+  // Executes program `pg` on the tile with id `tile` of set S (whose route is RT), for
+  // a sweep of shape KIND (SK_*), known at compile time: no step is a run-time branch
+  // around register updates.  The sweep runs in three stages (pre ops, mixer A + mid
+  // ops, mixer B + store), each compiled for lambda live or not; lambda becomes live
+  // where the energy step makes it.  Stores and buffer indices follow the program.
+  template <int RT, uint32_t KIND>
+  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+                                      const Ctx<R>& cx, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
+                                      double* zz_lds) {
+    static_assert((KIND & SK_GENERIC) == 0, "generic sweeps take run_rt");
+    static_assert(NS == ((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), "state count of the shape");
+    static_assert(!((KIND & SK_MAKE_LAM) && (sk_pre(KIND) & OP_ENERGY)), "lambda is made at the mid position");
+    constexpr int KL = LAST;
+    const uint64_t tile_base = pdep64(tile, S.fixmask);
+    if constexpr ((KIND & SK_INIT) != 0) {
+      init_at<KL>(S, cx.amp);
+    } else {
+      const uint64_t toff = tile_base + thread_off<KL>(S);
+      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N + toff, S);
+      if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
+        load_all<KL>(NS - 1, cx.lam + toff, S);
+        if (sc.fix_lam) {
+          const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const V x = a[NS - 1][r];
+            a[NS - 1][r] = mkv<R>(x.x * fr - x.y * fi, x.x * fi + x.y * fr);
+          }
+        }
+      }
+    }
+    constexpr bool LAM0 = NS == 2 && (KIND & SK_LAM_IN) != 0;
+    lam_live = LAM0;
+    ops_at<KL, LAM0, sk_pre(KIND)>(pg.pre_ops, false, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    bool at_p = false;
+    if constexpr ((KIND & SK_MIXA) != 0) {
+      R gs = R(0);
+      mix_fwd<RT, LAM0>(S.act, (R)sc.kA, (R)sc.wA, gs, lds_x);
+      if (pg.mixA_grad) acc.ba += (double)gs;
+      at_p = true;
+    }
+    if constexpr ((sk_mid(KIND) != 0 || (KIND & SK_MIXB) != 0) && (KIND & SK_MIXA) == 0) {
+      xchg<LAST, P, LAM0>(lds_x);
+      at_p = true;
+    }
+    ops_at<P, LAM0, sk_mid(KIND)>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, sc.F_mid, cx, ltab_mid,
+                                  acc.gmid, acc, zz_lds);
+    constexpr bool LAM1 = LAM0 || (NS == 2 && (KIND & SK_MAKE_LAM) != 0);
+    if constexpr ((KIND & SK_MIXB) != 0) {
+      R gs = R(0);
+      mix_bwd<RT, LAM1>(S.act, (R)sc.kB, (R)sc.wB, gs, lds_x);
+      if (pg.mixB_grad) acc.bb += (double)gs;
+      at_p = false;
+    }
+    const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
+    const bool st_lam = NS == 2 && LAM1 && (pg.flags & F_STORE_LAM) && cx.lam;
+    if ((st_psi || st_lam) && at_p) xchg<P, LAST, LAM1>(lds_x);
+    uint64_t toff = tile_base + thread_off<LAST>(S);
+    // opaque to the compiler: the store addresses are formed here, not kept in
+    // registers from the loads (that would hold 2 VGPRs per register and state)
+    asm volatile("" : "+v"(toff));
+    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N + toff, S);
+    if (st_lam) store_all<LAST>(NS - 1, cx.lam + toff, S);
+  }
+
+  // ================================================================ run-time-flag path
+  // The generic sweep (batched unit kernels and shapes without a specialization): the
+  // same steps as above with every decision taken from the program at run time.  Mixer
+  // butterflies follow a run-time set of pending qubits and lambda's liveness, and the
+  // mixer's gradient terms are formed pair by pair before each gate.
+  template <int KF, int KT> __device__ __forceinline__ void xchg_rt(V* lds) {
+    xchg1<KF, KT>(a[0], lds);
+    if (NS == 2 && lam_live) xchg1<KF, KT>(a[NS - 1], lds);
+  }
+
+  // (I - i k X_q) on every tile bit of `todo` held in registers by arrangement K:
+  // (x, y) -> (x - i k y, y - i k x), two FMAs per amplitude.  With `grad`, the pair's
+  // Im <lam|X_q|psi> is accumulated with weight wcur, which tracks the scale change of
+  // the preceding gates of the same mixer (wcur *= w after every qubit).
+  template <int K> __device__ __forceinline__ void mix_at_rt(uint32_t& todo, R k, R w, R& wcur, bool grad, R& gsum) {
+    constexpr int B0 = G::b0(K);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if ((todo >> (B0 + b)) & 1u) {
+        R gq = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r & (1 << b)) continue;
+          const int r1 = r | (1 << b);
+          if (NS == 2) {
+            if (grad) gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
+            if (lam_live) bflyk(a[NS - 1][r], a[NS - 1][r1], k);
+          }
+          bflyk(a[0][r], a[0][r1], k);
+        }
+        if (NS == 2 && grad) gsum += wcur * gq;
+        wcur *= w;
+      }
+    }
+    todo &= ~(((1u << RB) - 1u) << B0);
+  }
+
+  template <int K>
+  __device__ __forceinline__ void ops_at_rt(uint8_t ops, bool make_lam, const SetSpec& S, uint64_t tile_base, uint64_t F,
+                                         const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc, double* zz_lds) {
+    if (!ops) return;
+    const uint64_t zb = zbase<K>(S, tile_base, F);
+    if (EN && (ops & OP_ENERGY)) {
+      int hv[NR];
+      if (cx.g->h_is_cut)
+        cuts<K>(S, zb, cx.g, hv);
+      else
+        hvals<K>(S, zb, cx.terms, hv);
+      double e = 0.0, nr = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const R p2 = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
+        e += (double)p2 * (double)hv[r];
+        nr += (double)p2;
+      }
+      asm volatile("" : "+v"(e), "+v"(nr));  // formed here (see ops_at)
+      acc.e += e;
+      acc.nrm += nr;
+      if (ops & OP_PERTERM) perterm<K>(S, zb, cx, zz_lds);
+      if (NS == 2 && make_lam) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const R h = (R)hv[r];
+          a[NS - 1][r] = mkv<R>(h * a[0][r].x, h * a[0][r].y);
+        }
+        lam_live = true;
+      }
+    }
+    if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
+      int cv[NR];
+      cuts<K>(S, zb, cx.g, cv);
+      if (NS == 2 && (ops & OP_GRADG)) {
+        R gs = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+        asm volatile("" : "+v"(gs));  // formed here (see ops_at)
+        gacc += (double)gs;
+      }
+      if (ops & (OP_PHASE | OP_UNPHASE)) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const V tv = ltab[cv[r]];  // exp(-+i gamma C) times the scale correction
+          const R tc = tv.x, ts = tv.y;
+#pragma unroll
+          for (int s = 0; s < NS; ++s) {
+            if (s == 0 || lam_live) {
+              const V x = a[s][r];
+              a[s][r] = mkv<R>(x.x * tc - x.y * ts, x.x * ts + x.y * tc);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // Mixer routes (both start at the load arrangement LAST): ROUTE_FULL visits LAST, 0,
   // 1, ..., P; ROUTE_HIGH, for sets whose active qubits are all tile bits >= 4, skips
   // arrangement 0.  Mixer A walks the route forward and ends at the phase arrangement
   // P, mixer B walks it back to LAST.  A qubit is mixed at the first arrangement of the
   // walk that holds it in registers.
   template <int K, int PREV>
-  __device__ __forceinline__ void fwd_steps(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+  __device__ __forceinline__ void fwd_steps_rt(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
     if constexpr (K <= P) {
-      xchg<PREV, K>(lds);
-      mix_at<K>(todo, k, w, wcur, gr, gs);
-      fwd_steps<K + 1, K>(todo, k, w, wcur, gr, gs, lds);
+      xchg_rt<PREV, K>(lds);
+      mix_at_rt<K>(todo, k, w, wcur, gr, gs);
+      fwd_steps_rt<K + 1, K>(todo, k, w, wcur, gr, gs, lds);
     }
   }
   template <int K, int FIRST>
-  __device__ __forceinline__ void bwd_steps(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+  __device__ __forceinline__ void bwd_steps_rt(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
     if constexpr (K >= FIRST) {
-      xchg<K + 1, K>(lds);
-      mix_at<K>(todo, k, w, wcur, gr, gs);
-      bwd_steps<K - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
+      xchg_rt<K + 1, K>(lds);
+      mix_at_rt<K>(todo, k, w, wcur, gr, gs);
+      bwd_steps_rt<K - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
     }
   }
-  template <int RT> __device__ __forceinline__ void mix_fwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
-    mix_at<LAST>(todo, k, w, wcur, gr, gs);
-    fwd_steps<(RT == ROUTE_FULL ? 0 : 1), LAST>(todo, k, w, wcur, gr, gs, lds);
+  template <int RT> __device__ __forceinline__ void mix_fwd_rt(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+    mix_at_rt<LAST>(todo, k, w, wcur, gr, gs);
+    fwd_steps_rt<(RT == ROUTE_FULL ? 0 : 1), LAST>(todo, k, w, wcur, gr, gs, lds);
   }
-  template <int RT> __device__ __forceinline__ void mix_bwd(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
+  template <int RT> __device__ __forceinline__ void mix_bwd_rt(uint32_t& todo, R k, R w, R& wcur, bool gr, R& gs, V* lds) {
     constexpr int FIRST = (RT == ROUTE_FULL) ? 0 : 1;
-    mix_at<P>(todo, k, w, wcur, gr, gs);
-    bwd_steps<P - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
-    xchg<(FIRST < P ? FIRST : P), LAST>(lds);
-    mix_at<LAST>(todo, k, w, wcur, gr, gs);
+    mix_at_rt<P>(todo, k, w, wcur, gr, gs);
+    bwd_steps_rt<P - 1, FIRST>(todo, k, w, wcur, gr, gs, lds);
+    xchg_rt<(FIRST < P ? FIRST : P), LAST>(lds);
+    mix_at_rt<LAST>(todo, k, w, wcur, gr, gs);
   }
 
   // Executes program `pg` on the tile with id `tile` of set S (whose route is RT).
   // With `io` false the state stays in registers (whole state in one tile); stores still
   // happen when the program asks for them and a destination exists.
   template <int RT>
-  __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
+  __device__ __forceinline__ void run_rt(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                       const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
                                       double* zz_lds) {
     constexpr int KL = LAST;
@@ -484,30 +764,30 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     }
     const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
-    ops_at<KL>(pg.pre_ops, make_lam, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    ops_at_rt<KL>(pg.pre_ops, make_lam, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
     bool at_p = false;
     if (pg.mixA_dir) {
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      mix_fwd<RT>(todo, (R)sc.kA, (R)sc.wA, wcur, pg.mixA_grad != 0, gs, lds_x);
+      mix_fwd_rt<RT>(todo, (R)sc.kA, (R)sc.wA, wcur, pg.mixA_grad != 0, gs, lds_x);
       acc.ba += (double)gs;
       at_p = true;
     }
     if ((pg.mid_ops || pg.mixB_dir) && !at_p) {
-      xchg<KL, P>(lds_x);
+      xchg_rt<KL, P>(lds_x);
       at_p = true;
     }
-    ops_at<P>(pg.mid_ops, make_lam, S, tile_base, sc.F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
+    ops_at_rt<P>(pg.mid_ops, make_lam, S, tile_base, sc.F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
     if (pg.mixB_dir) {
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      mix_bwd<RT>(todo, (R)sc.kB, (R)sc.wB, wcur, pg.mixB_grad != 0, gs, lds_x);
+      mix_bwd_rt<RT>(todo, (R)sc.kB, (R)sc.wB, wcur, pg.mixB_grad != 0, gs, lds_x);
       acc.bb += (double)gs;
       at_p = false;
     }
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
-    if ((st_psi || st_lam) && at_p) xchg<P, KL>(lds_x);
+    if ((st_psi || st_lam) && at_p) xchg_rt<P, KL>(lds_x);
     if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N + tile_base + thread_off<KL>(S), S);
     if (st_lam) store_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
   }
@@ -515,9 +795,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
                                           const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,
                                           Acc& acc, double* zz_lds) {
     if (S.route == ROUTE_HIGH)
-      run<ROUTE_HIGH>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
+      run_rt<ROUTE_HIGH>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
     else
-      run<ROUTE_FULL>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
+      run_rt<ROUTE_FULL>(pg, S, sc, tile, cx, io, lds_x, ltab_pre, ltab_mid, acc, zz_lds);
   }
 };
 
@@ -590,9 +870,16 @@ template <class R> struct SweepArgs {
 };
 
 #define AAQ_TILE_BOUNDS __launch_bounds__(1 << (LT - kRegBits))
+// Specialized single-instance sweeps: at most 128 VGPRs per lane, i.e. four waves per
+// SIMD, the occupancy the tile LDS allows anyway; the generic sweeps are left to the
+// compiler.
+constexpr int sweep_waves_per_eu(uint32_t kind) { return (kind & SK_GENERIC) ? 1 : 4; }
+#define AAQ_SWEEP_BOUNDS(KIND) \
+  __launch_bounds__(1 << (LT - kRegBits)) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu(KIND))))
 
 // One workgroup per tile; partial sums per tile: partial[slot][tile].
-template <class R, int NS, bool PT, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS void k_sweep(SweepArgs<R> A) {
+template <class R, int NS, bool PT, bool EN, int RT, int LT, uint32_t KIND>
+__global__ AAQ_SWEEP_BOUNDS(KIND) void k_sweep(SweepArgs<R> A) {
   using G = Geo<R, LT>;
   using V = typename G::V;
   __shared__ V lds_x[lds_slot(G::TILE)];
@@ -614,14 +901,20 @@ template <class R, int NS, bool PT, bool EN, int RT, int LT> __global__ AAQ_TILE
   Acc acc;
   acc.zero();
   const uint32_t tile = blockIdx.x;
-  tl.template run<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
-  scale_acc(acc, A.prog, sc);
-  double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
-  block_sum<6, G::NT>(v, red);
+  if constexpr ((KIND & SK_GENERIC) != 0)
+    tl.template run_rt<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  else
+    tl.template run<RT, KIND>(A.prog, A.set, sc, tile, cx, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
   const uint32_t nt = A.set.ntiles;
-  if (threadIdx.x == 0) {
+  // only sweeps with an accumulating step write partial sums (the reduction reads no others)
+  if (((A.prog.pre_ops | A.prog.mid_ops) & (OP_ENERGY | OP_GRADG)) || A.prog.mixA_grad || A.prog.mixB_grad) {
+    scale_acc(acc, A.prog, sc);
+    double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+    block_sum<6, G::NT>(v, red);
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) A.partial[(size_t)i * nt + tile] = v[i];
+      for (int i = 0; i < 6; ++i) A.partial[(size_t)i * nt + tile] = v[i];
+    }
   }
   if (PT) {
     __syncthreads();
@@ -763,7 +1056,7 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
-  tl.template run<RT>(pg, S, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, nullptr);
+  tl.template run_rt<RT>(pg, S, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, nullptr);
   scale_acc(acc, pg, sc);
   double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
   block_sum<6, G::NT>(v, red);
@@ -805,21 +1098,42 @@ __global__ __launch_bounds__(1 << (LT - kRegBits)) void k_cuts(const GraphDev* g
 // ------------------------------------------------------------------------------------
 // Launch templates, instantiated once per (R, LT) by AAQ_INSTANTIATE_* in their own
 // translation units (see aaq_launch.h for the host-facing declarations).
+// a sweep kernel specialized for shape KIND (states, energy and per-term steps follow from it)
+template <class R, int RT, int LT, uint32_t KIND>
+static void sweep_launch_kind(const SweepArgs<R>& A, dim3 grid, dim3 blk, size_t dyn, hipStream_t st) {
+  constexpr int NS = (KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1;
+  constexpr bool EN = ((sk_pre(KIND) | sk_mid(KIND)) & OP_ENERGY) != 0;
+  constexpr bool PT = ((sk_pre(KIND) | sk_mid(KIND)) & OP_PERTERM) != 0;
+  hipLaunchKernelGGL((k_sweep<R, NS, PT, EN, RT, LT, KIND>), grid, blk, dyn, st, A);
+}
+
 template <class R, int RT, int LT>
 static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t dyn, hipStream_t st) {
   const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
   const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
   const dim3 grid(L.set.ntiles), blk(Geo<R, LT>::NT);
+  switch (sweep_kind(L.prog)) {
+    case SK_F_FIRST: return sweep_launch_kind<R, RT, LT, SK_F_FIRST>(A, grid, blk, dyn, st);
+    case SK_F_PLAIN: return sweep_launch_kind<R, RT, LT, SK_F_PLAIN>(A, grid, blk, dyn, st);
+    case SK_F_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_F_BOUNDARY>(A, grid, blk, dyn, st);
+    case SK_F_ENERGY: return sweep_launch_kind<R, RT, LT, SK_F_ENERGY>(A, grid, blk, dyn, st);
+    case SK_F_ENERGY_TERMS: return sweep_launch_kind<R, RT, LT, SK_F_ENERGY_TERMS>(A, grid, blk, dyn, st);
+    case SK_TURNAROUND: return sweep_launch_kind<R, RT, LT, SK_TURNAROUND>(A, grid, blk, dyn, st);
+    case SK_B_PLAIN: return sweep_launch_kind<R, RT, LT, SK_B_PLAIN>(A, grid, blk, dyn, st);
+    case SK_B_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY>(A, grid, blk, dyn, st);
+    case SK_B_LAST: return sweep_launch_kind<R, RT, LT, SK_B_LAST>(A, grid, blk, dyn, st);
+    default: break;
+  }
   if (pt)
-    hipLaunchKernelGGL((k_sweep<R, 1, true, true, RT, LT>), grid, blk, dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 1, true, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (L.two_states && en)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, true, RT, LT>), grid, blk, dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 2, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (L.two_states)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, false, RT, LT>), grid, blk, dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 2, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (en)
-    hipLaunchKernelGGL((k_sweep<R, 1, false, true, RT, LT>), grid, blk, dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 1, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else
-    hipLaunchKernelGGL((k_sweep<R, 1, false, false, RT, LT>), grid, blk, dyn, st, A);
+    hipLaunchKernelGGL((k_sweep<R, 1, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
 }
 
 template <class R, int LT> hipError_t sweep_launch_impl(const LaunchSweep& L, hipStream_t st) {

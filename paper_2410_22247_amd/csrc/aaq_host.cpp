@@ -324,14 +324,20 @@ int chosen_tile_bits(int n, bool dbl, bool grad) {
   return it == g_tune.end() ? auto_tile_bits(n) : it->second;
 }
 
-// Set of sweep i: a zig-zag k-1, ..., 1, 0, 1, ..., k-1, ... that starts at the last set,
-// so the first sweep (which synthesises |+>) and the last forward sweep (the turnaround)
-// fall on a set of high qubits, whose mixer needs one LDS transpose fewer than set 0's.
+// Set of forward sweep i.  Positions i = 0, k-1, 2(k-1), ... are the layer boundaries
+// (plus the first and the last sweep): such a sweep mixes the end of one layer and the
+// start of the next (or the first / last part of the circuit) on one set.  With k >= 3
+// they alternate between sets 1 and 2, and the k-2 sweeps between two of them mix the
+// other sets (0, 3, ..., k-1), each once: every layer then visits every set exactly once,
+// and set 0, whose twelve- or thirteen-qubit mixer needs the most work and transposes,
+// only ever gets a plain sweep (one mixer, no phase).  With k = 2 the boundaries
+// alternate between sets 1 and 0.
 int zig(int i, int k) {
   if (k == 1) return 0;
-  const int per = 2 * (k - 1);
-  const int m = i % per;
-  return (k - 1) - ((m <= k - 1) ? m : per - m);
+  const int seg = i / (k - 1), pos = i % (k - 1);
+  if (k == 2) return (seg % 2 == 0) ? 1 : 0;
+  if (pos == 0) return (seg % 2 == 0) ? 1 : 2;
+  return pos == 1 ? 0 : pos + 1;  // plain sweeps: sets 0, 3, 4, ..., k-1
 }
 
 SweepProg blank() {

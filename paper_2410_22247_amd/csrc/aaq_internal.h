@@ -9,6 +9,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <initializer_list>
+
 namespace aaq {
 
 constexpr int kMaxN = 34;
@@ -51,6 +53,36 @@ enum : uint8_t {
   F_MAKE_LAM = 64   // OP_ENERGY creates lambda = h psi
 };
 
+// Compile-time shape of a sweep (the steps it has), used to specialize the sweep
+// kernels so that no step is a run-time branch around register updates.  Bits 0-7:
+// structure; bits 8-15: the ops at the load position; bits 16-23: the ops at the
+// phase position.  SK_GENERIC: every decision is taken from the SweepProg at run time.
+enum : uint32_t {
+  SK_INIT = 1u << 0,      // synthesise |+>
+  SK_LOAD_PSI = 1u << 1,  // load psi
+  SK_LAM_IN = 1u << 2,    // load lambda, live from the start
+  SK_MIXA = 1u << 3,
+  SK_MIXB = 1u << 4,
+  SK_MAKE_LAM = 1u << 5,  // the energy step creates lambda
+  SK_GENERIC = 1u << 31
+};
+constexpr uint32_t sk_pre(uint32_t kind) { return (kind >> 8) & 0xFFu; }
+constexpr uint32_t sk_mid(uint32_t kind) { return (kind >> 16) & 0xFFu; }
+constexpr uint32_t sk_make(uint32_t bits, uint32_t pre_ops, uint32_t mid_ops) {
+  return bits | (pre_ops << 8) | (mid_ops << 16);
+}
+// the shapes of the multi-set sweep programs (first, plain, layer-boundary and last
+// forward sweeps; the turnaround; plain, layer-boundary and last backward sweeps)
+constexpr uint32_t SK_F_FIRST = sk_make(SK_INIT | SK_MIXA, OP_PHASE, 0);
+constexpr uint32_t SK_F_PLAIN = sk_make(SK_LOAD_PSI | SK_MIXA, 0, 0);
+constexpr uint32_t SK_F_BOUNDARY = sk_make(SK_LOAD_PSI | SK_MIXA | SK_MIXB, 0, OP_PHASE);
+constexpr uint32_t SK_F_ENERGY = sk_make(SK_LOAD_PSI | SK_MIXA, 0, OP_ENERGY);
+constexpr uint32_t SK_F_ENERGY_TERMS = sk_make(SK_LOAD_PSI | SK_MIXA, 0, OP_ENERGY | OP_PERTERM);
+constexpr uint32_t SK_TURNAROUND = sk_make(SK_LOAD_PSI | SK_MIXA | SK_MIXB | SK_MAKE_LAM, 0, OP_ENERGY);
+constexpr uint32_t SK_B_PLAIN = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA, 0, 0);
+constexpr uint32_t SK_B_BOUNDARY = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA | SK_MIXB, 0, OP_GRADG | OP_UNPHASE);
+constexpr uint32_t SK_B_LAST = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA, 0, OP_GRADG);
+
 // partial-sum slots written per sweep and tile
 enum : int { SLOT_E = 0, SLOT_NORM = 1, SLOT_GPRE = 2, SLOT_GMID = 3, SLOT_BA = 4, SLOT_BB = 5, SLOT_TERMS = 6 };
 
@@ -91,6 +123,23 @@ struct SweepProg {
   uint8_t st_buf;  // forward-state checkpoints, where sweep i stores buffer i
 };
 constexpr int kMaxCkpt = 32;  // max psi buffers of a checkpointed program
+
+// shape of a sweep program (stores and buffer indices stay run-time values)
+inline uint32_t sweep_kind(const SweepProg& s) {
+  uint32_t b = 0;
+  if (s.flags & F_INIT) b |= SK_INIT;
+  if (s.flags & F_LOAD_PSI) b |= SK_LOAD_PSI;
+  if ((s.flags & F_LOAD_LAM) && (s.flags & F_LAM_LIVE)) b |= SK_LAM_IN;
+  else if (s.flags & (F_LOAD_LAM | F_LAM_LIVE)) return SK_GENERIC;
+  if (s.mixA_dir) b |= SK_MIXA;
+  if (s.mixB_dir) b |= SK_MIXB;
+  if (s.flags & F_MAKE_LAM) b |= SK_MAKE_LAM;
+  const uint32_t k = sk_make(b, s.pre_ops, s.mid_ops);
+  for (uint32_t known : {SK_F_FIRST, SK_F_PLAIN, SK_F_BOUNDARY, SK_F_ENERGY, SK_F_ENERGY_TERMS, SK_TURNAROUND,
+                         SK_B_PLAIN, SK_B_BOUNDARY, SK_B_LAST})
+    if (k == known) return k;
+  return SK_GENERIC;
+}
 
 // Per-sweep scale record.  Mixer gates are applied as (I - i k X) per qubit, with
 // |k| <= 1; the dropped scalar factor phi per qubit (cos b, or +-i sin b together with
