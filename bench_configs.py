@@ -11,6 +11,10 @@ c5a  random tree n=34, p=1, complex64 forward energy (2^34 amplitudes, 128 GiB) 
      H_red and H_C; parity against the p=1 closed form.
 c5b  random tree n=33, p=2, energy + adjoint gradient (two 64 GiB states); parity
      against the light-cone FP64 adjoint.
+lc   light-cone evaluation (each orbit representative's <ZZ> on its distance-p cone, one
+     batched plan per instance) of the n=26 p=4, n=34 p=1 and n=33 p=2 trees: energy +
+     gradient evals/s for H_red and H_C against the full-state sweeps, parity against the
+     light-cone FP64 adjoint.
 """
 import math
 import time
@@ -173,6 +177,37 @@ def c5b(args):
     return {"workload": "c5b: random tree n=33 (seed 5) p=2, complex64 energy + adjoint gradient", "results": res}
 
 
+def lc(args):
+    from oracle import reduced as R
+
+    res = {}
+    for name, fn, npts in (("c3 n=26 p=4", C.config3, 8), ("c5a n=34 p=1", C.config5a, 8),
+                           ("c5b n=33 p=2", C.config5b, 4)):
+        wp, p, gam, bet = fn(npts)
+        pr = A.Problem.from_workload(wp)
+        r = {}
+        for oname, obs in (("H_red", A.AAQ_OBS_HRED), ("H_C", A.AAQ_OBS_HC)):
+            L = A.LightCone(pr, p, obs, with_grad=True)
+            L.params.copy_(torch.from_numpy(np.concatenate([gam[0], bet[0]])))
+            reps = 200 if wp.n != 26 else 50
+            dt = _timed(L.execute, reps)
+            errs_e, errs_g = [], []
+            for k in range(min(npts, 4)):
+                e, dg, db, _ = L.energy_grad(gam[k], bet[k])
+                e_lc, dg_lc, db_lc, _ = R.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(obs), gam[k], bet[k])
+                g, gr = np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc])
+                errs_e.append(abs(e - e_lc) / abs(e_lc))
+                errs_g.append(float(np.linalg.norm(g - gr) / np.linalg.norm(gr)))
+            r[oname] = {"units": L.units, "max_cone_qubits": L.max_qubits, "cone_amplitudes": L.amplitudes,
+                        "evals_s": round(1.0 / dt, 1), "max_rel_err_energy": float(max(errs_e)),
+                        "max_rel_err_grad": float(max(errs_g))}
+            L.close()
+        r["speedup_Hred_over_HC"] = round(r["H_red"]["evals_s"] / r["H_C"]["evals_s"], 3)
+        res[name] = r
+    return {"workload": "lc: light-cone x orbit evaluation (energy + adjoint gradient, complex64), device-resident "
+                        "parameters and outputs, graph replay", "unit": "evals/s", "results": res}
+
+
 def run(name, args):
     torch.cuda.set_device(0)
-    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b}[name](args)
+    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc}[name](args)

@@ -237,6 +237,38 @@ aaq_status aaq_plan_autotune(const aaq_problem *probs, int count, int p, aaq_obs
                              const aaq_plan_opts *base, void *d_ws, size_t ws_bytes, const double *d_params,
                              double *d_out, void *stream, int reps, aaq_plan_opts *best, double *best_ms);
 
+/* ---------------------------------------------------------------- light cones
+ * Light-cone evaluation, the locality reduction the paper names as compounding with the
+ * orbit reduction (its discussion of reverse causal cones): the depth-p expectation of a
+ * term Z_i Z_j depends only on the subgraph induced by the vertices within distance p of
+ * {i, j}, exactly.  Each term of the observable (H_C: every edge, weight 1; H_red: one
+ * representative per edge orbit, weight = orbit size) is simulated on its own cone as one
+ * unit of a batched plan (the kernels above), and
+ *   <H> = sum_t (w_t / 2) (1 - <Z_i Z_j>_t)
+ * together with its gradient are the sums over the units.  Cones are built on the host by
+ * breadth-first search; vertices keep their order, relabelled 0..|cone|-1.
+ *   d_params  device double[2p]: gamma_0..gamma_{p-1}, beta_0..beta_{p-1}
+ *   d_out     device double[2 + 2p]: energy, mean norm of the unit states, dE/dgamma[p],
+ *             dE/dbeta[p] (gradients only when with_grad)
+ * Errors as for the plans; AAQ_ERR_UNSUPPORTED for a graph without edges.  The handle
+ * owns its unit descriptions; the workspace is the caller's. */
+typedef struct aaq_lightcone aaq_lightcone;
+
+/* Host only: number of units (terms), the largest cone (qubits) and the total number of
+ * amplitudes of all cone states (sum over units of 2^|cone|). */
+aaq_status aaq_lightcone_info(const aaq_problem *prob, int p, aaq_observable obs, int *units, int *max_qubits,
+                              double *amplitudes);
+aaq_status aaq_lightcone_workspace_size(const aaq_problem *prob, int p, aaq_observable obs, int with_grad,
+                                        const aaq_plan_opts *opts, size_t *bytes);
+/* Builds the cones and their plan (opts as for aaq_plan_create) and uploads it on `stream`. */
+aaq_status aaq_lightcone_create(const aaq_problem *prob, int p, aaq_observable obs, int with_grad,
+                                const aaq_plan_opts *opts, void *d_ws, size_t ws_bytes, void *stream,
+                                aaq_lightcone **out);
+/* Asynchronous on `stream`; with opts.use_graph the launches are captured once per
+ * (d_params, d_out, stream) and replayed. */
+aaq_status aaq_lightcone_execute(aaq_lightcone *lc, const double *d_params, double *d_out, void *stream);
+void aaq_lightcone_destroy(aaq_lightcone *lc);
+
 /* ---------------------------------------------------------------- diagnostics */
 /* Per-kernel timing.  While enabled, every kernel launch of the library is bracketed
  * by two HIP events recorded on the stream it is launched on; aaq_timing_read waits

@@ -45,7 +45,8 @@ EXPORTS = (
     "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
     "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
     "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
-    "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed",
+    "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed", "aaq_lightcone_info",
+    "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
 )
 
 
@@ -88,6 +89,11 @@ def lib():
         "aaq_autotune": (i, [P, i, i, i, i, vp, sz, vp, sz, vp, sz, vp, i, ctypes.POINTER(i), dp]),
         "aaq_plan_autotune": (i, [P, i, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, vp, vp, i,
                                   ctypes.POINTER(CPlanOpts), dp]),
+        "aaq_lightcone_info": (i, [P, i, i, ctypes.POINTER(i), ctypes.POINTER(i), dp]),
+        "aaq_lightcone_workspace_size": (i, [P, i, i, i, ctypes.POINTER(CPlanOpts), szp]),
+        "aaq_lightcone_create": (i, [P, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, ctypes.POINTER(vp)]),
+        "aaq_lightcone_execute": (i, [vp, vp, vp, vp]),
+        "aaq_lightcone_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

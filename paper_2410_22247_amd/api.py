@@ -290,6 +290,42 @@ def aaq_plan_destroy(plan) -> None:
         _lib.lib().aaq_plan_destroy(plan)
 
 
+def aaq_lightcone_info(prob: Problem, p: int, obs: int = AAQ_OBS_HRED):
+    """(units, largest cone in qubits, total amplitudes of all cone states)."""
+    u, mq, amp = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(_lib.lib().aaq_lightcone_info(prob.ref(), int(p), int(obs), ctypes.byref(u), ctypes.byref(mq),
+                                         ctypes.byref(amp)))
+    return u.value, mq.value, amp.value
+
+
+def aaq_lightcone_workspace_size(prob: Problem, p: int, obs: int, with_grad: bool, **opts) -> int:
+    o = _opts(**opts)
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_lightcone_workspace_size(prob.ref(), int(p), int(obs), int(bool(with_grad)), ctypes.byref(o),
+                                                   ctypes.byref(out)))
+    return out.value
+
+
+def aaq_lightcone_create(prob: Problem, p: int, obs: int, with_grad: bool, d_ws, stream=None, **opts):
+    o = _opts(**opts)
+    wp, wb = _dev(d_ws)
+    h = ctypes.c_void_p()
+    _check(_lib.lib().aaq_lightcone_create(prob.ref(), int(p), int(obs), int(bool(with_grad)), ctypes.byref(o), wp, wb,
+                                           _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def aaq_lightcone_execute(handle, d_params, d_out, stream=None) -> None:
+    pp, _ = _dev(d_params)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_lightcone_execute(handle, pp, op, _stream(stream)))
+
+
+def aaq_lightcone_destroy(handle) -> None:
+    if handle:
+        _lib.lib().aaq_lightcone_destroy(handle)
+
+
 def aaq_timing_enable(on: bool) -> None:
     _check(_lib.lib().aaq_timing_enable(int(bool(on))))
 
@@ -387,6 +423,47 @@ class Plan:
     def close(self):
         if self.handle:
             aaq_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LightCone:
+    """Light-cone evaluation of one instance (aaq_lightcone_*): owns the workspace and
+    the parameter / output buffers (torch)."""
+
+    def __init__(self, prob: Problem, p: int, obs: int = AAQ_OBS_HRED, with_grad: bool = True, device: str = "cuda",
+                 stream=None, **opts):
+        import torch
+
+        self.prob, self.p, self.obs, self.with_grad = prob, int(p), obs, with_grad
+        self.units, self.max_qubits, self.amplitudes = aaq_lightcone_info(prob, p, obs)
+        wb = aaq_lightcone_workspace_size(prob, p, obs, with_grad, **opts)
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.handle = aaq_lightcone_create(prob, p, obs, with_grad, self.ws, stream, **opts)
+        self.params = torch.zeros(2 * self.p, dtype=torch.float64, device=device)
+        self.out = torch.zeros(2 + 2 * self.p, dtype=torch.float64, device=device)
+
+    def execute(self, stream=None):
+        aaq_lightcone_execute(self.handle, self.params, self.out, stream)
+        return self.out
+
+    def energy_grad(self, gamma, beta, stream=None):
+        """Synchronous convenience: (energy, dE/dgamma, dE/dbeta, mean norm) as numpy."""
+        import torch
+
+        g, b = _params(gamma, beta)
+        self.params.copy_(torch.from_numpy(np.concatenate([g, b])))
+        o = self.execute(stream).cpu().numpy()
+        return o[0], o[2:2 + self.p].copy(), o[2 + self.p:].copy(), o[1]
+
+    def close(self):
+        if self.handle:
+            aaq_lightcone_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

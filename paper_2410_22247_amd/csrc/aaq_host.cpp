@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <set>
 #include <string>
@@ -205,10 +206,13 @@ void add_term_lists(SetSpec& s, int L, const std::vector<int4>& terms, std::vect
 }
 
 // plain term list followed by every set's sorted lists (the device term array)
-std::vector<int4> term_array(const aaq_problem* pr, aaq_observable obs, int L, std::vector<SetSpec>& sets) {
-  std::vector<int4> terms = make_terms(pr, obs), ext = terms;
+std::vector<int4> term_array_of(const std::vector<int4>& terms, int L, std::vector<SetSpec>& sets) {
+  std::vector<int4> ext = terms;
   for (SetSpec& s : sets) add_term_lists(s, L, terms, ext);
   return ext;
+}
+std::vector<int4> term_array(const aaq_problem* pr, aaq_observable obs, int L, std::vector<SetSpec>& sets) {
+  return term_array_of(make_terms(pr, obs), L, sets);
 }
 
 // ------------------------------------------------------------------ sweep planner
@@ -795,8 +799,11 @@ aaq_status check_opts(const aaq_plan_opts& o) {
   return AAQ_OK;
 }
 
+// unit_terms: when given, unit i observes the weighted term list unit_terms[i] (vertex
+// pairs of its own graph) instead of the problem's H_C / H_red terms; its problem then
+// carries no orbit list (internal units of the light-cone evaluation).
 aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observable obs, bool grad, const aaq_plan_opts& o,
-                       PlanLayout& PL) {
+                       PlanLayout& PL, const std::vector<std::vector<int4>>* unit_terms = nullptr) {
   if (!probs || count < 1) return fail(AAQ_ERR_INVALID_ARG, "probs is NULL or count < 1");
   aaq_status st = validate_p(p);
   if (st) return st;
@@ -804,10 +811,12 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   const bool dbl = o.prec == AAQ_PREC_C128;
   const size_t amp = dbl ? 16 : 8;
-  for (int i = 0; i < count; ++i) {
-    if ((st = validate_problem(&probs[i]))) {
-      g_err = "unit " + std::to_string(i) + ": " + g_err;
-      return st;
+  if (!unit_terms) {
+    for (int i = 0; i < count; ++i) {
+      if ((st = validate_problem(&probs[i]))) {
+        g_err = "unit " + std::to_string(i) + ": " + g_err;
+        return st;
+      }
     }
   }
   // shared graph blocks: identical instance arrays (at the same tile size) are stored once
@@ -826,23 +835,24 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.n = pr->n;
     D.p = p;
     D.row = i;
-    D.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
+    D.T = unit_terms ? (int)(*unit_terms)[i].size() : (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
     D.cmax = pr->num_edges;
     D.L = unit_tile_bits(pr->n, o);
     auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size, (int)D.L);
-    auto it = gmap.find(key);
+    auto it = unit_terms ? gmap.end() : gmap.find(key);
     if (it == gmap.end()) {
       GraphDev g = make_graph(pr);
       g.T = D.T;
-      g.h_is_cut = obs == AAQ_OBS_HC;
+      g.h_is_cut = !unit_terms && obs == AAQ_OBS_HC;
       std::vector<SetSpec> sets = make_sets(pr->n, D.L);
-      std::vector<int4> t = term_array(pr, obs, D.L, sets);
+      std::vector<int4> t = unit_terms ? term_array_of((*unit_terms)[i], D.L, sets) : term_array(pr, obs, D.L, sets);
       int64_t goff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(GraphDev)));
       std::memcpy(PL.blob.data() + goff, &g, sizeof(g));
       int64_t toff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(int4) * std::max<size_t>(t.size(), 1)));
       if (!t.empty()) std::memcpy(PL.blob.data() + toff, t.data(), sizeof(int4) * t.size());
+      if (unit_terms) std::get<0>(key) = (const int32_t*)(intptr_t)(-1 - i);  // never shared
       it = gmap.emplace(key, GraphEntry{goff, toff, sets}).first;
     }
     D.graph_off = it->second.goff;  // relative to the graph area; fixed up below
@@ -910,6 +920,10 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   for (auto& kv : by_group) PL.group_units.emplace_back(kv.first.first, kv.second);
   return AAQ_OK;
 }
+
+aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
+                            const aaq_plan_opts* opts, void* d_ws, size_t ws_bytes, void* stream, aaq_plan** out,
+                            const std::vector<std::vector<int4>>* unit_terms);
 
 aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipStream_t hs) {
   LaunchUnits U;
@@ -1153,12 +1167,21 @@ aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, a
 
 aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
                            const aaq_plan_opts* opts, void* d_ws, size_t ws_bytes, void* stream, aaq_plan** out) {
+  return plan_create_impl(probs, count, p, obs, with_grad, opts, d_ws, ws_bytes, stream, out, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
+                            const aaq_plan_opts* opts, void* d_ws, size_t ws_bytes, void* stream, aaq_plan** out,
+                            const std::vector<std::vector<int4>>* unit_terms) {
   if (!out) return fail(AAQ_ERR_INVALID_ARG, "out is NULL");
   aaq_plan_opts o;
   aaq_plan_default_opts(&o);
   if (opts) o = *opts;
   PlanLayout PL;
-  aaq_status s = plan_layout(probs, count, p, obs, with_grad != 0, o, PL);
+  aaq_status s = plan_layout(probs, count, p, obs, with_grad != 0, o, PL, unit_terms);
   if (s) return s;
   if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
   if (ws_bytes < PL.total) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(PL.total) + " bytes)");
@@ -1222,6 +1245,9 @@ aaq_status aaq_plan_create(const aaq_problem* probs, int count, int p, aaq_obser
   *out = P;
   return AAQ_OK;
 }
+}  // namespace
+
+extern "C" {
 
 aaq_status aaq_plan_execute(aaq_plan* P, const double* d_params, double* d_out, void* stream) {
   if (!P || !d_params || !d_out) return fail(AAQ_ERR_INVALID_ARG, "plan / d_params / d_out is NULL");
@@ -1253,6 +1279,221 @@ aaq_status aaq_plan_execute(aaq_plan* P, const double* d_params, double* d_out, 
   }
   HIPCHK(hipGraphLaunch(P->exec, hs));
   return AAQ_OK;
+}
+
+// ====================================================================== light cones
+}  // extern "C"
+
+// <Z_i Z_j> of the depth-p ansatz depends only on the subgraph induced by the vertices
+// within distance p of {i, j}: conjugating Z_i Z_j by the layers from the last one back,
+// every cost gate on an edge that does not touch the current support commutes with it,
+// so the support grows by one neighbourhood per layer (the paper's reverse causal cone).
+// Each observable term (every edge with weight 1 for H_C; one representative per edge
+// orbit, weighted by the orbit size, for H_red) is evaluated on its own cone as one unit
+// of a batched plan; the energy and gradient are the sums over the units.
+struct aaq_lightcone {
+  aaq_plan* plan = nullptr;
+  int count = 0, p = 0;
+  bool grad = false;
+  unsigned char* ws = nullptr;
+  size_t params_off = 0, rows_off = 0;
+  std::vector<std::vector<int32_t>> edges;  // owned edge lists of the units
+  std::vector<aaq_problem> probs;
+  bool use_graph = true;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  const double* g_params = nullptr;
+  double* g_out = nullptr;
+  hipStream_t g_stream = nullptr;
+};
+
+namespace {
+
+struct Cones {
+  std::vector<int> n;                       // qubits of each unit
+  std::vector<std::vector<int32_t>> edges;  // relabelled edge list of each unit
+  std::vector<std::vector<int4>> terms;     // the unit's single weighted term
+};
+
+aaq_status build_cones(const aaq_problem* pr, int p, aaq_observable obs, Cones& C) {
+  aaq_status st = validate_problem(pr);
+  if (st) return st;
+  if ((st = validate_p(p))) return st;
+  if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
+  if (pr->num_edges == 0) return fail(AAQ_ERR_UNSUPPORTED, "a graph without edges has no observable terms");
+  const int n = pr->n, m = pr->num_edges;
+  std::vector<std::vector<int>> nb(n);
+  for (int e = 0; e < m; ++e) {
+    nb[pr->edges[2 * e]].push_back(pr->edges[2 * e + 1]);
+    nb[pr->edges[2 * e + 1]].push_back(pr->edges[2 * e]);
+  }
+  for (const int4& t : make_terms(pr, obs)) {
+    std::vector<int> dist(n, -1), q{t.x, t.y};
+    dist[t.x] = dist[t.y] = 0;
+    for (size_t h = 0; h < q.size(); ++h) {  // breadth-first search to depth p
+      const int v = q[h];
+      if (dist[v] == p) continue;
+      for (int w : nb[v])
+        if (dist[w] < 0) {
+          dist[w] = dist[v] + 1;
+          q.push_back(w);
+        }
+    }
+    std::vector<int> idx(n, -1);
+    int k = 0;
+    for (int v = 0; v < n; ++v)
+      if (dist[v] >= 0) idx[v] = k++;
+    std::vector<int32_t> es;
+    for (int e = 0; e < m; ++e) {
+      const int u = idx[pr->edges[2 * e]], v = idx[pr->edges[2 * e + 1]];
+      if (u >= 0 && v >= 0) {
+        es.push_back(u);
+        es.push_back(v);
+      }
+    }
+    C.n.push_back(k);
+    C.edges.push_back(std::move(es));
+    C.terms.push_back({make_int4(idx[t.x], idx[t.y], t.z, 0)});
+  }
+  return AAQ_OK;
+}
+
+std::vector<aaq_problem> cone_problems(const Cones& C) {
+  std::vector<aaq_problem> v(C.n.size());
+  for (size_t i = 0; i < v.size(); ++i) {
+    std::memset(&v[i], 0, sizeof(aaq_problem));
+    v[i].n = C.n[i];
+    v[i].num_edges = (int32_t)(C.edges[i].size() / 2);
+    v[i].edges = C.edges[i].data();
+  }
+  return v;
+}
+
+size_t lc_extra_bytes(int count, int p) {
+  return align_up(sizeof(double) * (size_t)count * 2 * p) + align_up(sizeof(double) * (size_t)count * (2 + 2 * p));
+}
+
+aaq_status lc_launch(aaq_lightcone* LC, const double* d_params, double* d_out, hipStream_t hs) {
+  double* uparams = (double*)(LC->ws + LC->params_off);
+  double* rows = (double*)(LC->ws + LC->rows_off);
+  HIPCHK(launch_lc_bcast(d_params, 2 * LC->p, uparams, LC->count, hs));
+  aaq_status st = plan_launch(LC->plan, uparams, rows, hs);
+  if (st) return st;
+  HIPCHK(launch_lc_sum(rows, LC->count, 2 + 2 * LC->p, d_out, hs));
+  return AAQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+aaq_status aaq_lightcone_info(const aaq_problem* prob, int p, aaq_observable obs, int* units, int* max_qubits,
+                              double* amplitudes) {
+  Cones C;
+  aaq_status st = build_cones(prob, p, obs, C);
+  if (st) return st;
+  int mx = 0;
+  double amp = 0.0;
+  for (int k : C.n) {
+    mx = std::max(mx, k);
+    amp += std::ldexp(1.0, k);
+  }
+  if (units) *units = (int)C.n.size();
+  if (max_qubits) *max_qubits = mx;
+  if (amplitudes) *amplitudes = amp;
+  return AAQ_OK;
+}
+
+aaq_status aaq_lightcone_workspace_size(const aaq_problem* prob, int p, aaq_observable obs, int with_grad,
+                                        const aaq_plan_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  Cones C;
+  aaq_status st = build_cones(prob, p, obs, C);
+  if (st) return st;
+  aaq_plan_opts o;
+  aaq_plan_default_opts(&o);
+  if (opts) o = *opts;
+  std::vector<aaq_problem> probs = cone_problems(C);
+  PlanLayout PL;
+  if ((st = plan_layout(probs.data(), (int)probs.size(), p, obs, with_grad != 0, o, PL, &C.terms))) return st;
+  *bytes = align_up(PL.total) + lc_extra_bytes((int)probs.size(), p);
+  return AAQ_OK;
+}
+
+aaq_status aaq_lightcone_create(const aaq_problem* prob, int p, aaq_observable obs, int with_grad,
+                                const aaq_plan_opts* opts, void* d_ws, size_t ws_bytes, void* stream,
+                                aaq_lightcone** out) {
+  if (!out) return fail(AAQ_ERR_INVALID_ARG, "out is NULL");
+  if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
+  auto LC = std::make_unique<aaq_lightcone>();
+  Cones C;
+  aaq_status st = build_cones(prob, p, obs, C);
+  if (st) return st;
+  aaq_plan_opts o;
+  aaq_plan_default_opts(&o);
+  if (opts) o = *opts;
+  LC->edges = C.edges;  // owned copies: the unit problems point into these
+  LC->probs = cone_problems(C);
+  for (size_t i = 0; i < LC->probs.size(); ++i) LC->probs[i].edges = LC->edges[i].data();
+  LC->count = (int)LC->probs.size();
+  LC->p = p;
+  LC->grad = with_grad != 0;
+  LC->use_graph = o.use_graph != 0;
+  PlanLayout PL;
+  if ((st = plan_layout(LC->probs.data(), LC->count, p, obs, LC->grad, o, PL, &C.terms))) return st;
+  const size_t plan_bytes = align_up(PL.total);
+  const size_t need = plan_bytes + lc_extra_bytes(LC->count, p);
+  if (ws_bytes < need) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(need) + " bytes)");
+  LC->ws = (unsigned char*)d_ws;
+  LC->params_off = plan_bytes;
+  LC->rows_off = plan_bytes + align_up(sizeof(double) * (size_t)LC->count * 2 * p);
+  aaq_plan_opts po = o;
+  po.use_graph = 0;  // the light-cone handle captures its own graph around the plan
+  if ((st = plan_create_impl(LC->probs.data(), LC->count, p, obs, with_grad, &po, d_ws, plan_bytes, stream, &LC->plan,
+                             &C.terms)))
+    return st;
+  *out = LC.release();
+  return AAQ_OK;
+}
+
+aaq_status aaq_lightcone_execute(aaq_lightcone* LC, const double* d_params, double* d_out, void* stream) {
+  if (!LC || !d_params || !d_out) return fail(AAQ_ERR_INVALID_ARG, "handle / d_params / d_out is NULL");
+  hipStream_t hs = (hipStream_t)stream;
+  if (!LC->use_graph || hs == nullptr) return lc_launch(LC, d_params, d_out, hs);
+  if (!LC->exec || LC->g_params != d_params || LC->g_out != d_out || LC->g_stream != hs) {
+    if (LC->exec) {
+      (void)hipGraphExecDestroy(LC->exec);
+      LC->exec = nullptr;
+    }
+    if (LC->graph) {
+      (void)hipGraphDestroy(LC->graph);
+      LC->graph = nullptr;
+    }
+    HIPCHK(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+    aaq_status s = lc_launch(LC, d_params, d_out, hs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(hs, &g);
+    if (s) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(AAQ_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    LC->graph = g;
+    HIPCHK(hipGraphInstantiate(&LC->exec, g, nullptr, nullptr, 0));
+    LC->g_params = d_params;
+    LC->g_out = d_out;
+    LC->g_stream = hs;
+  }
+  HIPCHK(hipGraphLaunch(LC->exec, hs));
+  return AAQ_OK;
+}
+
+void aaq_lightcone_destroy(aaq_lightcone* LC) {
+  if (!LC) return;
+  if (LC->exec) (void)hipGraphExecDestroy(LC->exec);
+  if (LC->graph) (void)hipGraphDestroy(LC->graph);
+  aaq_plan_destroy(LC->plan);
+  delete LC;
 }
 
 // ====================================================================== tuning

@@ -277,6 +277,22 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
 // exact integer diagonal values through the same per-amplitude code as the kernels,
 // computed at arrangement K (0: load arrangement, 1: phase arrangement) of set S
 
+// light-cone units: the shared (gamma, beta) into every unit's parameter row, and the
+// fixed-order sum of the unit outputs (energy and gradients summed, norm averaged)
+__global__ __launch_bounds__(256) void k_lc_bcast(const double* __restrict__ params, int np, double* __restrict__ rows,
+                                                  int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count * np) rows[i] = params[i % np];
+}
+__global__ __launch_bounds__(256) void k_lc_sum(const double* __restrict__ rows, int count, int stride,
+                                                double* __restrict__ out) {
+  const int o = threadIdx.x;
+  if (o >= stride) return;
+  double s = 0.0;
+  for (int u = 0; u < count; ++u) s += rows[(size_t)u * stride + o];
+  out[o] = (o == 1) ? s / count : s;
+}
+
 // ------------------------------------------------------------------------------------
 // launch functions used by the host code
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
@@ -289,6 +305,18 @@ hipError_t launch_tables(const double* gamma, const double* beta, int p, int cma
   else
     hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
                        reinterpret_cast<float2*>(tab), progs, nsweep, sets, nsets, scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_lc_bcast(const double* params, int np, double* rows, int count, hipStream_t st) {
+  const int tot = count * np;
+  hipLaunchKernelGGL(k_lc_bcast, dim3((tot + 255) / 256), dim3(256), 0, st, params, np, rows, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_lc_sum(const double* rows, int count, int stride, double* out, hipStream_t st) {
+  if (stride > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lc_sum, dim3(1), dim3(256), 0, st, rows, count, stride, out);
   return hipGetLastError();
 }
 

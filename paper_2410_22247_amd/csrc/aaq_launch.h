@@ -56,6 +56,10 @@ hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, 
 hipError_t launch_tables(const double* gamma, const double* beta, int p, int cmax, void* tab, const SweepProg* progs,
                          int nsweep, const SetSpec* sets, int nsets, SwScale* scales, bool dbl, hipStream_t st);
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st);
+// light-cone units: copy the shared parameters [np] into every unit row; sum the unit
+// output rows [count][stride] in unit order (column 1, the norm, is averaged)
+hipError_t launch_lc_bcast(const double* params, int np, double* rows, int count, hipStream_t st);
+hipError_t launch_lc_sum(const double* rows, int count, int stride, double* out, hipStream_t st);
 // fixed-order sums of per-tile partials; stage holds nout * kReduceChunks doubles
 constexpr int kReduceChunks = 32;
 hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* stage, double* out,
