@@ -237,6 +237,26 @@ aaq_status aaq_plan_autotune(const aaq_problem *probs, int count, int p, aaq_obs
                              const aaq_plan_opts *base, void *d_ws, size_t ws_bytes, const double *d_params,
                              double *d_out, void *stream, int reps, aaq_plan_opts *best, double *best_ms);
 
+/* ---------------------------------------------------------------- edge orbits
+ * Edge orbits of Aut(G) on the host (the paper's Algorithm 1 with its generator source,
+ * nauty in the paper, replaced by an individualisation-refinement search): the edge list
+ * is closed under automorphism generators by breadth-first search, each class seeded at
+ * its lowest-index edge (with a sorted edge list, exactly Algorithm 1's order); whenever
+ * two classes whose seed edges have equal colour-refinement invariants are apart, the
+ * search looks for an automorphism mapping one seed onto the other.  The result is the
+ * orbit partition under the whole group Aut(G).
+ *   edges       [2 * num_edges] (u, v) pairs, any order; 0 <= u, v < n, u != v, no duplicates
+ *   orbit_of    out [num_edges]: class of each edge
+ *   num_orbits  out: number of classes
+ *   orbit_rep   out [num_edges] (first *num_orbits used): seed edge index of each class
+ *   orbit_size  out [num_edges] (first *num_orbits used): class sizes
+ * The outputs fill an aaq_problem's orbit arrays directly.  Host only, n <= 4096; errors
+ * AAQ_ERR_GRAPH / AAQ_ERR_INVALID_ARG, outputs untouched on error.  The search is
+ * exponential in the worst case (as is any generator search), fast on the graph families
+ * of the paper. */
+aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t *edges, int32_t *orbit_of, int32_t *num_orbits,
+                           int32_t *orbit_rep, int32_t *orbit_size);
+
 /* ---------------------------------------------------------------- light cones
  * Light-cone evaluation, the locality reduction the paper names as compounding with the
  * orbit reduction (its discussion of reverse causal cones): the depth-p expectation of a

@@ -47,6 +47,7 @@ EXPORTS = (
     "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
     "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed", "aaq_lightcone_info",
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
+    "aaq_edge_orbits",
 )
 
 
@@ -94,6 +95,9 @@ def lib():
         "aaq_lightcone_create": (i, [P, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, ctypes.POINTER(vp)]),
         "aaq_lightcone_execute": (i, [vp, vp, vp, vp]),
         "aaq_lightcone_destroy": (None, [vp]),
+        "aaq_edge_orbits": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -73,6 +73,12 @@ class Problem:
         return self.num_edges if obs == AAQ_OBS_HC else self.num_orbits
 
     @classmethod
+    def from_edges(cls, n: int, edges) -> "Problem":
+        """An instance whose Aut(G) edge orbits are computed by the library (aaq_edge_orbits)."""
+        of, rep, size = aaq_edge_orbits(n, edges)
+        return cls(n, edges, rep, size, of)
+
+    @classmethod
     def from_workload(cls, prob) -> "Problem":
         """From any object with n, edges(), orbit_rep(), orbit_size(), edge_orbit()."""
         return cls(prob.n, prob.edges(), prob.orbit_rep(), prob.orbit_size(), prob.edge_orbit())
@@ -288,6 +294,19 @@ def aaq_plan_execute(plan, d_params, d_out, stream=None) -> None:
 def aaq_plan_destroy(plan) -> None:
     if plan:
         _lib.lib().aaq_plan_destroy(plan)
+
+
+def aaq_edge_orbits(n: int, edges):
+    """Edge orbits of Aut(G) computed by the library: (orbit_of[m], orbit_rep[k], orbit_size[k])."""
+    e = _i32(edges)
+    m = e.size // 2
+    of = np.zeros(max(m, 1), dtype=np.int32)
+    rep = np.zeros(max(m, 1), dtype=np.int32)
+    size = np.zeros(max(m, 1), dtype=np.int32)
+    k = ctypes.c_int32()
+    _check(_lib.lib().aaq_edge_orbits(int(n), m, _ptr_i32(e), _ptr_i32(of), ctypes.byref(k), _ptr_i32(rep),
+                                      _ptr_i32(size)))
+    return of[:m].copy(), rep[:k.value].copy(), size[:k.value].copy()
 
 
 def aaq_lightcone_info(prob: Problem, p: int, obs: int = AAQ_OBS_HRED):

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libaaqaoa.so")
 
 def sources():
     return ([os.path.join(CSRC, "aaq_kernels.hip")] + sorted(glob.glob(os.path.join(CSRC, "aaq_inst_*.hip")))
-            + [os.path.join(CSRC, "aaq_host.cpp")])
+            + [os.path.join(CSRC, "aaq_host.cpp"), os.path.join(CSRC, "aaq_orbits.cpp")])
 
 
 # Packed FP32 instructions are disabled for all device code.

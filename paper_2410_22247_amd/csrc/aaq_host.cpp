@@ -37,6 +37,13 @@ aaq_status fail(aaq_status s, const std::string& msg) {
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+}  // namespace
+
+// the error message of the library's other translation units (aaq_orbits.cpp)
+aaq_status aaq::set_error(aaq_status s, const std::string& msg) { return fail(s, msg); }
+
+namespace {
+
 // ------------------------------------------------------------------ optional per-kernel timing
 // When enabled, launches are bracketed by HIP events on the launching stream and the
 // elapsed times are accumulated per kernel class with the algorithmic bytes moved.

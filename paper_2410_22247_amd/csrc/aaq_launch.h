@@ -2,9 +2,15 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include "aaq_internal.h"
+#include "aaqaoa.h"
 
 namespace aaq {
+
+// sets the message aaq_last_error_message returns; returns s
+aaq_status set_error(aaq_status s, const std::string& msg);
 
 struct LaunchSweep {
   void* psi;
