@@ -85,6 +85,9 @@ template <class V, class R> __device__ __forceinline__ void bflyk(V& x, V& y, R 
 }
 // Im(conj(u) v)
 template <class V> __device__ __forceinline__ auto imcm(const V& u, const V& v) { return u.x * v.y - u.y * v.x; }
+// a * b + c, one rounding
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ __forceinline__ uint64_t pdep64(uint64_t x, uint64_t mask) {
   uint64_t r = 0;
@@ -227,14 +230,20 @@ template <class R, int NS, bool EN, int LT> struct Tile {
 #pragma unroll
       for (int b = 0; b < RB; ++b) {
         if (!((MASK >> (B0 + b)) & 1u)) continue;
-        R gq = R(0);
+        // sum over pairs of Im(conj(lam_r) psi_r1) + Im(conj(lam_r1) psi_r): two chains
+        // of fused multiply-adds (four per pair)
+        R g0 = R(0), g1 = R(0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r & (1 << b)) continue;
           const int r1 = r | (1 << b);
-          gq += imcm(a[NS - 1][r], a[0][r1]) + imcm(a[NS - 1][r1], a[0][r]);
+          const V &l0 = a[NS - 1][r], &l1 = a[NS - 1][r1], &p0 = a[0][r], &p1 = a[0][r1];
+          g0 = fmar(l0.x, p1.y, g0);
+          g0 = fmar(-l0.y, p1.x, g0);
+          g1 = fmar(l1.x, p0.y, g1);
+          g1 = fmar(-l1.y, p0.x, g1);
         }
-        gt += ((act >> (B0 + b)) & 1u) ? gq : R(0);
+        gt += ((act >> (B0 + b)) & 1u) ? g0 + g1 : R(0);
       }
       gsum += wcur * gt;
       // the terms are formed here, before a following transpose: the empty volatile asm

@@ -635,6 +635,40 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   return AAQ_OK;
 }
 
+// the inputs that determine a single-instance host plan
+struct PlanKey {
+  std::vector<int32_t> v;
+  bool operator==(const PlanKey& o) const { return v == o.v; }
+};
+PlanKey plan_key(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg, aaq_precision prec,
+                 int tile, bool ckpt) {
+  PlanKey k;
+  k.v = {pr->n, pr->num_edges, pr->num_orbits, p, (int)grad, (int)obs, (int)agg, (int)prec, tile, (int)ckpt,
+         pr->edge_orbit ? 1 : 0};
+  k.v.insert(k.v.end(), pr->edges, pr->edges + 2 * pr->num_edges);
+  if (pr->num_orbits > 0) {
+    k.v.insert(k.v.end(), pr->orbit_rep, pr->orbit_rep + pr->num_orbits);
+    k.v.insert(k.v.end(), pr->orbit_size, pr->orbit_size + pr->num_orbits);
+  }
+  return k;
+}
+
+// per-thread pinned host buffer for the argument upload and the result download; it
+// grows as needed and is kept for the life of the process
+unsigned char* pinned_staging(size_t bytes) {
+  thread_local unsigned char* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    const size_t want = std::max(align_up(bytes, 4096), (size_t)65536);
+    if (hipHostMalloc((void**)&buf, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    cap = want;
+  }
+  return buf;
+}
+
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
                       void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
@@ -643,9 +677,20 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   if (st) return st;
   if ((st = validate_p(p))) return st;
   if ((st = validate_params(p, gamma, beta))) return st;
-  Single S;
   if (!tile) tile = chosen_tile_bits(pr->n, prec == AAQ_PREC_C128, grad);
-  if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, S, true, ckpt))) return st;
+  // the host plan of the last call on this thread is reused when the instance and the
+  // shape of the call are the same (repeated evaluations at new parameters)
+  thread_local PlanKey last_key;
+  thread_local Single last_plan;
+  thread_local bool have_last = false;
+  PlanKey key = plan_key(pr, p, grad, obs, agg, prec, tile, ckpt);
+  if (!have_last || !(key == last_key)) {
+    have_last = false;
+    if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, last_plan, true, ckpt))) return st;
+    last_key = std::move(key);
+    have_last = true;
+  }
+  const Single& S = last_plan;
   const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
   if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
   if (state_bytes < need_state * S.nbuf)
@@ -660,21 +705,24 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   const Layout& L = S.lay;
   hipStream_t hs = (hipStream_t)stream;
   unsigned char* ws = (unsigned char*)d_ws;
-  // host staging of everything that is uploaded
-  std::vector<unsigned char> up(L.upload_end, 0);
+  // host staging of everything that is uploaded (pinned, reused: the copies are
+  // asynchronous, and the call ends with a stream synchronisation)
+  unsigned char* up = pinned_staging(L.upload_end + sizeof(double) * L.nout);
+  if (!up) return fail(AAQ_ERR_HIP, "hipHostMalloc of the staging buffer failed");
+  std::memset(up, 0, L.upload_end);
   GraphDev g = make_graph(pr);
   const std::vector<int4>& terms = S.terms;
   g.T = S.T;
   g.h_is_cut = obs == AAQ_OBS_HC;
-  std::memcpy(up.data() + L.graph, &g, sizeof(g));
-  if (!terms.empty()) std::memcpy(up.data() + L.terms, terms.data(), sizeof(int4) * terms.size());
-  std::memcpy(up.data() + L.params, gamma, sizeof(double) * p);
-  std::memcpy(up.data() + L.params + sizeof(double) * p, beta, sizeof(double) * p);
-  if (!S.src.empty()) std::memcpy(up.data() + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
-  std::memcpy(up.data() + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
-  std::memcpy(up.data() + L.progs, S.progs.data(), sizeof(SweepProg) * S.progs.size());
-  std::memcpy(up.data() + L.sets, S.sets.data(), sizeof(SetSpec) * S.sets.size());
-  HIPCHK(hipMemcpyAsync(ws, up.data(), L.upload_end, hipMemcpyHostToDevice, hs));
+  std::memcpy(up + L.graph, &g, sizeof(g));
+  if (!terms.empty()) std::memcpy(up + L.terms, terms.data(), sizeof(int4) * terms.size());
+  std::memcpy(up + L.params, gamma, sizeof(double) * p);
+  std::memcpy(up + L.params + sizeof(double) * p, beta, sizeof(double) * p);
+  if (!S.src.empty()) std::memcpy(up + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
+  std::memcpy(up + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
+  std::memcpy(up + L.progs, S.progs.data(), sizeof(SweepProg) * S.progs.size());
+  std::memcpy(up + L.sets, S.sets.data(), sizeof(SetSpec) * S.sets.size());
+  HIPCHK(hipMemcpyAsync(ws, up, L.upload_end, hipMemcpyHostToDevice, hs));
   const double* dparams = (const double*)(ws + L.params);
   {
     TimedLaunch tl(KC_TABLES, 0.0, hs);
@@ -723,9 +771,10 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
                          (double*)(ws + L.stage), (double*)(ws + L.out), L.nout, hs));
     tl.done();
   }
-  res.assign(L.nout, 0.0);
-  HIPCHK(hipMemcpyAsync(res.data(), ws + L.out, sizeof(double) * L.nout, hipMemcpyDeviceToHost, hs));
+  double* down = (double*)(up + L.upload_end);
+  HIPCHK(hipMemcpyAsync(down, ws + L.out, sizeof(double) * L.nout, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
+  res.assign(down, down + L.nout);
   if (agg != AAQ_AGG_FUSED) {
     // energy from the per-term <ZZ>: sum_t (w_t/2)(1 - <ZZ>_t)
     double e = 0.0;
