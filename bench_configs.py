@@ -208,6 +208,30 @@ def lc(args):
                         "parameters and outputs, graph replay", "unit": "evals/s", "results": res}
 
 
+def sample(args):
+    """Final-state sampling at the n=26 p=4 and n=33 p=2 tree sizes: forward sweeps that keep
+    the state, then inverse-CDF draws; sampled approximation ratios against C_max = |E|."""
+    res = {}
+    for name, fn in (("c3 n=26 p=4", C.config3), ("c5b n=33 p=2", C.config5b)):
+        wp, p, gam, bet = fn(1)
+        pr = A.Problem.from_workload(wp)
+        cmax = len(wp.edges())  # trees are bipartite
+        for shots in (1 << 10, 1 << 20):
+            s = A.Sampler(pr, p, shots)
+            s.uniform.copy_(torch.rand(shots, dtype=torch.float64, generator=torch.Generator().manual_seed(shots)))
+            best, mean = A.aaq_sample(pr, gam[0], bet[0], A.AAQ_PREC_C64, s.uniform, s.state, s.ws, s.samples,
+                                      s.cuts)
+            dt = _timed(lambda: A.aaq_sample(pr, gam[0], bet[0], A.AAQ_PREC_C64, s.uniform, s.state, s.ws,
+                                             s.samples, s.cuts), 5 if wp.n > 30 else 20)
+            res[f"{name} shots={shots}"] = {"calls_s": round(1.0 / dt, 2), "shots_s": round(shots / dt, 1),
+                                            "best_cut": best, "mean_cut": mean, "R_best": best / cmax,
+                                            "R_mean": mean / cmax}
+            del s
+            torch.cuda.empty_cache()
+    return {"workload": "sample: forward pass keeping the state + inverse-CDF sampling (complex64 state, FP64 CDF)",
+            "unit": "calls/s", "results": res}
+
+
 def run(name, args):
     torch.cuda.set_device(0)
-    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc}[name](args)
+    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc, "sample": sample}[name](args)

@@ -237,6 +237,27 @@ aaq_status aaq_plan_autotune(const aaq_problem *probs, int count, int p, aaq_obs
                              const aaq_plan_opts *base, void *d_ws, size_t ws_bytes, const double *d_params,
                              double *d_out, void *stream, int reps, aaq_plan_opts *best, double *best_ms);
 
+/* ---------------------------------------------------------------- final-state sampling
+ * The read-out the paper's approximation ratios come from: bitstrings z drawn with
+ * probability |psi(z)|^2 from the depth-p QAOA state (its results section samples the
+ * final state), their cut values and the best and mean cut.  The forward sweeps keep the
+ * final state in d_state; each shot k takes the uniform number u_k = d_uniform[k] (values
+ * outside [0, 1) are clamped into it, NaN reads as 0) and returns the smallest bitstring z, in the order
+ * of the integers z, whose cumulative probability exceeds u_k (inverse CDF, FP64
+ * accumulation of the complex64 or complex128 probabilities).  Random numbers are the
+ * caller's: the same u gives the same shots.
+ *   d_uniform  device double[num_shots]
+ *   d_samples  device uint64[num_shots]: bit v of sample k = vertex v's side
+ *   d_cuts     device int32[num_shots]: cut value C(z) of each sample (exact integers)
+ *   best_cut_out, mean_cut_out  host doubles (may be NULL)
+ * d_state as for aaq_energy; the workspace from aaq_sample_workspace_size.  Synchronises
+ * the stream; AAQ_ERR_UNSUPPORTED for a graph without edges. */
+aaq_status aaq_sample_workspace_size(const aaq_problem *prob, int p, aaq_precision prec, size_t *bytes);
+aaq_status aaq_sample(const aaq_problem *prob, int p, const double *gamma, const double *beta, aaq_precision prec,
+                      int num_shots, const double *d_uniform, void *d_state, size_t state_bytes, void *d_ws,
+                      size_t ws_bytes, void *stream, uint64_t *d_samples, int32_t *d_cuts, double *best_cut_out,
+                      double *mean_cut_out);
+
 /* ---------------------------------------------------------------- edge orbits
  * Edge orbits of Aut(G) on the host (the paper's Algorithm 1 with its generator source,
  * nauty in the paper, replaced by an individualisation-refinement search): the edge list

@@ -97,6 +97,18 @@ def state(n: int, edges, gamma, beta) -> np.ndarray:
     return out.view(np.complex128)
 
 
+def sample(n: int, edges, gamma, beta, uniform):
+    """Final-state sampling by inverse CDF (the paper's read-out of the QAOA state): for
+    each u in [0, 1), the smallest integer z with CDF(z) > u, where CDF(z) is the FP64
+    running sum of |psi(y)|^2 over y <= z divided by the total.  Returns (z, C(z), CDF)."""
+    psi = state(n, edges, gamma, beta)
+    cdf = np.cumsum(np.abs(psi) ** 2)
+    cdf /= cdf[-1]
+    u = np.clip(np.asarray(uniform, dtype=np.float64), 0.0, np.nextafter(1.0, 0.0))
+    z = np.minimum(np.searchsorted(cdf, u, side="right"), (1 << n) - 1)
+    return z.astype(np.uint64), cut_values(n, edges)[z], cdf
+
+
 def zz(n: int, psi: np.ndarray, terms) -> np.ndarray:
     ti, tj, _ = _terms(terms)
     buf = np.ascontiguousarray(psi.astype(np.complex128)).view(np.float64)

@@ -12,5 +12,5 @@ from .api import (  # noqa: F401
     aaq_version, aaq_workspace_size, aaq_timing_enable, aaq_timing_read, aaq_set_tile_bits, aaq_get_tile_bits,
     aaq_autotune, aaq_plan_autotune, aaq_checkpoint_bytes, aaq_energy_grad_checkpointed, Estimator, Plan,
     aaq_lightcone_info, aaq_lightcone_workspace_size, aaq_lightcone_create, aaq_lightcone_execute,
-    aaq_lightcone_destroy, LightCone, aaq_edge_orbits,
+    aaq_lightcone_destroy, LightCone, aaq_edge_orbits, aaq_sample_workspace_size, aaq_sample, Sampler,
 )

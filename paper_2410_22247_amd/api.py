@@ -296,6 +296,27 @@ def aaq_plan_destroy(plan) -> None:
         _lib.lib().aaq_plan_destroy(plan)
 
 
+def aaq_sample_workspace_size(prob: Problem, p: int, prec: int = AAQ_PREC_C64) -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.lib().aaq_sample_workspace_size(prob.ref(), int(p), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def aaq_sample(prob: Problem, gamma, beta, prec: int, d_uniform, d_state, d_ws, d_samples, d_cuts, stream=None):
+    """Draws len(d_uniform) bitstrings into d_samples (uint64) and their cut values into d_cuts
+    (int32); returns (best cut, mean cut)."""
+    g, b = _params(gamma, beta)
+    up, ub = _dev(d_uniform)
+    sp, sb = _dev(d_state)
+    wp, wb = _dev(d_ws)
+    zp, _ = _dev(d_samples)
+    cp, _ = _dev(d_cuts)
+    best, mean = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.lib().aaq_sample(prob.ref(), g.size, _dp(g), _dp(b), int(prec), ub // 8, up, sp, sb, wp, wb,
+                                 _stream(stream), zp, cp, ctypes.byref(best), ctypes.byref(mean)))
+    return best.value, mean.value
+
+
 def aaq_edge_orbits(n: int, edges):
     """Edge orbits of Aut(G) computed by the library: (orbit_of[m], orbit_rep[k], orbit_size[k])."""
     e = _i32(edges)
@@ -490,3 +511,29 @@ class LightCone:
             self.close()
         except Exception:
             pass
+
+
+class Sampler:
+    """Final-state sampling of one instance (aaq_sample): owns the state, workspace and
+    sample buffers (torch)."""
+
+    def __init__(self, prob: Problem, p: int, shots: int, prec: int = AAQ_PREC_C64, device: str = "cuda"):
+        import torch
+
+        self.prob, self.p, self.shots, self.prec = prob, int(p), int(shots), prec
+        self.state = torch.empty(aaq_state_bytes(prob, prec), dtype=torch.uint8, device=device)
+        self.ws = torch.empty(aaq_sample_workspace_size(prob, p, prec), dtype=torch.uint8, device=device)
+        self.uniform = torch.zeros(self.shots, dtype=torch.float64, device=device)
+        self.samples = torch.zeros(self.shots, dtype=torch.int64, device=device)
+        self.cuts = torch.zeros(self.shots, dtype=torch.int32, device=device)
+
+    def sample(self, gamma, beta, uniform=None, stream=None):
+        """(samples, cuts, best, mean); `uniform` (numpy or torch, length shots) is copied in
+        when given, else the buffer's current contents are used."""
+        import torch
+
+        if uniform is not None:
+            self.uniform.copy_(torch.as_tensor(np.asarray(uniform, dtype=np.float64)))
+        best, mean = aaq_sample(self.prob, gamma, beta, self.prec, self.uniform, self.state, self.ws, self.samples,
+                                self.cuts, stream)
+        return self.samples.cpu().numpy().view(np.uint64), self.cuts.cpu().numpy(), best, mean

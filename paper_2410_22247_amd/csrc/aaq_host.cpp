@@ -545,7 +545,8 @@ struct Single {
 // grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
 // sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
 aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
-                       aaq_precision prec, int tile, Single& S, bool with_grids = false, bool ckpt = false) {
+                       aaq_precision prec, int tile, Single& S, bool with_grids = false, bool ckpt = false,
+                       bool keep_state = false) {
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
     return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
@@ -563,7 +564,7 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.terms = term_array(pr, obs, S.L, S.sets);
   S.k = (int)S.sets.size();
   uint8_t eops = OP_ENERGY | (agg == AAQ_AGG_PER_TERM ? OP_PERTERM : 0);
-  S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM, ckpt && grad && S.k >= 2);
+  S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM || keep_state, ckpt && grad && S.k >= 2);
   S.nbuf = prog_buffers(S.progs);
   if (S.nbuf > kMaxCkpt) return fail(AAQ_ERR_UNSUPPORTED, "too many checkpoint states for this depth (max 32)");
   Layout& L = S.lay;
@@ -641,10 +642,10 @@ struct PlanKey {
   bool operator==(const PlanKey& o) const { return v == o.v; }
 };
 PlanKey plan_key(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg, aaq_precision prec,
-                 int tile, bool ckpt) {
+                 int tile, bool ckpt, bool keep_state) {
   PlanKey k;
   k.v = {pr->n, pr->num_edges, pr->num_orbits, p, (int)grad, (int)obs, (int)agg, (int)prec, tile, (int)ckpt,
-         pr->edge_orbit ? 1 : 0};
+         pr->edge_orbit ? 1 : 0, (int)keep_state};
   k.v.insert(k.v.end(), pr->edges, pr->edges + 2 * pr->num_edges);
   if (pr->num_orbits > 0) {
     k.v.insert(k.v.end(), pr->orbit_rep, pr->orbit_rep + pr->num_orbits);
@@ -672,7 +673,7 @@ unsigned char* pinned_staging(size_t bytes) {
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
                       void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
-                      int tile = 0, bool ckpt = false) {
+                      int tile = 0, bool ckpt = false, bool keep_state = false, Single* plan_out = nullptr) {
   aaq_status st = validate_problem(pr);
   if (st) return st;
   if ((st = validate_p(p))) return st;
@@ -683,10 +684,10 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   thread_local PlanKey last_key;
   thread_local Single last_plan;
   thread_local bool have_last = false;
-  PlanKey key = plan_key(pr, p, grad, obs, agg, prec, tile, ckpt);
+  PlanKey key = plan_key(pr, p, grad, obs, agg, prec, tile, ckpt, keep_state);
   if (!have_last || !(key == last_key)) {
     have_last = false;
-    if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, last_plan, true, ckpt))) return st;
+    if ((st = plan_single(pr, p, grad, obs, agg, prec, tile, last_plan, true, ckpt, keep_state))) return st;
     last_key = std::move(key);
     have_last = true;
   }
@@ -781,6 +782,54 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     for (int t = 0; t < S.T; ++t) e += 0.5 * terms[t].z * (1.0 - res[2 + 2 * p + t]);
     res[0] = e;
   }
+  if (plan_out) *plan_out = S;
+  return AAQ_OK;
+}
+
+// ------------------------------------------------------------------ final-state sampling
+constexpr int kSampleBlockBits = 13;  // CDF blocks of 2^13 bitstrings
+
+int sample_block_bits(int n) { return std::min(n, kSampleBlockBits); }
+
+size_t sample_extra_bytes(int n) {
+  const size_t nb = (size_t)1 << (n - sample_block_bits(n));
+  return align_up(sizeof(double) * nb) * 2 + align_up(sizeof(double) * 2);
+}
+
+aaq_status run_sample(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_precision prec,
+                      int shots, const double* d_uniform, void* d_state, size_t state_bytes, void* d_ws, size_t ws_bytes,
+                      void* stream, uint64_t* d_samples, int32_t* d_cuts, double* best_out, double* mean_out) {
+  aaq_status st = validate_problem(pr);
+  if (st) return st;
+  if (pr->num_edges == 0) return fail(AAQ_ERR_UNSUPPORTED, "a graph without edges has nothing to sample for");
+  if (shots < 1) return fail(AAQ_ERR_INVALID_ARG, "num_shots must be >= 1");
+  if (!d_uniform || !d_samples || !d_cuts) return fail(AAQ_ERR_INVALID_ARG, "d_uniform / d_samples / d_cuts is NULL");
+  const size_t extra = sample_extra_bytes(pr->n);
+  if (ws_bytes < extra) return fail(AAQ_ERR_BUFFER, "workspace too small for sampling");
+  // the forward pass keeps the final state; its own workspace is everything before the
+  // sampling area at the end of the caller's workspace
+  std::vector<double> res;
+  Single S;
+  if ((st = run_single(pr, p, gamma, beta, AAQ_OBS_HC, AAQ_AGG_FUSED, prec, false, d_state, state_bytes, nullptr, 0,
+                       d_ws, ws_bytes - extra, stream, res, 0, false, true, &S)))
+    return st;
+  hipStream_t hs = (hipStream_t)stream;
+  unsigned char* ws = (unsigned char*)d_ws;
+  // sampling area right after the forward pass's layout: [block sums][cumulative sums][best, mean]
+  unsigned char* sw = ws + S.lay.total;
+  const int lb = sample_block_bits(S.n);
+  const size_t nb = (size_t)1 << (S.n - lb);
+  double* bsum = (double*)sw;
+  double* cum = (double*)(sw + align_up(sizeof(double) * nb));
+  double* stats = (double*)(sw + 2 * align_up(sizeof(double) * nb));
+  const SwScale* fin = (const SwScale*)(ws + S.lay.scales) + S.lay.nsweep;
+  HIPCHK(launch_sample(d_state, S.n, lb, bsum, cum, &fin->F_pre, d_uniform, shots, (const GraphDev*)(ws + S.lay.graph),
+                       d_samples, d_cuts, stats, S.dbl, hs));
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  if (best_out) *best_out = h[0];
+  if (mean_out) *mean_out = h[1];
   return AAQ_OK;
 }
 
@@ -1154,6 +1203,29 @@ aaq_status aaq_energy_grad_checkpointed(const aaq_problem* prob, int p, const do
     dbeta_out[l] = res[2 + p + l];
   }
   return AAQ_OK;
+}
+
+aaq_status aaq_sample_workspace_size(const aaq_problem* prob, int p, aaq_precision prec, size_t* bytes) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if ((s = validate_p(p))) return s;
+  if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
+  size_t mx = 0;
+  for (int tile : {12, 13}) {
+    Single S;
+    if ((s = plan_single(prob, p, false, AAQ_OBS_HC, AAQ_AGG_FUSED, prec, tile, S, false, false, true))) return s;
+    mx = std::max(mx, S.lay.total);
+  }
+  *bytes = mx + sample_extra_bytes(prob->n);
+  return AAQ_OK;
+}
+
+aaq_status aaq_sample(const aaq_problem* prob, int p, const double* gamma, const double* beta, aaq_precision prec,
+                      int num_shots, const double* d_uniform, void* d_state, size_t state_bytes, void* d_ws,
+                      size_t ws_bytes, void* stream, uint64_t* d_samples, int32_t* d_cuts, double* best_cut_out,
+                      double* mean_cut_out) {
+  return run_sample(prob, p, gamma, beta, prec, num_shots, d_uniform, d_state, state_bytes, d_ws, ws_bytes, stream,
+                    d_samples, d_cuts, best_cut_out, mean_cut_out);
 }
 
 aaq_status aaq_cut_values_layout(const aaq_problem* prob, aaq_observable obs, int set_index, int arrangement,

@@ -277,6 +277,136 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
 // exact integer diagonal values through the same per-amplitude code as the kernels,
 // computed at arrangement K (0: load arrangement, 1: phase arrangement) of set S
 
+// ---------------------------------------------------------------- final-state sampling
+// The buffer holds sigma psi(z ^ F) at index z (uniform scale sigma, flip mask F), so the
+// probability of bitstring z is |buf[z ^ F]|^2 / sum |buf|^2.  Bitstrings are drawn by
+// inverse CDF in bitstring order: FP64 sums over blocks of 2^lb indices (index block c
+// holds bitstring block c ^ (F >> lb)), their inclusive prefix in bitstring-block order,
+// then per shot a binary search over the blocks and a wave-wide prefix scan inside the
+// chosen block.
+template <class R>
+__global__ __launch_bounds__(256) void k_samp_blocksum(const typename Cx<R>::V* __restrict__ psi, int lb,
+                                                       double* __restrict__ bsum) {
+  __shared__ double red[4];
+  const uint64_t base = (uint64_t)blockIdx.x << lb;
+  const int B = 1 << lb;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < B; i += 256) {
+    const typename Cx<R>::V a = psi[base + i];
+    acc += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// one workgroup: cum[b] = sum_{c <= b} bsum[c ^ fhi], in a fixed order
+__global__ __launch_bounds__(1024) void k_samp_scan(const double* __restrict__ bsum, uint64_t nb,
+                                                    const uint64_t* __restrict__ flips, int lb, double* __restrict__ cum) {
+  __shared__ double part[1024];
+  const uint64_t fhi = (*flips >> lb) & (nb - 1);
+  const uint64_t chunk = (nb + 1023) / 1024;
+  const uint64_t lo = min(nb, (uint64_t)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+  double s = 0.0;
+  for (uint64_t b = lo; b < hi; ++b) s += bsum[b ^ fhi];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int t = 0; t < 1024; ++t) {
+      const double v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  double run = part[threadIdx.x];
+  for (uint64_t b = lo; b < hi; ++b) {
+    run += bsum[b ^ fhi];
+    cum[b] = run;
+  }
+}
+
+// one wave per shot (four shots per workgroup)
+template <class R>
+__global__ __launch_bounds__(256) void k_sample(const typename Cx<R>::V* __restrict__ psi, int lb, uint64_t nb,
+                                                const double* __restrict__ cum, const uint64_t* __restrict__ flips,
+                                                const double* __restrict__ uniform, int shots, const GraphDev* g,
+                                                uint64_t* __restrict__ samples, int32_t* __restrict__ cuts) {
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (k >= shots) return;  // uniform over the wave
+  const uint64_t F = *flips;
+  const double total = cum[nb - 1];
+  const double u = fmin(fmax(uniform[k], 0.0), 0x1.fffffffffffffp-1);  // into [0, 1); NaN -> 0
+  const double t = u * total;
+  uint64_t lo = 0, hi = nb - 1;  // smallest block with cum > t
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (cum[mid] > t) hi = mid;
+    else lo = mid + 1;
+  }
+  const uint64_t b = lo;
+  const double r = t - (b ? cum[b - 1] : 0.0);
+  const int B = 1 << lb;
+  uint64_t zsel = ~0ull, zlast = b << lb;
+  double run = 0.0;
+  for (int c = 0; c < B; c += 64) {
+    const int j = c + lane;
+    double pz = 0.0;
+    if (j < B) {
+      const typename Cx<R>::V a = psi[((b << lb) | (uint64_t)j) ^ F];
+      pz = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    double s = pz;  // inclusive prefix over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double v = __shfl_up(s, o, 64);
+      if (lane >= o) s += v;
+    }
+    const uint64_t hit = __ballot(run + s > r);
+    const uint64_t nz = __ballot(pz > 0.0);
+    if (nz) zlast = (b << lb) | (uint64_t)(c + 63 - __builtin_clzll(nz));
+    if (hit) {
+      zsel = (b << lb) | (uint64_t)(c + __builtin_ctzll(hit));
+      break;
+    }
+    run += __shfl(s, 63, 64);
+  }
+  if (zsel == ~0ull) zsel = zlast;  // rounding left the residual above the block's scanned mass
+  int cut = 0;
+  for (int v = 0; v < g->n; ++v) cut += (int)((zsel >> v) & 1u) * __popcll(g->adj[v] & ~zsel);
+  if (lane == 0) {
+    samples[k] = zsel;
+    cuts[k] = cut;
+  }
+}
+
+// best and mean cut of the shots
+__global__ __launch_bounds__(256) void k_samp_stats(const int32_t* __restrict__ cuts, int shots, double* __restrict__ stats) {
+  __shared__ long long smax[256], ssum[256];
+  long long mx = -1, sm = 0;
+  for (int k = threadIdx.x; k < shots; k += 256) {
+    mx = max(mx, (long long)cuts[k]);
+    sm += cuts[k];
+  }
+  smax[threadIdx.x] = mx;
+  ssum[threadIdx.x] = sm;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + o]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = (double)smax[0];
+    stats[1] = (double)ssum[0] / (double)shots;
+  }
+}
+
 // light-cone units: the shared (gamma, beta) into every unit's parameter row, and the
 // fixed-order sum of the unit outputs (energy and gradients summed, norm averaged)
 __global__ __launch_bounds__(256) void k_lc_bcast(const double* __restrict__ params, int np, double* __restrict__ rows,
@@ -305,6 +435,26 @@ hipError_t launch_tables(const double* gamma, const double* beta, int p, int cma
   else
     hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
                        reinterpret_cast<float2*>(tab), progs, nsweep, sets, nsets, scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, const uint64_t* flips,
+                         const double* uniform, int shots, const GraphDev* g, uint64_t* samples, int32_t* cuts,
+                         double* stats, bool dbl, hipStream_t st) {
+  const uint64_t nb = (uint64_t)1 << (n - lb);
+  const dim3 gs((unsigned)((shots + 3) / 4));
+  if (dbl) {
+    hipLaunchKernelGGL(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum);
+    hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
+    hipLaunchKernelGGL(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, flips, uniform, shots,
+                       g, samples, cuts);
+  } else {
+    hipLaunchKernelGGL(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum);
+    hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
+    hipLaunchKernelGGL(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, flips, uniform, shots, g,
+                       samples, cuts);
+  }
+  hipLaunchKernelGGL(k_samp_stats, dim3(1), dim3(256), 0, st, cuts, shots, stats);
   return hipGetLastError();
 }
 

@@ -248,3 +248,34 @@ def test_gradient_p1_closed_form_and_hred_identity():
         assert abs(dg[0] - cg) < 1e-7 and abs(db[0] - cb) < 1e-7
         en2, dg2, db2 = O.energy_grad(15, e, prob.terms(OBS_HRED), [gam], [bet])
         assert abs(en - en2) < 1e-12 and abs(dg[0] - dg2[0]) < 1e-11 and abs(db[0] - db2[0]) < 1e-11
+
+
+# ------------------------------------------------------------------ final-state sampling
+def test_sample_uniform_state_closed_form():
+    """gamma = 0 (and beta = 0) leave |psi|^2 uniform: the inverse CDF is floor(u 2^n)."""
+    g = G.prufer_tree(9, 2)
+    u = np.concatenate([np.random.default_rng(0).random(200), [0.0, 1.0 - 2.0 ** -53, 0.5]])
+    for gam, bet in ((np.zeros(2), np.array([0.3, 1.1])), (np.array([0.4, 2.0]), np.zeros(2))):
+        z, c, cdf = O.sample(g.n, g.edge_array(), gam, bet, u)
+        assert np.allclose(cdf, np.arange(1, 513) / 512, rtol=0, atol=1e-13)
+        # floor(u 2^n), except where u sits within rounding of a multiple of 2^-n
+        want = np.floor(u * 512).astype(np.int64)
+        near = np.abs(u * 512 - np.round(u * 512)) < 1e-9
+        assert np.all((z == want) | near)
+        assert np.array_equal(c, O.cut_values(g.n, g.edge_array())[z])
+
+
+def test_sample_frequencies_and_mean_cut():
+    """On an even grid of M uniforms, bitstring z is drawn within 1 of M |psi(z)|^2 times
+    and the mean sampled cut lies within |E|/M of <H_C> (an independently pinned energy)."""
+    g = rand_graph(7, 0.5, 11)
+    gam, bet = np.array([0.7, 0.2]), np.array([0.35, 0.9])
+    M = 1 << 16
+    u = (np.arange(M) + 0.5) / M
+    z, c, _ = O.sample(g.n, g.edge_array(), gam, bet, u)
+    prob = np.abs(O.state(g.n, g.edge_array(), gam, bet)) ** 2
+    cnt = np.bincount(z.astype(np.int64), minlength=1 << g.n)
+    assert np.all(np.abs(cnt - M * prob) <= 1.0 + 1e-9)
+    e = O.energy(g.n, g.edge_array(), make_problem(g).terms(OBS_HC), gam, bet)
+    assert abs(c.mean() - e) <= 2 * g.m / M * (1 << g.n)  # each bitstring's count is off by < 1
+    assert np.all(np.diff(z.astype(np.int64)) >= 0)  # monotone in u

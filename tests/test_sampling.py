@@ -1,0 +1,157 @@
+"""Final-state sampling (aaq_sample): inverse-CDF draws over |psi|^2 in bitstring order,
+the read-out behind the paper's sampled approximation ratios.
+
+CPU: workspace sizing and the error paths.
+GPU: every draw is a valid inverse-CDF result of the FP64 oracle's distribution within
+the CDF tolerance (1e-5 absolute for complex64, 1e-10 for complex128), and the same
+bitstring as the oracle's wherever u is farther than that from a CDF step; cut values
+bit-exact; best and mean cut exact over the shots; edge uniforms; repeat calls; the
+n = 26 p = 4 tree at full size through properties (cuts exact, mean cut against the
+light-cone energy within six standard errors)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2410_22247_amd as A
+from oracle import reduced as Rd
+from workloads import graphs as G
+from workloads.configs import OBS_HC, config3, make_problem
+
+CDF_TOL = {A.AAQ_PREC_C64: 1e-5, A.AAQ_PREC_C128: 1e-10}
+
+
+def rand_graph(n, pe, seed):
+    rng = np.random.default_rng(seed)
+    es = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < pe]
+    return G.Graph(n, es or [(0, 1)], name=f"G({n},{pe},{seed})")
+
+
+def cut_of(edges, z):
+    z = np.asarray(z, dtype=np.uint64)
+    c = np.zeros(z.shape, dtype=np.int64)
+    for u, v in edges:
+        c += ((z >> np.uint64(u)) ^ (z >> np.uint64(v))).astype(np.int64) & 1
+    return c
+
+
+# ------------------------------------------------------------------ host (CPU)
+def test_sample_workspace_and_errors():
+    g = G.binary_tree(11)
+    pr = A.Problem.from_workload(make_problem(g))
+    w64 = A.aaq_sample_workspace_size(pr, 2, A.AAQ_PREC_C64)
+    w128 = A.aaq_sample_workspace_size(pr, 2, A.AAQ_PREC_C128)
+    assert w64 > 0 and w128 >= w64
+    with pytest.raises(A.AAQError) as e:
+        A.aaq_sample_workspace_size(pr, 0, A.AAQ_PREC_C64)
+    assert e.value.status == 1  # AAQ_ERR_INVALID_ARG
+    with pytest.raises(A.AAQError):
+        A.aaq_sample_workspace_size(pr, 2, 7)
+    empty = A.Problem(3, np.zeros((0, 2), dtype=np.int32))
+    # the argument checks come before any device work: NULL device buffers are fine here
+    with pytest.raises(A.AAQError) as e:
+        A.aaq_sample(empty, [0.1], [0.2], A.AAQ_PREC_C64, _Null(8), _Null(64), _Null(1 << 20), _Null(8), _Null(4), stream=0)
+    assert e.value.status == 6  # AAQ_ERR_UNSUPPORTED
+    with pytest.raises(A.AAQError) as e:
+        A.aaq_sample(pr, [0.1, 0.2], [0.2, 0.3], A.AAQ_PREC_C64, _Null(0), _Null(64), _Null(1 << 20), _Null(0),
+                     _Null(0), stream=0)
+    assert e.value.status == 1
+
+
+class _Null:
+    """A stand-in device buffer of a given byte size at address 0 (host-side checks only)."""
+
+    def __init__(self, nbytes):
+        self.nbytes = nbytes
+
+    def data_ptr(self):
+        return 0
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
+
+
+# ------------------------------------------------------------------ GPU
+def check_draws(n, edges, gam, bet, u, z, cuts, prec):
+    zo, co, cdf = O.sample(n, edges, gam, bet, u)
+    z = z.astype(np.int64)
+    tol = CDF_TOL[prec]
+    uc = np.clip(np.nan_to_num(u, nan=0.0), 0.0, np.nextafter(1.0, 0.0))
+    assert np.all((z >= 0) & (z < (1 << n)))
+    lo = np.where(z > 0, cdf[np.maximum(z - 1, 0)], 0.0)
+    assert np.all(lo - tol <= uc), "a draw lies above its inverse-CDF interval"
+    assert np.all(uc < cdf[z] + tol), "a draw lies below its inverse-CDF interval"
+    # away from the CDF steps the bitstring is the oracle's
+    step_lo = np.where(zo > 0, cdf[np.maximum(zo.astype(np.int64) - 1, 0)], 0.0)
+    clear = (uc - step_lo > tol) & (cdf[zo.astype(np.int64)] - uc > tol)
+    assert np.array_equal(z[clear], zo.astype(np.int64)[clear])
+    if tol * (1 << n) < 0.05:  # the tolerance band is narrow against the mean CDF step 2^-n
+        assert clear.mean() > 0.5
+    assert np.array_equal(cuts, O.cut_values(n, edges)[z])
+
+
+SAMPLE_CASES = [(G.Graph(2, [(0, 1)]), 1), (G.star(4), 2), (G.binary_tree(10), 2), (rand_graph(12, 0.3, 5), 3),
+                (G.complete(13), 1), (G.prufer_tree(14, 1), 2), (G.binary_tree(15), 3), (G.generalized_petersen(8, 3), 2),
+                (rand_graph(17, 0.25, 9), 2)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("g,p", SAMPLE_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_sample_matches_oracle_inverse_cdf(g, p):
+    pr = A.Problem.from_workload(make_problem(g))
+    rng = np.random.default_rng(1000 + g.n * 7 + p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    u = rng.random(3001)
+    for prec in (A.AAQ_PREC_C64, A.AAQ_PREC_C128):
+        s = A.Sampler(pr, p, u.size, prec)
+        z, cuts, best, mean = s.sample(gam, bet, u)
+        check_draws(g.n, g.edge_array(), gam, bet, u, z, cuts, prec)
+        assert best == cuts.max() and mean == pytest.approx(cuts.mean(), rel=1e-15, abs=0)
+
+
+@pytest.mark.gpu
+def test_sample_edge_uniforms_and_repeat_calls():
+    g = G.prufer_tree(15, 4)
+    pr = A.Problem.from_workload(make_problem(g))
+    gam, bet = np.array([0.5, 1.2]), np.array([0.3, 0.7])
+    u = np.array([0.0, 1.0 - 2.0 ** -53, 1.0, 1.5, -0.25, np.nan, 0.5, 1e-300])
+    s = A.Sampler(pr, 2, u.size)
+    z, cuts, best, _ = s.sample(gam, bet, u)
+    check_draws(g.n, g.edge_array(), gam, bet, u, z, cuts, A.AAQ_PREC_C64)
+    assert z[1] == z[2] == z[3] and z[0] == z[4] == z[5]
+    u2 = np.random.default_rng(4).random(1000)
+    s2 = A.Sampler(pr, 2, u2.size)
+    a = s2.sample(gam, bet, u2)
+    b = s2.sample(gam, bet, u2)  # same u, same shots
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2:] == b[2:]
+    # a different angle set through the same buffers, then back
+    s2.sample(bet, gam, u2)
+    c = s2.sample(gam, bet, u2)
+    assert np.array_equal(a[0], c[0])
+
+
+@pytest.mark.gpu
+def test_sample_n26_config3_full_size():
+    import torch
+
+    wp, p, gams, bets = config3(1)
+    pr = A.Problem.from_workload(wp)
+    shots = 1 << 14
+    u = np.random.default_rng(26).random(shots)
+    s = A.Sampler(pr, p, shots)
+    z, cuts, best, mean = s.sample(gams[0], bets[0], u)
+    assert np.all(z < (1 << wp.n))
+    assert np.array_equal(cuts, cut_of(wp.edges(), z))
+    assert best == cuts.max() and best <= len(wp.edges())
+    e = Rd.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(OBS_HC), gams[0], bets[0])[0]
+    assert abs(mean - e) <= 6 * cuts.std() / math.sqrt(shots)
+    # sorted uniforms give sorted bitstrings (inverse CDF is monotone)
+    us = np.sort(u[:4096])
+    zs = s.sample(gams[0], bets[0], np.concatenate([us, u[4096:]]))[0][:4096]
+    assert np.all(np.diff(zs.astype(np.int64)) >= 0)
+    del s
+    torch.cuda.empty_cache()
