@@ -7,7 +7,8 @@
  *
  * What it computes (the plain definitions, written out without blocking,
  * fusion or reordering):
- *   - cut value C(z) = sum over edges (u,v) of [z_u != z_v]           (H_C, eq. for H_P with w=1)
+ *   - cut value C(z) = sum over edges (u,v) of w_uv [z_u != z_v]      (the eq. for H_P; w_uv = 1 unless
+ *                                                                         integer weights are given)
  *   - ansatz |psi> = prod_{l=1..p} e^{-i beta_l H_M} e^{-i gamma_l H_C} |+>^n,
  *     layer 1 applied first, cost before mixer                          (QAOA section, eq. for |psi>_p;
  *                                                                         explicit order in eq. A2)
@@ -33,12 +34,12 @@
 
 typedef double complex cplx;
 
-/* number of cut edges of z: sum over edges of [bit u != bit v] */
-static int cut_of(uint64_t z, int m, const int32_t *edges) {
+/* cut value of z: sum over edges of w_e [bit u != bit v] (w_e = 1 when wts is NULL) */
+static int cut_of(uint64_t z, int m, const int32_t *edges, const int32_t *wts) {
   int c = 0;
   for (int e = 0; e < m; ++e) {
     uint64_t bu = (z >> edges[2 * e]) & 1u, bv = (z >> edges[2 * e + 1]) & 1u;
-    c += (bu != bv);
+    if (bu != bv) c += wts ? wts[e] : 1;
   }
   return c;
 }
@@ -53,11 +54,11 @@ static double term_value(uint64_t z, int T, const int32_t *ti, const int32_t *tj
   return h;
 }
 
-int orc_cut_values(int n, int m, const int32_t *edges, int32_t *out) {
+int orc_cut_values(int n, int m, const int32_t *edges, const int32_t *wts, int32_t *out) {
   if (n < 1 || n > 30) return -1;
   uint64_t N = (uint64_t)1 << n;
 #pragma omp parallel for schedule(static)
-  for (int64_t z = 0; z < (int64_t)N; ++z) out[z] = cut_of((uint64_t)z, m, edges);
+  for (int64_t z = 0; z < (int64_t)N; ++z) out[z] = cut_of((uint64_t)z, m, edges, wts);
   return 0;
 }
 
@@ -70,11 +71,12 @@ int orc_term_values(int n, int T, const int32_t *ti, const int32_t *tj, const do
 }
 
 /* psi(z) <- exp(-i gamma C(z)) psi(z); sign = +1 applies the gate, -1 its inverse */
-static void apply_phase(cplx *psi, int n, int m, const int32_t *edges, double gamma, double sign) {
+static void apply_phase(cplx *psi, int n, int m, const int32_t *edges, const int32_t *wts, double gamma,
+                        double sign) {
   uint64_t N = (uint64_t)1 << n;
 #pragma omp parallel for schedule(static)
   for (int64_t z = 0; z < (int64_t)N; ++z) {
-    double ang = -sign * gamma * (double)cut_of((uint64_t)z, m, edges);
+    double ang = -sign * gamma * (double)cut_of((uint64_t)z, m, edges, wts);
     psi[z] *= cos(ang) + I * sin(ang);
   }
 }
@@ -92,14 +94,15 @@ static void apply_rx(cplx *psi, int n, int q, double beta, double sign) {
   }
 }
 
-int orc_state(int n, int m, const int32_t *edges, int p, const double *gamma, const double *beta, double *psi_out) {
+int orc_state(int n, int m, const int32_t *edges, const int32_t *wts, int p, const double *gamma, const double *beta,
+              double *psi_out) {
   if (n < 1 || n > 30 || p < 0) return -1;
   uint64_t N = (uint64_t)1 << n;
   cplx *psi = (cplx *)psi_out;
   double amp = pow(2.0, -0.5 * n);
   for (uint64_t z = 0; z < N; ++z) psi[z] = amp;
   for (int l = 0; l < p; ++l) {
-    apply_phase(psi, n, m, edges, gamma[l], 1.0);
+    apply_phase(psi, n, m, edges, wts, gamma[l], 1.0);
     for (int q = 0; q < n; ++q) apply_rx(psi, n, q, beta[l], 1.0);
   }
   return 0;
@@ -123,14 +126,14 @@ int orc_zz(int n, const double *psi_in, int T, const int32_t *ti, const int32_t 
 }
 
 /* energy = sum_t (w_t/2)(1 - <Z Z>_t); also the independent route sum_z |psi|^2 h(z) */
-int orc_energy(int n, int m, const int32_t *edges, int T, const int32_t *ti, const int32_t *tj, const double *tw,
-               int p, const double *gamma, const double *beta, double *energy_terms, double *energy_direct,
+int orc_energy(int n, int m, const int32_t *edges, const int32_t *wts, int T, const int32_t *ti, const int32_t *tj,
+               const double *tw, int p, const double *gamma, const double *beta, double *energy_terms, double *energy_direct,
                double *zz_out, double *norm_out) {
   if (n < 1 || n > 30) return -1;
   uint64_t N = (uint64_t)1 << n;
   double *buf = (double *)malloc(sizeof(double) * 2 * N);
   if (!buf) return -2;
-  orc_state(n, m, edges, p, gamma, beta, buf);
+  orc_state(n, m, edges, wts, p, gamma, beta, buf);
   double *zz = (double *)malloc(sizeof(double) * (T > 0 ? T : 1));
   orc_zz(n, buf, T, ti, tj, zz);
   double e = 0.0;
@@ -162,12 +165,12 @@ static double im_lam_x_psi(const cplx *lam, const cplx *psi, int n, int q) {
 }
 
 /* Im sum_z conj(lam(z)) C(z) psi(z)  (the <lambda|H_C|psi> part of the gamma gradient) */
-static double im_lam_c_psi(const cplx *lam, const cplx *psi, int n, int m, const int32_t *edges) {
+static double im_lam_c_psi(const cplx *lam, const cplx *psi, int n, int m, const int32_t *edges, const int32_t *wts) {
   uint64_t N = (uint64_t)1 << n;
   double acc = 0.0;
 #pragma omp parallel for reduction(+ : acc) schedule(static)
   for (int64_t z = 0; z < (int64_t)N; ++z)
-    acc += (double)cut_of((uint64_t)z, m, edges) * cimag(conj(lam[z]) * psi[z]);
+    acc += (double)cut_of((uint64_t)z, m, edges, wts) * cimag(conj(lam[z]) * psi[z]);
   return acc;
 }
 
@@ -178,8 +181,8 @@ static double im_lam_c_psi(const cplx *lam, const cplx *psi, int n, int m, const
  * the gate on both psi and lam.  The mixer's generator sum_q X_q is accumulated
  * qubit by qubit as the single-qubit gates are undone.
  */
-int orc_energy_grad(int n, int m, const int32_t *edges, int T, const int32_t *ti, const int32_t *tj,
-                    const double *tw, int p, const double *gamma, const double *beta, double *energy,
+int orc_energy_grad(int n, int m, const int32_t *edges, const int32_t *wts, int T, const int32_t *ti,
+                    const int32_t *tj, const double *tw, int p, const double *gamma, const double *beta, double *energy,
                     double *dgamma, double *dbeta, double *final_dev) {
   if (n < 1 || n > 30 || p < 1) return -1;
   uint64_t N = (uint64_t)1 << n;
@@ -190,7 +193,7 @@ int orc_energy_grad(int n, int m, const int32_t *edges, int T, const int32_t *ti
     free(lam);
     return -2;
   }
-  orc_state(n, m, edges, p, gamma, beta, (double *)psi);
+  orc_state(n, m, edges, wts, p, gamma, beta, (double *)psi);
   double e = 0.0;
 #pragma omp parallel for reduction(+ : e) schedule(static)
   for (int64_t z = 0; z < (int64_t)N; ++z) {
@@ -208,9 +211,9 @@ int orc_energy_grad(int n, int m, const int32_t *edges, int T, const int32_t *ti
       apply_rx(lam, n, q, beta[l], -1.0);
     }
     dbeta[l] = gb;
-    dgamma[l] = 2.0 * im_lam_c_psi(lam, psi, n, m, edges);
-    apply_phase(psi, n, m, edges, gamma[l], -1.0);
-    apply_phase(lam, n, m, edges, gamma[l], -1.0);
+    dgamma[l] = 2.0 * im_lam_c_psi(lam, psi, n, m, edges, wts);
+    apply_phase(psi, n, m, edges, wts, gamma[l], -1.0);
+    apply_phase(lam, n, m, edges, wts, gamma[l], -1.0);
   }
   if (final_dev) {
     /* after undoing every gate psi must be |+>^n again */

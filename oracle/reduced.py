@@ -7,6 +7,12 @@ full-state C oracle from outside itself:
   (Wang, Hadfield, Jiang, Rieffel, PRA 97, 022304 (2018)) with d = deg u - 1,
   e = deg v - 1 and f = number of triangles on (u, v), for the convention
   U_P = e^{-i gamma H_C}, U_M = e^{-i beta sum X}.
+* ``p1_weighted_energy``: the single-layer expectation of Z_u Z_v for an Ising cost with
+  couplings (Ozaeta, van Dam, McMahon, Quantum Sci. Technol. 7, 045036 (2022)), written
+  for the weighted cut phase exp(-i gamma sum_e w_e (1 - Z Z)/2), theta_e = gamma w_e:
+  <ZZ>_uv = -(1/2) sin 4b sin theta_uv [prod_{x in N(u)-v} cos theta_ux + prod_{x in N(v)-u} cos theta_vx]
+            -(1/2) sin^2 2b [prod_{x != u,v} cos(theta_ux + theta_vx) - prod_{x != u,v} cos(theta_ux - theta_vx)]
+  (theta = 0 for a non-edge).  With every w = 1 it reduces to the formula above.
 * ``complete_graph_energy``: K_n evolves inside the symmetric (Dicke) subspace;
   C = k(n-k) for Hamming weight k and <k+1| sum X |k> = sqrt((k+1)(n-k)).
 * ``star_energy``: hub (x) Dicke subspace of the leaves, 2(L+1) dimensions.
@@ -56,6 +62,27 @@ def p1_energy(n: int, edges, terms, gamma: float, beta: float) -> float:
         tri = len(adj[i] & adj[j])
         tot += float(w) * p1_edge_cut_probability(len(adj[i]), len(adj[j]), tri, gamma, beta)
     return tot
+
+
+def p1_weighted_zz(n: int, edges, weights, u: int, v: int, gamma: float, beta: float) -> float:
+    """<Z_u Z_v> at p = 1 for the weighted cut phase (the Ising single-layer formula)."""
+    th = np.zeros((n, n))
+    for (a, b), w in zip(np.asarray(edges).reshape(-1, 2), np.asarray(weights).reshape(-1)):
+        th[int(a), int(b)] = th[int(b), int(a)] = gamma * float(w)
+    others = [x for x in range(n) if x != u and x != v]
+    pu = math.prod(math.cos(th[u, x]) for x in others)
+    pv = math.prod(math.cos(th[v, x]) for x in others)
+    pplus = math.prod(math.cos(th[u, x] + th[v, x]) for x in others)
+    pminus = math.prod(math.cos(th[u, x] - th[v, x]) for x in others)
+    return (-0.5 * math.sin(4 * beta) * math.sin(th[u, v]) * (pu + pv)
+            - 0.5 * math.sin(2 * beta) ** 2 * (pplus - pminus))
+
+
+def p1_weighted_energy(n: int, edges, weights, terms, gamma: float, beta: float) -> float:
+    """sum_t (w_t/2)(1 - <Z_i Z_j>_t) at p = 1 under the weighted cut phase."""
+    ti, tj, tw = terms
+    return sum(0.5 * float(w) * (1.0 - p1_weighted_zz(n, edges, weights, int(i), int(j), gamma, beta))
+               for i, j, w in zip(ti, tj, tw))
 
 
 def p1_dEdgamma_dbeta(n: int, edges, terms, gamma: float, beta: float, h: float = 1e-6):
@@ -127,26 +154,30 @@ def ball(n: int, edges, sources: Sequence[int], radius: int) -> List[int]:
     return sorted(dist)
 
 
-def _cone(n, edges, i, j, p):
+def _cone(n, edges, i, j, p, weights=None):
     verts = ball(n, edges, [int(i), int(j)], p)
     idx = {v: k for k, v in enumerate(verts)}
-    sub = [(idx[int(u)], idx[int(v)]) for u, v in np.asarray(edges).reshape(-1, 2) if int(u) in idx and int(v) in idx]
-    return verts, idx, np.asarray(sub, dtype=np.int32).reshape(-1, 2)
+    es = np.asarray(edges).reshape(-1, 2)
+    keep = [k for k, (u, v) in enumerate(es) if int(u) in idx and int(v) in idx]
+    sub = np.asarray([(idx[int(es[k, 0])], idx[int(es[k, 1])]) for k in keep], dtype=np.int32).reshape(-1, 2)
+    sw = None if weights is None else np.asarray(weights, dtype=np.int32).reshape(-1)[keep]
+    return verts, idx, sub, sw
 
 
-def light_cone_energy(n: int, edges, terms, gamma, beta) -> float:
-    """sum_t (w_t/2)(1 - <Z_i Z_j>_t), each term simulated on its cone subgraph."""
+def light_cone_energy(n: int, edges, terms, gamma, beta, weights=None) -> float:
+    """sum_t (w_t/2)(1 - <Z_i Z_j>_t), each term simulated on its cone subgraph (with the
+    cone's edge weights when ``weights`` are given)."""
     p = len(np.atleast_1d(gamma))
     ti, tj, tw = terms
     tot = 0.0
     for i, j, w in zip(ti, tj, tw):
-        verts, idx, sub = _cone(n, edges, i, j, p)
+        verts, idx, sub, sw = _cone(n, edges, i, j, p, weights)
         t = ([idx[int(i)]], [idx[int(j)]], [float(w)])
-        tot += _full_energy(len(verts), sub, t, gamma, beta)
+        tot += _full_energy(len(verts), sub, t, gamma, beta, weights=sw)
     return tot
 
 
-def light_cone_energy_grad(n: int, edges, terms, gamma, beta):
+def light_cone_energy_grad(n: int, edges, terms, gamma, beta, weights=None):
     """Energy and gradient, each term's contribution by the FP64 adjoint on its cone."""
     gamma = np.asarray(gamma, dtype=np.float64).reshape(-1)
     beta = np.asarray(beta, dtype=np.float64).reshape(-1)
@@ -157,10 +188,10 @@ def light_cone_energy_grad(n: int, edges, terms, gamma, beta):
     db = np.zeros(p)
     max_ball = 0
     for i, j, w in zip(ti, tj, tw):
-        verts, idx, sub = _cone(n, edges, i, j, p)
+        verts, idx, sub, sw = _cone(n, edges, i, j, p, weights)
         max_ball = max(max_ball, len(verts))
         t = ([idx[int(i)]], [idx[int(j)]], [float(w)])
-        en, g, b = _full_energy_grad(len(verts), sub, t, gamma, beta)
+        en, g, b = _full_energy_grad(len(verts), sub, t, gamma, beta, weights=sw)
         e += en
         dg += g
         db += b

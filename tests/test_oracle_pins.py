@@ -279,3 +279,96 @@ def test_sample_frequencies_and_mean_cut():
     e = O.energy(g.n, g.edge_array(), make_problem(g).terms(OBS_HC), gam, bet)
     assert abs(c.mean() - e) <= 2 * g.m / M * (1 << g.n)  # each bitstring's count is off by < 1
     assert np.all(np.diff(z.astype(np.int64)) >= 0)  # monotone in u
+
+
+# ------------------------------------------------------------------ weighted cut (integer w_ij)
+def weighted_graphs():
+    """(graph, integer weights) pairs: weights drawn per edge, per orbit of Aut(G) (so every
+    automorphism preserves them), and with triangles."""
+    out = []
+    rng = np.random.default_rng(5)
+    for g in (G.complete(5), rand_graph(8, 0.5, 3), G.cycle(7), G.generalized_petersen(5, 2), G.binary_tree(10)):
+        out.append((g, rng.integers(1, 6, g.m).astype(np.int32)))
+    for g in (G.binary_tree(15), G.star(7), G.complete(6)):
+        wp = make_problem(g)
+        out.append((g, (1 + 2 * np.asarray(wp.orbits.orbit_of) % 5).astype(np.int32)))
+    return out
+
+
+@pytest.mark.parametrize("g,w", weighted_graphs(), ids=lambda x: getattr(x, "name", None) or "w")
+def test_weighted_cut_values_brute_force(g, w):
+    z = np.arange(1 << g.n)
+    bits = (z[:, None] >> np.arange(g.n)[None, :]) & 1
+    want = np.zeros(1 << g.n, dtype=np.int64)
+    for (u, v), we in zip(g.edges, w):
+        want += int(we) * (bits[:, u] ^ bits[:, v])
+    assert np.array_equal(O.cut_values(g.n, g.edge_array(), w), want)
+    assert np.array_equal(O.cut_values(g.n, g.edge_array(), np.ones(g.m)), O.cut_values(g.n, g.edge_array()))
+
+
+@pytest.mark.parametrize("g,w", weighted_graphs(), ids=lambda x: getattr(x, "name", None) or "w")
+def test_weighted_p1_closed_form(g, w):
+    """The single-layer Ising formula against the full-state oracle, every edge term."""
+    rng = np.random.default_rng(g.n)
+    ti, tj, _ = make_problem(g).terms(OBS_HC)
+    for _ in range(3):
+        gam, bet = float(rng.uniform(0, math.pi)), float(rng.uniform(0, math.pi / 2))
+        _, _, zz, _ = O.energy(g.n, g.edge_array(), (ti, tj, np.ones(len(ti))), [gam], [bet], full=True,
+                               weights=w)
+        want = [R.p1_weighted_zz(g.n, g.edge_array(), w, int(i), int(j), gam, bet) for i, j in zip(ti, tj)]
+        assert np.allclose(zz, want, rtol=0, atol=1e-12)
+        # unit weights reduce the formula to the unweighted closed form
+        e1 = R.p1_weighted_energy(g.n, g.edge_array(), np.ones(g.m), (ti, tj, np.ones(len(ti))), gam, bet)
+        assert abs(e1 - R.p1_energy(g.n, g.edge_array(), (ti, tj, np.ones(len(ti))), gam, bet)) < 1e-12
+
+
+def test_weighted_state_scaling_and_unit_weights():
+    """psi(k w, gamma / k) = psi(w, gamma): a weight enters the phase only as gamma w."""
+    g = rand_graph(8, 0.4, 9)
+    w = np.random.default_rng(2).integers(1, 4, g.m).astype(np.int32)
+    gam, bet = np.array([0.3, 0.8]), np.array([0.5, 0.2])
+    a = O.state(g.n, g.edge_array(), gam, bet, weights=w)
+    b = O.state(g.n, g.edge_array(), gam / 3, bet, weights=3 * w)
+    assert np.allclose(a, b, rtol=0, atol=1e-13)
+    assert np.array_equal(O.state(g.n, g.edge_array(), gam, bet, weights=np.ones(g.m)),
+                          O.state(g.n, g.edge_array(), gam, bet))
+
+
+@pytest.mark.parametrize("g", [G.binary_tree(15), G.star(7), G.complete(6), G.generalized_petersen(5, 2)],
+                         ids=lambda g: g.name)
+def test_weighted_exact_identity_and_gradient(g):
+    """Weights constant on the edge orbits of Aut(G): every automorphism preserves them, so
+    <H_red> = <H_C> with H_red weights orbit size x edge weight (energy and gradient), and the
+    adjoint gradient matches central differences of the energy."""
+    wp = make_problem(g)
+    w = (1 + 2 * np.asarray(wp.orbits.orbit_of) % 5).astype(np.int32)
+    ti, tj, _ = wp.terms(OBS_HC)
+    hc = (ti, tj, w.astype(np.float64))
+    rep = wp.orbit_rep()
+    hred = (ti[rep], tj[rep], (wp.orbit_size() * w[rep]).astype(np.float64))
+    gam, bet = np.array([0.4, 1.1]), np.array([0.7, 0.3])
+    e_c, dg_c, db_c = O.energy_grad(g.n, g.edge_array(), hc, gam, bet, weights=w)
+    e_r, dg_r, db_r = O.energy_grad(g.n, g.edge_array(), hred, gam, bet, weights=w)
+    assert abs(e_c - e_r) < 1e-12 and np.allclose(dg_c, dg_r, atol=1e-11) and np.allclose(db_c, db_r, atol=1e-11)
+    assert abs(e_c - O.energy(g.n, g.edge_array(), hc, gam, bet, weights=w)) < 1e-12
+    h = 1e-5
+    for l in range(2):
+        d = np.zeros(2)
+        d[l] = h
+        fd_g = (O.energy(g.n, g.edge_array(), hc, gam + d, bet, weights=w)
+                - O.energy(g.n, g.edge_array(), hc, gam - d, bet, weights=w)) / (2 * h)
+        fd_b = (O.energy(g.n, g.edge_array(), hc, gam, bet + d, weights=w)
+                - O.energy(g.n, g.edge_array(), hc, gam, bet - d, weights=w)) / (2 * h)
+        assert abs(fd_g - dg_c[l]) < 1e-6 * max(1.0, abs(dg_c[l]))
+        assert abs(fd_b - db_c[l]) < 1e-6 * max(1.0, abs(db_c[l]))
+
+
+def test_weighted_light_cone_equals_full_state():
+    g = G.prufer_tree(14, 6)
+    w = np.random.default_rng(1).integers(1, 5, g.m).astype(np.int32)
+    ti, tj, _ = make_problem(g).terms(OBS_HC)
+    hc = (ti, tj, w.astype(np.float64))
+    gam, bet = np.array([0.6, 0.25]), np.array([0.35, 0.9])
+    e, dg, db = O.energy_grad(g.n, g.edge_array(), hc, gam, bet, weights=w)
+    e2, dg2, db2, _ = R.light_cone_energy_grad(g.n, g.edge_array(), hc, gam, bet, weights=w)
+    assert abs(e - e2) < 1e-11 and np.allclose(dg, dg2, atol=1e-10) and np.allclose(db, db2, atol=1e-10)

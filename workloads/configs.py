@@ -29,6 +29,7 @@ class Problem:
     graph: Graph
     orbits: EdgeOrbits
     reps: List[int]  # representative edge index per orbit
+    weights: Optional[np.ndarray] = None  # integer edge weights (weighted MaxCut), None: all 1
 
     @property
     def n(self) -> int:
@@ -50,20 +51,30 @@ class Problem:
     def edge_orbit(self) -> np.ndarray:
         return np.asarray(self.orbits.orbit_of, dtype=np.int32)
 
+    def edge_weight(self) -> np.ndarray:
+        if self.weights is None:
+            return np.ones(self.m, dtype=np.int32)
+        return np.asarray(self.weights, dtype=np.int32)
+
     def terms(self, observable: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-        """(i, j, w) arrays of the ZZ terms of the observable."""
+        """(i, j, w) arrays of the ZZ terms of the observable (H_C: every edge with its
+        weight; H_red: one representative per orbit, weight orbit size x edge weight)."""
         e = self.edges()
+        w = self.edge_weight()
         if observable == OBS_HC:
-            return e[:, 0].copy(), e[:, 1].copy(), np.ones(self.m, dtype=np.int32)
+            return e[:, 0].copy(), e[:, 1].copy(), w.copy()
         if observable == OBS_HRED:
             r = self.orbit_rep()
-            return e[r, 0].copy(), e[r, 1].copy(), self.orbit_size()
+            return e[r, 0].copy(), e[r, 1].copy(), (self.orbit_size() * w[r]).astype(np.int32)
         raise ValueError("observable must be 0 (H_C) or 1 (H_red)")
 
 
-def make_problem(g: Graph, rep_rng: Optional[np.random.Generator] = None) -> Problem:
-    eo = edge_orbits(g)
-    return Problem(g, eo, eo.representatives(rep_rng))
+def make_problem(g: Graph, rep_rng: Optional[np.random.Generator] = None, weights=None) -> Problem:
+    """The instance with its (weight-preserving, when integer ``weights`` are given) edge
+    orbits and the seed edge (or a random member) of each as representative."""
+    w = None if weights is None else np.asarray(weights, dtype=np.int32).reshape(-1)
+    eo = edge_orbits(g, w)
+    return Problem(g, eo, eo.representatives(rep_rng), w)
 
 
 # ---------------------------------------------------------------- config 1

@@ -15,6 +15,11 @@ of the edges under the full group Aut(G), the reading taken for the phrase
 
 Edge (u, v) is stored with u < v; the image of an edge under a permutation is
 normalised to (min, max) before lookup.
+
+With integer edge weights (weighted MaxCut, the paper's H_P with its w_ij) the group is the
+weight-preserving automorphisms: refinement sees (neighbour colour, edge weight) pairs,
+a candidate permutation must map every edge onto an edge of the same weight, and edges of
+different weights are never compared.
 """
 from __future__ import annotations
 
@@ -25,16 +30,19 @@ from typing import Dict, List, Optional, Sequence, Tuple
 from .graphs import Graph
 
 
-def _refine(adj: List[List[int]], colors: List[int]) -> List[int]:
-    """Colour refinement (1-dimensional Weisfeiler-Leman) to a stable colouring.
+def _refine(adj: List[List[int]], colors: List[int], wadj: Optional[List[List[int]]] = None) -> List[int]:
+    """Colour refinement (1-dimensional Weisfeiler-Leman) to a stable colouring;
+    ``wadj[v][k]`` is the weight of the edge to ``adj[v][k]`` (all 1 when None).
 
     Colour names are canonical: they depend only on the multiset structure, so
     two disjoint copies refined together get comparable colours.
     """
     cur = list(colors)
     ncls = len(set(cur))
+    if wadj is None:
+        wadj = [[1] * len(a) for a in adj]
     while True:
-        sigs = [(cur[v], tuple(sorted(cur[w] for w in adj[v]))) for v in range(len(adj))]
+        sigs = [(cur[v], tuple(sorted((cur[w], x) for w, x in zip(adj[v], wadj[v])))) for v in range(len(adj))]
         table = {s: i for i, s in enumerate(sorted(set(sigs)))}
         new = [table[s] for s in sigs]
         k = len(table)
@@ -46,18 +54,23 @@ def _refine(adj: List[List[int]], colors: List[int]) -> List[int]:
 class _Searcher:
     """Finds automorphisms of G that extend a partial vertex mapping."""
 
-    def __init__(self, g: Graph):
+    def __init__(self, g: Graph, weights: Optional[Sequence[int]] = None):
         self.n = g.n
         self.adj = g.adjacency()
-        self.adjsets = [set(a) for a in self.adj]
         n = self.n
+        wt = {}
+        for k, (u, v) in enumerate(g.edges):
+            wt[(u, v)] = wt[(v, u)] = 1 if weights is None else int(weights[k])
+        self.wadj = [[wt[(v, w)] for w in self.adj[v]] for v in range(n)]
+        self.adjsets = [{(w, x) for w, x in zip(self.adj[v], self.wadj[v])} for v in range(n)]
         # disjoint union of two copies: vertex v in copy 0, n + v in copy 1
         self.adj2 = [list(a) for a in self.adj] + [[n + w for w in a] for a in self.adj]
-        self.base = _refine(self.adj, [0] * n)
+        self.wadj2 = self.wadj + self.wadj
+        self.base = _refine(self.adj, [0] * n, self.wadj)
 
     def is_automorphism(self, phi: Sequence[int]) -> bool:
         for v in range(self.n):
-            img = {phi[w] for w in self.adj[v]}
+            img = {(phi[w], x) for w, x in zip(self.adj[v], self.wadj[v])}
             if img != self.adjsets[phi[v]]:
                 return False
         return True
@@ -73,7 +86,7 @@ class _Searcher:
 
     def _search(self, colors: List[int], next_color: int) -> Optional[List[int]]:
         n = self.n
-        col = _refine(self.adj2, colors)
+        col = _refine(self.adj2, colors, self.wadj2)
         cnt0: Dict[int, int] = {}
         cnt1: Dict[int, int] = {}
         for v in range(n):
@@ -158,13 +171,15 @@ def close_under_generators(g: Graph, generators: Sequence[Sequence[int]]) -> Tup
     return orbit_of, orbits
 
 
-def edge_orbits(g: Graph) -> EdgeOrbits:
-    """Exact Aut(G) edge orbits of g."""
+def edge_orbits(g: Graph, weights: Optional[Sequence[int]] = None) -> EdgeOrbits:
+    """Exact Aut(G) edge orbits of g (weight-preserving automorphisms when integer edge
+    ``weights`` are given, one per edge in the graph's edge order)."""
     if g.m == 0:
         return EdgeOrbits([], [], [])
-    s = _Searcher(g)
+    s = _Searcher(g, weights)
     gens: List[List[int]] = []
-    inv = [tuple(sorted((s.base[u], s.base[v]))) for (u, v) in g.edges]
+    inv = [tuple(sorted((s.base[u], s.base[v]))) + ((1 if weights is None else int(weights[k])),)
+           for k, (u, v) in enumerate(g.edges)]
     tested = set()
     while True:
         orbit_of, orbits = close_under_generators(g, gens)
