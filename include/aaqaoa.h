@@ -79,7 +79,18 @@ typedef enum { AAQ_PREC_C64 = 0, AAQ_PREC_C128 = 1 } aaq_precision;
  *   orbit_rep   [|O_E|] edge index of each orbit's representative (0 <= . < |E|)
  *   orbit_size  [|O_E|] |S_m| >= 1, summing to |E|
  *   edge_orbit  [|E|] orbit id of every edge, or NULL; when given, the library
- *               checks that sizes and representatives agree with it. */
+ *               checks that sizes and representatives agree with it.
+ *   edge_weight [|E|] integer edge weights w_ij >= 1 of the MaxCut H_P (the QAOA
+ *               section's H_P = 1/2 sum w_ij (1 - Z_i Z_j); the paper's experiments use
+ *               w = 1), or NULL for all 1.  The cut C(z) = sum w_ij [z_i != z_j] stays an
+ *               exact integer; the total weight sum w_ij must be <= AAQ_MAX_COST (the
+ *               phase tables hold C = 0 .. sum w).  The orbits must be orbits of the
+ *               weight-preserving automorphisms (aaq_edge_orbits with the same weights);
+ *               with edge_orbit given, equal weights inside every orbit are checked.
+ *               H_C's terms carry w_ij, H_red's the orbit size times the
+ *               representative's weight.  Weighted instances run the sweeps whose steps
+ *               are taken from the sweep program at run time. */
+#define AAQ_MAX_COST 561
 typedef struct {
   int32_t n;
   int32_t num_edges;
@@ -88,6 +99,7 @@ typedef struct {
   const int32_t *orbit_rep;
   const int32_t *orbit_size;
   const int32_t *edge_orbit;
+  const int32_t *edge_weight;
 } aaq_problem;
 
 /* Host-side validation of a problem and depth p (1 <= p <= AAQ_MAX_P). No HIP calls. */
@@ -267,6 +279,9 @@ aaq_status aaq_sample(const aaq_problem *prob, int p, const double *gamma, const
  * search looks for an automorphism mapping one seed onto the other.  The result is the
  * orbit partition under the whole group Aut(G).
  *   edges       [2 * num_edges] (u, v) pairs, any order; 0 <= u, v < n, u != v, no duplicates
+ *   edge_weight [num_edges] integer weights, or NULL: with weights the group is the
+ *               weight-preserving automorphisms (refinement sees edge weights, a
+ *               generator maps every edge onto one of equal weight)
  *   orbit_of    out [num_edges]: class of each edge
  *   num_orbits  out: number of classes
  *   orbit_rep   out [num_edges] (first *num_orbits used): seed edge index of each class
@@ -275,8 +290,8 @@ aaq_status aaq_sample(const aaq_problem *prob, int p, const double *gamma, const
  * AAQ_ERR_GRAPH / AAQ_ERR_INVALID_ARG, outputs untouched on error.  The search is
  * exponential in the worst case (as is any generator search), fast on the graph families
  * of the paper. */
-aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t *edges, int32_t *orbit_of, int32_t *num_orbits,
-                           int32_t *orbit_rep, int32_t *orbit_size);
+aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t *edges, const int32_t *edge_weight, int32_t *orbit_of,
+                           int32_t *num_orbits, int32_t *orbit_rep, int32_t *orbit_size);
 
 /* ---------------------------------------------------------------- light cones
  * Light-cone evaluation, the locality reduction the paper names as compounding with the

@@ -17,6 +17,7 @@ class CProblem(ctypes.Structure):
         ("orbit_rep", ctypes.POINTER(ctypes.c_int32)),
         ("orbit_size", ctypes.POINTER(ctypes.c_int32)),
         ("edge_orbit", ctypes.POINTER(ctypes.c_int32)),
+        ("edge_weight", ctypes.POINTER(ctypes.c_int32)),
     ]
 
 
@@ -99,7 +100,7 @@ def lib():
         "aaq_sample": (i, [P, i, dp, dp, i, i, vp, vp, sz, vp, sz, vp, vp, vp, dp, dp]),
         "aaq_edge_orbits": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32)]),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -46,10 +46,11 @@ class Problem:
     """A MaxCut instance and its Aut(G) edge orbits, as the C struct ``aaq_problem``.
 
     ``edges``: (m, 2) vertex pairs; ``orbit_rep``: representative edge index per
-    orbit; ``orbit_size``: orbit sizes; ``edge_orbit``: orbit id per edge or None.
+    orbit; ``orbit_size``: orbit sizes; ``edge_orbit``: orbit id per edge or None;
+    ``edge_weight``: integer edge weights (weighted MaxCut) or None for all 1.
     The numpy arrays are kept alive by this object."""
 
-    def __init__(self, n: int, edges, orbit_rep=None, orbit_size=None, edge_orbit=None):
+    def __init__(self, n: int, edges, orbit_rep=None, orbit_size=None, edge_orbit=None, edge_weight=None):
         self.n = int(n)
         self.edges = _i32(edges)
         m = self.edges.size // 2
@@ -58,8 +59,9 @@ class Problem:
         self.orbit_rep = _i32(orbit_rep)
         self.orbit_size = _i32(orbit_size)
         self.edge_orbit = None if edge_orbit is None else _i32(edge_orbit)
+        self.edge_weight = None if edge_weight is None else _i32(edge_weight)
         self.c = _lib.CProblem(self.n, m, _ptr_i32(self.edges), self.orbit_rep.size, _ptr_i32(self.orbit_rep),
-                               _ptr_i32(self.orbit_size), _ptr_i32(self.edge_orbit))
+                               _ptr_i32(self.orbit_size), _ptr_i32(self.edge_orbit), _ptr_i32(self.edge_weight))
 
     @property
     def num_edges(self) -> int:
@@ -73,15 +75,18 @@ class Problem:
         return self.num_edges if obs == AAQ_OBS_HC else self.num_orbits
 
     @classmethod
-    def from_edges(cls, n: int, edges) -> "Problem":
-        """An instance whose Aut(G) edge orbits are computed by the library (aaq_edge_orbits)."""
-        of, rep, size = aaq_edge_orbits(n, edges)
-        return cls(n, edges, rep, size, of)
+    def from_edges(cls, n: int, edges, edge_weight=None) -> "Problem":
+        """An instance whose Aut(G) edge orbits (weight-preserving ones with weights) are
+        computed by the library (aaq_edge_orbits)."""
+        of, rep, size = aaq_edge_orbits(n, edges, edge_weight)
+        return cls(n, edges, rep, size, of, edge_weight)
 
     @classmethod
     def from_workload(cls, prob) -> "Problem":
-        """From any object with n, edges(), orbit_rep(), orbit_size(), edge_orbit()."""
-        return cls(prob.n, prob.edges(), prob.orbit_rep(), prob.orbit_size(), prob.edge_orbit())
+        """From any object with n, edges(), orbit_rep(), orbit_size(), edge_orbit() (and an
+        optional ``weights`` attribute)."""
+        return cls(prob.n, prob.edges(), prob.orbit_rep(), prob.orbit_size(), prob.edge_orbit(),
+                   getattr(prob, "weights", None))
 
     def ref(self):
         return ctypes.byref(self.c)
@@ -317,16 +322,20 @@ def aaq_sample(prob: Problem, gamma, beta, prec: int, d_uniform, d_state, d_ws, 
     return best.value, mean.value
 
 
-def aaq_edge_orbits(n: int, edges):
-    """Edge orbits of Aut(G) computed by the library: (orbit_of[m], orbit_rep[k], orbit_size[k])."""
+def aaq_edge_orbits(n: int, edges, edge_weight=None):
+    """Edge orbits of Aut(G) computed by the library: (orbit_of[m], orbit_rep[k], orbit_size[k]);
+    with integer ``edge_weight`` the orbits of the weight-preserving automorphisms."""
     e = _i32(edges)
     m = e.size // 2
+    w = None if edge_weight is None else _i32(edge_weight)
+    if w is not None and w.size != m:
+        raise ValueError("one weight per edge")
     of = np.zeros(max(m, 1), dtype=np.int32)
     rep = np.zeros(max(m, 1), dtype=np.int32)
     size = np.zeros(max(m, 1), dtype=np.int32)
     k = ctypes.c_int32()
-    _check(_lib.lib().aaq_edge_orbits(int(n), m, _ptr_i32(e), _ptr_i32(of), ctypes.byref(k), _ptr_i32(rep),
-                                      _ptr_i32(size)))
+    _check(_lib.lib().aaq_edge_orbits(int(n), m, _ptr_i32(e), _ptr_i32(w), _ptr_i32(of), ctypes.byref(k),
+                                      _ptr_i32(rep), _ptr_i32(size)))
     return of[:m].copy(), rep[:k.value].copy(), size[:k.value].copy()
 
 

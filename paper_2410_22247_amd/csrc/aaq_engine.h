@@ -320,14 +320,23 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   template <int K> __device__ __forceinline__ void hvals(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR]) const {
     static_assert(K == LAST || K == P, "term lists exist for the load and phase arrangements");
     constexpr int KI = (K == LAST) ? 0 : 1;
-    const int4* tp = terms + S.toff[KI];
+    hsum(zb, terms + S.toff[KI], S.tcnt[KI], hv);
+  }
+  // the weighted cut C(z) = sum_e w_e [z_u != z_v] from the set's cost-term lists
+  template <int K> __device__ __forceinline__ void wcuts(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR]) const {
+    static_assert(K == LAST || K == P, "term lists exist for the load and phase arrangements");
+    constexpr int KI = (K == LAST) ? 0 : 1;
+    hsum(zb, terms + S.coff[KI], S.ccnt[KI], hv);
+  }
+  // the sum over one grouped term list (counts: the six group sizes)
+  __device__ __forceinline__ void hsum(uint64_t zb, const int4* tp, const uint16_t (&cnt)[6], int (&hv)[NR]) const {
     auto xbit = [&](const int4& tm) -> int { return (int)(((uint32_t)(zb >> tm.x) ^ (uint32_t)(zb >> tm.y)) & 1u); };
     int h0 = 0;
     int dh[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) dh[b] = 0;
     {
-      const int c = S.tcnt[KI][0];
+      const int c = cnt[0];
       for (int t = 0; t < c; ++t) {
         const int4 tm = tp[t];
         h0 += tm.z * xbit(tm);
@@ -336,7 +345,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
-      const int c = S.tcnt[KI][1 + b];
+      const int c = cnt[1 + b];
       for (int t = 0; t < c; ++t) {
         const int4 tm = tp[t];
         const int x = xbit(tm);
@@ -348,7 +357,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     int corr[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) corr[r] = 0;
-    for (int t = 0, c = S.tcnt[KI][5]; t < c; ++t) {
+    for (int t = 0, c = cnt[5]; t < c; ++t) {
       const int4 tm = tp[t];
       const int x = xbit(tm);
       const int ri = tm.w & 15, rj = tm.w >> 4;
@@ -687,7 +696,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
-      cuts<K>(S, zb, cx.g, cv);
+      if (cx.g->weighted)
+        wcuts<K>(S, zb, cx.terms, cv);
+      else
+        cuts<K>(S, zb, cx.g, cv);
       if (NS == 2 && (ops & OP_GRADG)) {
         R gs = R(0);
 #pragma unroll
@@ -1121,7 +1133,7 @@ static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t 
   const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
   const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
   const dim3 grid(L.set.ntiles), blk(Geo<R, LT>::NT);
-  switch (sweep_kind(L.prog)) {
+  switch (L.generic ? SK_GENERIC : sweep_kind(L.prog)) {
     case SK_F_FIRST: return sweep_launch_kind<R, RT, LT, SK_F_FIRST>(A, grid, blk, dyn, st);
     case SK_F_PLAIN: return sweep_launch_kind<R, RT, LT, SK_F_PLAIN>(A, grid, blk, dyn, st);
     case SK_F_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_F_BOUNDARY>(A, grid, blk, dyn, st);

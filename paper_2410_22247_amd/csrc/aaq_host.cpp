@@ -111,6 +111,14 @@ aaq_status validate_problem(const aaq_problem* pr) {
     if (!seen.insert({std::min(u, v), std::max(u, v)}).second)
       return fail(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a duplicate");
   }
+  if (pr->edge_weight) {
+    long long wsum = 0;
+    for (int e = 0; e < m; ++e) {
+      if (pr->edge_weight[e] < 1) return fail(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " has a weight < 1");
+      wsum += pr->edge_weight[e];
+    }
+    if (wsum > AAQ_MAX_COST) return fail(AAQ_ERR_UNSUPPORTED, "total edge weight exceeds AAQ_MAX_COST (561)");
+  }
   const int k = pr->num_orbits;
   if (m == 0) {
     if (k != 0) return fail(AAQ_ERR_ORBITS, "a graph without edges has no edge orbits");
@@ -138,6 +146,10 @@ aaq_status validate_problem(const aaq_problem* pr) {
       if (cnt[o] != pr->orbit_size[o]) return fail(AAQ_ERR_ORBITS, "orbit size disagrees with edge_orbit");
       if (pr->edge_orbit[pr->orbit_rep[o]] != o) return fail(AAQ_ERR_ORBITS, "representative is not in its orbit");
     }
+    if (pr->edge_weight)
+      for (int e = 0; e < m; ++e)
+        if (pr->edge_weight[e] != pr->edge_weight[pr->orbit_rep[pr->edge_orbit[e]]])
+          return fail(AAQ_ERR_ORBITS, "edge " + std::to_string(e) + " has another weight than its orbit's representative");
   }
   return AAQ_OK;
 }
@@ -155,12 +167,28 @@ aaq_status validate_params(int p, const double* g, const double* b) {
 }
 
 // ------------------------------------------------------------------ graph block
+int edge_weight(const aaq_problem* pr, int e) { return pr->edge_weight ? pr->edge_weight[e] : 1; }
+
+// the largest cut value sum_e w_e (the phase tables hold C = 0 .. this)
+int total_weight(const aaq_problem* pr) {
+  int w = 0;
+  for (int e = 0; e < pr->num_edges; ++e) w += edge_weight(pr, e);
+  return w;
+}
+
+bool is_weighted(const aaq_problem* pr) {
+  for (int e = 0; e < pr->num_edges; ++e)
+    if (edge_weight(pr, e) != 1) return true;
+  return false;
+}
+
 GraphDev make_graph(const aaq_problem* pr) {
   GraphDev g;
   std::memset(&g, 0, sizeof(g));
   g.n = pr->n;
   g.m = pr->num_edges;
-  g.cmax = pr->num_edges;
+  g.cmax = total_weight(pr);
+  g.weighted = is_weighted(pr);
   for (int e = 0; e < pr->num_edges; ++e) {
     int u = pr->edges[2 * e], v = pr->edges[2 * e + 1];
     g.adj[u] |= 1ull << v;
@@ -174,11 +202,12 @@ GraphDev make_graph(const aaq_problem* pr) {
 std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
   std::vector<int4> t;
   if (obs == AAQ_OBS_HC) {
-    for (int e = 0; e < pr->num_edges; ++e) t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], 1, 0));
+    for (int e = 0; e < pr->num_edges; ++e)
+      t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], edge_weight(pr, e), 0));
   } else {
     for (int o = 0; o < pr->num_orbits; ++o) {
       int e = pr->orbit_rep[o];
-      t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], pr->orbit_size[o], 0));
+      t.push_back(make_int4(pr->edges[2 * e], pr->edges[2 * e + 1], pr->orbit_size[o] * edge_weight(pr, e), 0));
     }
   }
   return t;
@@ -186,7 +215,7 @@ std::vector<int4> make_terms(const aaq_problem* pr, aaq_observable obs) {
 
 // Appends to `ext` (which starts with the plain term list) the term lists of set s
 // sorted for its load and phase arrangements (see SetSpec::toff).
-void add_term_lists(SetSpec& s, int L, const std::vector<int4>& terms, std::vector<int4>& ext) {
+void add_term_lists(SetSpec& s, int L, const std::vector<int4>& terms, std::vector<int4>& ext, bool cost = false) {
   const int na = geo_na(L);
   for (int ki = 0; ki < 2; ++ki) {
     const int b0 = geo_b0(ki == 0 ? na - 1 : na - 2, L);
@@ -204,22 +233,28 @@ void add_term_lists(SetSpec& s, int L, const std::vector<int4>& terms, std::vect
       else
         grp[1 + (ri >= 0 ? ri : rj)].push_back(t);
     }
-    s.toff[ki] = (uint16_t)ext.size();
+    (cost ? s.coff : s.toff)[ki] = (uint16_t)ext.size();
     for (int g = 0; g < 6; ++g) {
-      s.tcnt[ki][g] = (uint16_t)grp[g].size();
+      (cost ? s.ccnt : s.tcnt)[ki][g] = (uint16_t)grp[g].size();
       ext.insert(ext.end(), grp[g].begin(), grp[g].end());
     }
   }
 }
 
-// plain term list followed by every set's sorted lists (the device term array)
-std::vector<int4> term_array_of(const std::vector<int4>& terms, int L, std::vector<SetSpec>& sets) {
+// plain term list followed by every set's sorted lists (the device term array); with
+// `cost` (the weighted cut's terms) also every set's sorted cost-term lists
+std::vector<int4> term_array_of(const std::vector<int4>& terms, int L, std::vector<SetSpec>& sets,
+                                const std::vector<int4>* cost = nullptr) {
   std::vector<int4> ext = terms;
   for (SetSpec& s : sets) add_term_lists(s, L, terms, ext);
+  if (cost)
+    for (SetSpec& s : sets) add_term_lists(s, L, *cost, ext, true);
   return ext;
 }
 std::vector<int4> term_array(const aaq_problem* pr, aaq_observable obs, int L, std::vector<SetSpec>& sets) {
-  return term_array_of(make_terms(pr, obs), L, sets);
+  if (!is_weighted(pr)) return term_array_of(make_terms(pr, obs), L, sets);
+  const std::vector<int4> cost = make_terms(pr, AAQ_OBS_HC);
+  return term_array_of(make_terms(pr, obs), L, sets, &cost);
 }
 
 // ------------------------------------------------------------------ sweep planner
@@ -558,7 +593,7 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.grad = grad;
   S.agg = agg;
   S.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
-  S.cmax = pr->num_edges;
+  S.cmax = total_weight(pr);
   S.L = tile;
   S.sets = make_sets(S.n, S.L);
   S.terms = term_array(pr, obs, S.L, S.sets);
@@ -651,6 +686,7 @@ PlanKey plan_key(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aa
     k.v.insert(k.v.end(), pr->orbit_rep, pr->orbit_rep + pr->num_orbits);
     k.v.insert(k.v.end(), pr->orbit_size, pr->orbit_size + pr->num_orbits);
   }
+  for (int e = 0; e < pr->num_edges; ++e) k.v.push_back(edge_weight(pr, e));
   return k;
 }
 
@@ -714,7 +750,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   GraphDev g = make_graph(pr);
   const std::vector<int4>& terms = S.terms;
   g.T = S.T;
-  g.h_is_cut = obs == AAQ_OBS_HC;
+  g.h_is_cut = obs == AAQ_OBS_HC && !g.weighted;
   std::memcpy(up + L.graph, &g, sizeof(g));
   if (!terms.empty()) std::memcpy(up + L.terms, terms.data(), sizeof(int4) * terms.size());
   std::memcpy(up + L.params, gamma, sizeof(double) * p);
@@ -748,6 +784,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     A.set = S.sets[S.progs[sw].set];
     A.prog = S.progs[sw];
     A.two_states = needs_two_states(S.progs[sw]);
+    A.generic = g.weighted != 0;
     const SweepProg& pg = S.progs[sw];
     const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
                       !!(pg.flags & F_STORE_LAM);
@@ -824,7 +861,7 @@ aaq_status run_sample(const aaq_problem* pr, int p, const double* gamma, const d
   double* stats = (double*)(sw + 2 * align_up(sizeof(double) * nb));
   const SwScale* fin = (const SwScale*)(ws + S.lay.scales) + S.lay.nsweep;
   HIPCHK(launch_sample(d_state, S.n, lb, bsum, cum, &fin->F_pre, d_uniform, shots, (const GraphDev*)(ws + S.lay.graph),
-                       d_samples, d_cuts, stats, S.dbl, hs));
+                       (const int4*)(ws + S.lay.terms), d_samples, d_cuts, stats, S.dbl, hs));
   double h[2];
   HIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
@@ -929,7 +966,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     int64_t goff, toff;
     std::vector<SetSpec> sets;
   };
-  std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*, int>, GraphEntry> gmap;
+  std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*, const int32_t*, int>, GraphEntry> gmap;
   PL.ud.assign(count, UnitDesc{});
   PL.blob.clear();
   std::vector<std::vector<SweepProg>> progs(count);
@@ -941,16 +978,22 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.p = p;
     D.row = i;
     D.T = unit_terms ? (int)(*unit_terms)[i].size() : (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
-    D.cmax = pr->num_edges;
+    D.cmax = total_weight(pr);
     D.L = unit_tile_bits(pr->n, o);
-    auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size, (int)D.L);
+    auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size, pr->edge_weight, (int)D.L);
     auto it = unit_terms ? gmap.end() : gmap.find(key);
     if (it == gmap.end()) {
       GraphDev g = make_graph(pr);
       g.T = D.T;
-      g.h_is_cut = !unit_terms && obs == AAQ_OBS_HC;
+      g.h_is_cut = !unit_terms && obs == AAQ_OBS_HC && !g.weighted;
       std::vector<SetSpec> sets = make_sets(pr->n, D.L);
-      std::vector<int4> t = unit_terms ? term_array_of((*unit_terms)[i], D.L, sets) : term_array(pr, obs, D.L, sets);
+      std::vector<int4> t;
+      if (!unit_terms) {
+        t = term_array(pr, obs, D.L, sets);
+      } else {
+        const std::vector<int4> cost = make_terms(pr, AAQ_OBS_HC);
+        t = term_array_of((*unit_terms)[i], D.L, sets, g.weighted ? &cost : nullptr);
+      }
       int64_t goff = (int64_t)PL.blob.size();
       PL.blob.resize(align_up(PL.blob.size() + sizeof(GraphDev)));
       std::memcpy(PL.blob.data() + goff, &g, sizeof(g));
@@ -1248,12 +1291,13 @@ aaq_status aaq_cut_values_layout(const aaq_problem* prob, aaq_observable obs, in
   std::vector<unsigned char> up(need, 0);
   GraphDev g = make_graph(prob);
   g.T = T;
+  g.h_is_cut = obs == AAQ_OBS_HC && !g.weighted;
   std::memcpy(up.data(), &g, sizeof(g));
   if (!terms.empty()) std::memcpy(up.data() + align_up(sizeof(GraphDev)), terms.data(), sizeof(int4) * terms.size());
   hipStream_t hs = (hipStream_t)stream;
   unsigned char* ws = (unsigned char*)d_ws;
   HIPCHK(hipMemcpyAsync(ws, up.data(), need, hipMemcpyHostToDevice, hs));
-  HIPCHK(launch_cuts((const GraphDev*)ws, (const int4*)(ws + align_up(sizeof(GraphDev))), T, obs == AAQ_OBS_HRED ? 1 : 0,
+  HIPCHK(launch_cuts((const GraphDev*)ws, (const int4*)(ws + align_up(sizeof(GraphDev))), T, g.h_is_cut ? 0 : 1,
                      sets[set_index], arrangement, d_out, dbl, tile, hs));
   HIPCHK(hipStreamSynchronize(hs));
   return AAQ_OK;
@@ -1426,6 +1470,7 @@ struct aaq_lightcone {
   unsigned char* ws = nullptr;
   size_t params_off = 0, rows_off = 0;
   std::vector<std::vector<int32_t>> edges;  // owned edge lists of the units
+  std::vector<std::vector<int32_t>> weights;  // owned edge weights of the units (empty: unweighted)
   std::vector<aaq_problem> probs;
   bool use_graph = true;
   hipGraphExec_t exec = nullptr;
@@ -1440,6 +1485,7 @@ namespace {
 struct Cones {
   std::vector<int> n;                       // qubits of each unit
   std::vector<std::vector<int32_t>> edges;  // relabelled edge list of each unit
+  std::vector<std::vector<int32_t>> weights;  // its edge weights (empty when the instance is unweighted)
   std::vector<std::vector<int4>> terms;     // the unit's single weighted term
 };
 
@@ -1471,16 +1517,18 @@ aaq_status build_cones(const aaq_problem* pr, int p, aaq_observable obs, Cones& 
     int k = 0;
     for (int v = 0; v < n; ++v)
       if (dist[v] >= 0) idx[v] = k++;
-    std::vector<int32_t> es;
+    std::vector<int32_t> es, ws;
     for (int e = 0; e < m; ++e) {
       const int u = idx[pr->edges[2 * e]], v = idx[pr->edges[2 * e + 1]];
       if (u >= 0 && v >= 0) {
         es.push_back(u);
         es.push_back(v);
+        if (pr->edge_weight) ws.push_back(pr->edge_weight[e]);
       }
     }
     C.n.push_back(k);
     C.edges.push_back(std::move(es));
+    C.weights.push_back(std::move(ws));
     C.terms.push_back({make_int4(idx[t.x], idx[t.y], t.z, 0)});
   }
   return AAQ_OK;
@@ -1493,6 +1541,7 @@ std::vector<aaq_problem> cone_problems(const Cones& C) {
     v[i].n = C.n[i];
     v[i].num_edges = (int32_t)(C.edges[i].size() / 2);
     v[i].edges = C.edges[i].data();
+    v[i].edge_weight = C.weights[i].empty() ? nullptr : C.weights[i].data();
   }
   return v;
 }
@@ -1561,8 +1610,12 @@ aaq_status aaq_lightcone_create(const aaq_problem* prob, int p, aaq_observable o
   aaq_plan_default_opts(&o);
   if (opts) o = *opts;
   LC->edges = C.edges;  // owned copies: the unit problems point into these
+  LC->weights = C.weights;
   LC->probs = cone_problems(C);
-  for (size_t i = 0; i < LC->probs.size(); ++i) LC->probs[i].edges = LC->edges[i].data();
+  for (size_t i = 0; i < LC->probs.size(); ++i) {
+    LC->probs[i].edges = LC->edges[i].data();
+    LC->probs[i].edge_weight = LC->weights[i].empty() ? nullptr : LC->weights[i].data();
+  }
   LC->count = (int)LC->probs.size();
   LC->p = p;
   LC->grad = with_grad != 0;

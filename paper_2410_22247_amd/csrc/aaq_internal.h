@@ -104,6 +104,10 @@ struct SetSpec {
   // int4 entries from the start of the unit's term array, tcnt the six group sizes.
   uint16_t toff[2];
   uint16_t tcnt[2][6];
+  // The weighted cut's terms (every edge with its weight) in the same grouping, for the
+  // cost phase and the gamma gradient of weighted instances (empty otherwise).
+  uint16_t coff[2];
+  uint16_t ccnt[2][6];
 };
 
 struct SweepProg {
@@ -163,7 +167,7 @@ struct SwScale {
 struct GraphDev {
   int32_t n, m, T, cmax;   // cmax = |E| = last phase-table index
   int32_t h_is_cut;        // the observable is H_C: h(z) = C(z), computed from the adjacency masks
-  int32_t pad0;
+  int32_t weighted;        // integer edge weights: C(z) comes from the sets' cost-term lists
   uint64_t adj[kMaxN];     // adjacency bitmasks
   int32_t deg[kMaxN];
   int32_t pad[2];

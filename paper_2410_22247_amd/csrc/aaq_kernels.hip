@@ -333,7 +333,8 @@ template <class R>
 __global__ __launch_bounds__(256) void k_sample(const typename Cx<R>::V* __restrict__ psi, int lb, uint64_t nb,
                                                 const double* __restrict__ cum, const uint64_t* __restrict__ flips,
                                                 const double* __restrict__ uniform, int shots, const GraphDev* g,
-                                                uint64_t* __restrict__ samples, int32_t* __restrict__ cuts) {
+                                                const int4* __restrict__ cost_terms, uint64_t* __restrict__ samples,
+                                                int32_t* __restrict__ cuts) {
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= shots) return;  // uniform over the wave
@@ -376,7 +377,14 @@ __global__ __launch_bounds__(256) void k_sample(const typename Cx<R>::V* __restr
   }
   if (zsel == ~0ull) zsel = zlast;  // rounding left the residual above the block's scanned mass
   int cut = 0;
-  for (int v = 0; v < g->n; ++v) cut += (int)((zsel >> v) & 1u) * __popcll(g->adj[v] & ~zsel);
+  if (g->weighted) {  // the weighted cut: the H_C term list holds every edge with its weight
+    for (int t = 0; t < g->T; ++t) {
+      const int4 tm = cost_terms[t];
+      cut += tm.z * (int)(((zsel >> tm.x) ^ (zsel >> tm.y)) & 1u);
+    }
+  } else {
+    for (int v = 0; v < g->n; ++v) cut += (int)((zsel >> v) & 1u) * __popcll(g->adj[v] & ~zsel);
+  }
   if (lane == 0) {
     samples[k] = zsel;
     cuts[k] = cut;
@@ -439,20 +447,20 @@ hipError_t launch_tables(const double* gamma, const double* beta, int p, int cma
 }
 
 hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, const uint64_t* flips,
-                         const double* uniform, int shots, const GraphDev* g, uint64_t* samples, int32_t* cuts,
-                         double* stats, bool dbl, hipStream_t st) {
+                         const double* uniform, int shots, const GraphDev* g, const int4* cost_terms, uint64_t* samples,
+                         int32_t* cuts, double* stats, bool dbl, hipStream_t st) {
   const uint64_t nb = (uint64_t)1 << (n - lb);
   const dim3 gs((unsigned)((shots + 3) / 4));
   if (dbl) {
     hipLaunchKernelGGL(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum);
     hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
     hipLaunchKernelGGL(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, flips, uniform, shots,
-                       g, samples, cuts);
+                       g, cost_terms, samples, cuts);
   } else {
     hipLaunchKernelGGL(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum);
     hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
     hipLaunchKernelGGL(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, flips, uniform, shots, g,
-                       samples, cuts);
+                       cost_terms, samples, cuts);
   }
   hipLaunchKernelGGL(k_samp_stats, dim3(1), dim3(256), 0, st, cuts, shots, stats);
   return hipGetLastError();

@@ -26,6 +26,7 @@ struct LaunchSweep {
   SetSpec set;
   SweepProg prog;
   bool two_states;
+  bool generic = false;  // take every step from the program at run time (weighted instances)
 };
 
 struct LaunchUnits {
@@ -67,8 +68,8 @@ hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t
 // final-state sampling: block sums of |psi|^2, their prefix in bitstring order, one
 // inverse-CDF draw per uniform number (one wave per shot), cut values, best / mean cut
 hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, const uint64_t* flips,
-                         const double* uniform, int shots, const GraphDev* g, uint64_t* samples, int32_t* cuts,
-                         double* stats, bool dbl, hipStream_t st);
+                         const double* uniform, int shots, const GraphDev* g, const int4* cost_terms, uint64_t* samples,
+                         int32_t* cuts, double* stats, bool dbl, hipStream_t st);
 hipError_t launch_lc_bcast(const double* params, int np, double* rows, int count, hipStream_t st);
 hipError_t launch_lc_sum(const double* rows, int count, int stride, double* out, hipStream_t st);
 // fixed-order sums of per-tile partials; stage holds nout * kReduceChunks doubles

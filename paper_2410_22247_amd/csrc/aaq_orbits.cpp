@@ -10,7 +10,10 @@
 // still apart, the search looks for an automorphism mapping one seed onto the other,
 // adds it to the generators and closes again.  The result is the orbit partition of the
 // edges under the whole group Aut(G) (the group generated, the reading taken for the
-// paper's "mapped onto each other via a generator").
+// paper's "mapped onto each other via a generator").  With integer edge weights (the
+// w_ij of the MaxCut H_P) the group is the weight-preserving automorphisms: refinement
+// sees (neighbour colour, edge weight) pairs, a permutation must map every edge onto
+// one of equal weight, and only seeds of equal weight are compared.
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -28,20 +31,22 @@ namespace aaq_orbits {
 
 using Adj = std::vector<std::vector<int>>;
 
-// colour refinement (1-dimensional Weisfeiler-Leman) to a stable colouring; colour
-// names are canonical (ranks of sorted signatures), so the two copies of a disjoint
-// union refined together get comparable colours
-std::vector<int> refine(const Adj& adj, std::vector<int> cur) {
+// colour refinement (1-dimensional Weisfeiler-Leman) to a stable colouring; wadj[v][k]
+// is the weight of the edge to adj[v][k].  Colour names are canonical (ranks of sorted
+// signatures), so the two copies of a disjoint union refined together get comparable
+// colours
+std::vector<int> refine(const Adj& adj, const Adj& wadj, std::vector<int> cur) {
   const int n = (int)adj.size();
   size_t ncls = std::set<int>(cur.begin(), cur.end()).size();
+  using Sig = std::pair<int, std::vector<std::pair<int, int>>>;
   for (;;) {
-    std::vector<std::pair<int, std::vector<int>>> sig(n);
+    std::vector<Sig> sig(n);
     for (int v = 0; v < n; ++v) {
       sig[v].first = cur[v];
-      for (int w : adj[v]) sig[v].second.push_back(cur[w]);
+      for (size_t k = 0; k < adj[v].size(); ++k) sig[v].second.push_back({cur[adj[v][k]], wadj[v][k]});
       std::sort(sig[v].second.begin(), sig[v].second.end());
     }
-    std::vector<std::pair<int, std::vector<int>>> uniq = sig;
+    std::vector<Sig> uniq = sig;
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
     std::vector<int> nxt(n);
@@ -57,30 +62,32 @@ std::vector<int> refine(const Adj& adj, std::vector<int> cur) {
 // colour class is a singleton, which defines the mapping.
 struct Searcher {
   int n;
-  Adj adj, adj2;
-  std::vector<std::set<int>> nbs;
-  std::vector<int> base;  // stable colouring of G alone (edge invariants)
+  Adj adj, wadj, adj2, wadj2;
+  std::vector<std::set<std::pair<int, int>>> nbs;  // (neighbour, edge weight)
+  std::vector<int> base;                           // stable colouring of G alone (edge invariants)
 
-  explicit Searcher(const Adj& a) : n((int)a.size()), adj(a), adj2(2 * a.size()), nbs(a.size()) {
+  Searcher(const Adj& a, const Adj& w)
+      : n((int)a.size()), adj(a), wadj(w), adj2(2 * a.size()), wadj2(2 * a.size()), nbs(a.size()) {
     for (int v = 0; v < n; ++v) {
-      nbs[v] = std::set<int>(adj[v].begin(), adj[v].end());
+      for (size_t k = 0; k < adj[v].size(); ++k) nbs[v].insert({adj[v][k], wadj[v][k]});
       adj2[v] = adj[v];
-      for (int w : adj[v]) adj2[n + v].push_back(n + w);
+      wadj2[v] = wadj2[n + v] = wadj[v];
+      for (int x : adj[v]) adj2[n + v].push_back(n + x);
     }
-    base = refine(adj, std::vector<int>(n, 0));
+    base = refine(adj, wadj, std::vector<int>(n, 0));
   }
 
   bool is_automorphism(const std::vector<int>& phi) const {
     for (int v = 0; v < n; ++v) {
-      std::set<int> img;
-      for (int w : adj[v]) img.insert(phi[w]);
+      std::set<std::pair<int, int>> img;
+      for (size_t k = 0; k < adj[v].size(); ++k) img.insert({phi[adj[v][k]], wadj[v][k]});
       if (img != nbs[phi[v]]) return false;
     }
     return true;
   }
 
   bool search(std::vector<int> colors, std::vector<int>& phi) const {
-    std::vector<int> col = refine(adj2, std::move(colors));
+    std::vector<int> col = refine(adj2, wadj2, std::move(colors));
     std::map<int, int> c0, c1;
     for (int v = 0; v < n; ++v) {
       c0[col[v]]++;
@@ -159,8 +166,8 @@ void close(const std::vector<std::pair<int, int>>& edges, const std::map<std::pa
 }  // namespace aaq_orbits
 
 
-extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges, int32_t* orbit_of, int32_t* num_orbits,
-                                      int32_t* orbit_rep, int32_t* orbit_size) {
+extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges, const int32_t* edge_weight,
+                                      int32_t* orbit_of, int32_t* num_orbits, int32_t* orbit_rep, int32_t* orbit_size) {
   using namespace aaq_orbits;
   if (n < 1 || n > 4096) return aaq::set_error(AAQ_ERR_INVALID_ARG, "n must be in [1, 4096]");
   if (num_edges < 0) return aaq::set_error(AAQ_ERR_GRAPH, "num_edges < 0");
@@ -169,7 +176,8 @@ extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges
   if (!num_orbits) return aaq::set_error(AAQ_ERR_INVALID_ARG, "num_orbits is NULL");
   std::vector<std::pair<int, int>> es(num_edges);
   std::map<std::pair<int, int>, int> index;
-  Adj adj(n);
+  Adj adj(n), wadj(n);
+  std::vector<int> wt(num_edges, 1);
   for (int e = 0; e < num_edges; ++e) {
     const int u = edges[2 * e], v = edges[2 * e + 1];
     if (u < 0 || u >= n || v < 0 || v >= n)
@@ -178,14 +186,20 @@ extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges
     es[e] = {std::min(u, v), std::max(u, v)};
     if (!index.emplace(es[e], e).second)
       return aaq::set_error(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a duplicate");
+    if (edge_weight) {
+      if (edge_weight[e] < 1) return aaq::set_error(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " has a weight < 1");
+      wt[e] = edge_weight[e];
+    }
     adj[u].push_back(v);
     adj[v].push_back(u);
+    wadj[u].push_back(wt[e]);
+    wadj[v].push_back(wt[e]);
   }
   if (num_edges == 0) {
     *num_orbits = 0;
     return AAQ_OK;
   }
-  Searcher S(adj);
+  Searcher S(adj, wadj);
   std::vector<std::vector<int>> gens;
   std::set<std::pair<int, int>> tested;
   std::vector<int> of;
@@ -199,7 +213,7 @@ extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges
         const auto [a, b] = es[ei];
         const auto [c, d] = es[ej];
         const auto inv_i = std::minmax(S.base[a], S.base[b]), inv_j = std::minmax(S.base[c], S.base[d]);
-        if (inv_i != inv_j || !tested.insert({ei, ej}).second) continue;
+        if (inv_i != inv_j || wt[ei] != wt[ej] || !tested.insert({ei, ej}).second) continue;
         std::vector<int> phi;
         if (S.extend({{a, c}, {b, d}}, phi) || S.extend({{a, d}, {b, c}}, phi)) {
           gens.push_back(phi);
