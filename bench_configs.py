@@ -15,6 +15,12 @@ lc   light-cone evaluation (each orbit representative's <ZZ> on its distance-p c
      batched plan per instance) of the n=26 p=4, n=34 p=1 and n=33 p=2 trees: energy +
      gradient evals/s for H_red and H_C against the full-state sweeps, parity against the
      light-cone FP64 adjoint.
+sample  forward pass keeping the state + inverse-CDF sampling at the n=26 p=4 and n=33
+     p=2 tree sizes (2^10 and 2^20 shots); sampled approximation ratios.
+weighted  the n=26 p=4 tree with integer edge weights 1..4 (seeded): energy + gradient
+     (checkpoints) through the run-time sweep path, against the same tree unweighted,
+     and the weighted light-cone evaluation; parity against the weighted light-cone
+     FP64 adjoint.
 """
 import math
 import time
@@ -232,6 +238,47 @@ def sample(args):
             "unit": "calls/s", "results": res}
 
 
+def weighted(args):
+    from oracle import reduced as R
+
+    wp0, p, gam, bet = C.config3(4)
+    g = wp0.graph
+    w = np.random.default_rng(26).integers(1, 5, g.m).astype(np.int32)
+    wp = C.make_problem(g, weights=w)
+    res = {"total_weight": int(w.sum()), "orbits": wp.orbits.count}
+    for name, prob in (("weighted", wp), ("unweighted", wp0)):
+        pr = A.Problem.from_workload(prob)
+        est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=True)
+        k = [0]
+
+        def step():
+            est.energy_grad(gam[k[0] % 4], bet[k[0] % 4])
+            k[0] += 1
+
+        dt = _timed(step, 20)
+        r = {"evals_s": round(1.0 / dt, 2)}
+        if name == "weighted":
+            errs_e, errs_g = [], []
+            for j in range(2):
+                e, dg, db, _ = est.energy_grad(gam[j], bet[j])
+                e_lc, dg_lc, db_lc, _ = R.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(A.AAQ_OBS_HRED), gam[j],
+                                                                 bet[j], weights=w)
+                errs_e.append(abs(e - e_lc) / abs(e_lc))
+                errs_g.append(float(np.linalg.norm(np.concatenate([dg - dg_lc, db - db_lc]))
+                                    / max(np.linalg.norm(np.concatenate([dg_lc, db_lc])), abs(e_lc))))
+            r["max_rel_err_energy"] = float(max(errs_e))
+            r["max_rel_err_grad"] = float(max(errs_g))
+            L = A.LightCone(pr, p, A.AAQ_OBS_HRED, with_grad=True)
+            L.params.copy_(torch.from_numpy(np.concatenate([gam[0], bet[0]])))
+            r["light_cone_evals_s"] = round(1.0 / _timed(L.execute, 50), 1)
+            L.close()
+        res[name] = r
+        del est
+        torch.cuda.empty_cache()
+    return {"workload": "weighted: n=26 p=4 tree, integer edge weights 1..4, H_red energy + gradient (complex64, "
+                        "checkpoints)", "unit": "evals/s", "results": res}
+
+
 def run(name, args):
     torch.cuda.set_device(0)
-    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc, "sample": sample}[name](args)
+    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc, "sample": sample, "weighted": weighted}[name](args)
