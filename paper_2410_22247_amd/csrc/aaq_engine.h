@@ -118,6 +118,7 @@ template <class R> struct Ctx {
   int T;
   int cmax;
   uint64_t N = 0;  // amplitudes per state (stride between checkpoint buffers)
+  bool off32 = false;  // every byte offset inside one state buffer fits in 32 bits
 };
 
 // Per-thread accumulators for one sweep.
@@ -499,26 +500,96 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   template <int K> __device__ __forceinline__ bool is_dummy(const SetSpec& S, int r) const {
     return S.dummy && (tidx<G::b0(K), RB>(threadIdx.x, r) & S.dummy);
   }
-  template <int K> __device__ __forceinline__ void load_all(int s, const V* p, const SetSpec& S) {
-    static_assert(K == LAST, "global I/O happens at the load arrangement");
-    if (!S.dummy) {
+  // Global I/O of the tile at the load arrangement: register r of this thread is element
+  // toff + roff[r] of the buffer at `base`.  With off32 (every byte offset inside the
+  // buffer below 2^32) the address of register r is the uniform base + roff[r] (scalar
+  // registers) plus one 32-bit per-thread byte offset shared by all registers, the form
+  // the global load and store instructions take directly; otherwise each register gets a
+  // 64-bit address on the vector unit.
+  // With OFF32 the registers move through raw buffer loads and stores: a descriptor on
+  // `base` (stride 0, every offset below 2^32 in range), the thread's byte offset in one
+  // vector register and register r's byte offset roff[r] as a scalar offset.
+  static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)0xFFFFFFFF, 0x00020000);
+  }
+  static __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(V) == 8)
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, 0));
+    else
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)so, 0));
+  }
+  static __device__ __forceinline__ void buf_store(V x, __amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(V) == 8)
+      __builtin_amdgcn_raw_buffer_store_b64(
+          __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rs, 0, 0, 0)), x), rs, (int)vo, (int)so, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b128(
+          __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0)), x), rs, (int)vo, (int)so, 0);
+  }
+  template <int K, bool OFF32> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t toff,
+                                                                         const SetSpec& S) {
+    if constexpr (OFF32) {
+      const __amdgpu_buffer_rsrc_t rs = rsrc(base);
+      const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
+      if (!S.dummy) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+        for (int r = 0; r < NR; ++r) a[s][r] = buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      }
     } else {
+      const V* p = base + toff;
+      if (!S.dummy) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[S.roff[r]];
+        for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[S.roff[r]];
+      }
     }
   }
-  template <int K> __device__ __forceinline__ void store_all(int s, V* p, const SetSpec& S) const {
-    static_assert(K == LAST, "global I/O happens at the load arrangement");
-    if (!S.dummy) {
+  template <int K, bool OFF32> __device__ __forceinline__ void store_regs(int s, V* base, uint64_t toff,
+                                                                          const SetSpec& S) const {
+    if constexpr (OFF32) {
+      const __amdgpu_buffer_rsrc_t rs = rsrc(base);
+      const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
+      if (!S.dummy) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) p[S.roff[r]] = a[s][r];
+        for (int r = 0; r < NR; ++r) buf_store(a[s][r], rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (!is_dummy<K>(S, r)) buf_store(a[s][r], rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      }
     } else {
+      V* p = base + toff;
+      if (!S.dummy) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (!is_dummy<K>(S, r)) p[S.roff[r]] = a[s][r];
+        for (int r = 0; r < NR; ++r) p[S.roff[r]] = a[s][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (!is_dummy<K>(S, r)) p[S.roff[r]] = a[s][r];
+      }
     }
+  }
+  template <int K> __device__ __forceinline__ void load_all(int s, const V* base, uint64_t toff, const SetSpec& S,
+                                                            bool off32) {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    if (off32)
+      load_regs<K, true>(s, base, toff, S);
+    else
+      load_regs<K, false>(s, base, toff, S);
+  }
+  template <int K> __device__ __forceinline__ void store_all(int s, V* base, uint64_t toff, const SetSpec& S,
+                                                             bool off32) const {
+    static_assert(K == LAST, "global I/O happens at the load arrangement");
+    if (off32)
+      store_regs<K, true>(s, base, toff, S);
+    else
+      store_regs<K, false>(s, base, toff, S);
   }
   template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
 #pragma unroll
@@ -579,9 +650,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
     } else {
       const uint64_t toff = tile_base + thread_off<KL>(S);
-      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N + toff, S);
+      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, toff, S, cx.off32);
       if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
-        load_all<KL>(NS - 1, cx.lam + toff, S);
+        load_all<KL>(NS - 1, cx.lam, toff, S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -622,8 +693,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     // opaque to the compiler: the store addresses are formed here, not kept in
     // registers from the loads (that would hold 2 VGPRs per register and state)
     asm volatile("" : "+v"(toff));
-    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N + toff, S);
-    if (st_lam) store_all<LAST>(NS - 1, cx.lam + toff, S);
+    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N, toff, S, cx.off32);
+    if (st_lam) store_all<LAST>(NS - 1, cx.lam, toff, S, cx.off32);
   }
 
   // ================================================================ run-time-flag path
@@ -770,10 +841,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N + tile_base + thread_off<KL>(S), S);
+      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base + thread_off<KL>(S), S, cx.off32);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
-        load_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
+        load_all<KL>(NS - 1, cx.lam, tile_base + thread_off<KL>(S), S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -809,8 +880,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
     if ((st_psi || st_lam) && at_p) xchg_rt<P, KL>(lds_x);
-    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N + tile_base + thread_off<KL>(S), S);
-    if (st_lam) store_all<KL>(NS - 1, cx.lam + tile_base + thread_off<KL>(S), S);
+    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N, tile_base + thread_off<KL>(S), S, cx.off32);
+    if (st_lam) store_all<KL>(NS - 1, cx.lam, tile_base + thread_off<KL>(S), S, cx.off32);
   }
   __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                           const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,
@@ -917,7 +988,7 @@ __global__ AAQ_SWEEP_BOUNDS(KIND) void k_sweep(SweepArgs<R> A) {
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N};
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V)};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
