@@ -110,6 +110,10 @@ def main():
     ap.add_argument("--grad-mode", default="checkpoint", choices=["checkpoint", "uncompute"],
                     help="checkpoint: forward states kept in HBM, backward sweeps read them (default); "
                          "uncompute: backward sweeps recompute psi in place (two state buffers)")
+    ap.add_argument("--api", default="resident", choices=["resident", "host"],
+                    help="resident (default): parameters and outputs stay in device memory and evaluations queue "
+                         "back to back (aaq_resident_*); host: one synchronous aaq_energy_grad call per step with "
+                         "host parameters and host results")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU work: turn two rocprofv3 --pmc counter_collection.csv files into profiles/traffic.json")
     args = ap.parse_args()
@@ -143,11 +147,23 @@ def main():
     wp, p, gams, bets = config3(32)
     pr = A.Problem.from_workload(wp)
     torch.cuda.set_device(0)
-    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=args.grad_mode == "checkpoint")
+    ckpt = args.grad_mode == "checkpoint"
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=ckpt)
     stream = torch.cuda.current_stream()
+    res = None
+    if args.api == "resident":
+        res = A.Resident(pr, p, A.AAQ_OBS_HRED, with_grad=True, checkpoint=ckpt)
+        dparams = torch.from_numpy(np.concatenate([gams, bets], 1)).to("cuda")  # [32][2p], resident before timing
+        dout = torch.zeros(max(args.steps, args.warmup, 1), 2 + 2 * p, dtype=torch.float64, device="cuda")
+
+    def step(k):
+        if res is not None:
+            res.execute(dparams[k % 32], dout[k])
+        else:
+            est.energy_grad(gams[k % 32], bets[k % 32])
 
     for k in range(args.warmup):
-        est.energy_grad(gams[k % 32], bets[k % 32])
+        step(k)
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- timed region
@@ -157,10 +173,8 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    energies = []
     for k in range(args.steps):
-        e, dg, db, nrm = est.energy_grad(gams[k % 32], bets[k % 32])
-        energies.append(e)
+        step(k)
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -200,6 +214,8 @@ def main():
             "tile_sets": A.aaq_num_sets(26),
             "tile_bits": A.aaq_get_tile_bits(26, A.AAQ_PREC_C64, True),
             "gradient_mode": args.grad_mode,
+            "api": ("resident: device parameters and outputs, evaluations queued without host synchronisation"
+                    if res is not None else "host: synchronous call per evaluation"),
         },
         "roofline": {
             "bound": "hbm",
@@ -251,6 +267,17 @@ def main():
                                     "speedup": round(r_red / r_hc, 3)}
         ext["orbit_ratio_E_over_OE"] = round(wp.m / wp.orbits.count, 3)
         out["hred_vs_hc"] = ext
+        if res is not None:
+            # the same evaluations through the synchronous host API: rate and largest difference
+            k_chk = min(args.steps, 4)
+            got = dout[:k_chk].cpu().numpy()
+            diff = 0.0
+            for k in range(k_chk):
+                e, dg, db, nrm = est.energy_grad(gams[k % 32], bets[k % 32])
+                want = np.concatenate([[e, nrm], dg, db])
+                diff = max(diff, float(np.max(np.abs(got[k] - want) / np.maximum(np.abs(want), 1e-300))))
+            out["host_api"] = {"evals_s": round(rate(lambda: est.energy_grad(g0, b0)), 2),
+                               "max_rel_diff_vs_resident": diff}
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu_baseline:

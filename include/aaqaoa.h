@@ -249,6 +249,33 @@ aaq_status aaq_plan_autotune(const aaq_problem *probs, int count, int p, aaq_obs
                              const aaq_plan_opts *base, void *d_ws, size_t ws_bytes, const double *d_params,
                              double *d_out, void *stream, int reps, aaq_plan_opts *best, double *best_ms);
 
+/* ---------------------------------------------------------------- resident evaluator
+ * For optimizer loops whose parameters live on the device (e.g. a torch optimizer on the
+ * GPU): the same fused evaluation as aaq_energy / aaq_energy_grad(_checkpointed), with the
+ * instance, its sweep programs and tile sets uploaded once at creation.  Each execute
+ * reads d_params = [gamma[p], beta[p]] (device doubles) and writes d_out = [energy, norm,
+ * dgamma[p], dbeta[p]] (device doubles; the gradient entries are 0 without with_grad),
+ * asynchronously on the stream: no host synchronisation and no host-device copy, so
+ * evaluations queue back to back.
+ *   with_grad   energy + adjoint gradient
+ *   checkpoint  forward-state checkpoints (with_grad only): d_state then holds the
+ *               checkpoint states
+ *   d_state, d_lambda, d_ws  caller buffers of at least the sizes from
+ *               aaq_resident_workspace_size (state_bytes also bounds d_lambda with
+ *               with_grad, one state); they stay owned by the caller, must outlive the
+ *               evaluator and are used by every execute, so executions on one evaluator
+ *               are to be ordered on one stream.
+ * Create validates like aaq_energy and synchronises the stream once (the upload);
+ * execute checks only its pointers. */
+typedef struct aaq_resident aaq_resident;
+aaq_status aaq_resident_workspace_size(const aaq_problem *prob, int p, aaq_observable obs, int with_grad, int checkpoint,
+                                       aaq_precision prec, size_t *ws_bytes, size_t *state_bytes);
+aaq_status aaq_resident_create(const aaq_problem *prob, int p, aaq_observable obs, int with_grad, int checkpoint,
+                               aaq_precision prec, void *d_state, size_t state_bytes, void *d_lambda,
+                               size_t lambda_bytes, void *d_ws, size_t ws_bytes, void *stream, aaq_resident **out);
+aaq_status aaq_resident_execute(aaq_resident *r, const double *d_params, double *d_out, void *stream);
+void aaq_resident_destroy(aaq_resident *r);
+
 /* ---------------------------------------------------------------- final-state sampling
  * The read-out the paper's approximation ratios come from: bitstrings z drawn with
  * probability |psi(z)|^2 from the depth-p QAOA state (its results section samples the

@@ -48,7 +48,8 @@ EXPORTS = (
     "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
     "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed", "aaq_lightcone_info",
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
-    "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample",
+    "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample", "aaq_resident_workspace_size",
+    "aaq_resident_create", "aaq_resident_execute", "aaq_resident_destroy",
 )
 
 
@@ -96,6 +97,10 @@ def lib():
         "aaq_lightcone_create": (i, [P, i, i, i, ctypes.POINTER(CPlanOpts), vp, sz, vp, ctypes.POINTER(vp)]),
         "aaq_lightcone_execute": (i, [vp, vp, vp, vp]),
         "aaq_lightcone_destroy": (None, [vp]),
+        "aaq_resident_workspace_size": (i, [P, i, i, i, i, i, szp, szp]),
+        "aaq_resident_create": (i, [P, i, i, i, i, i, vp, sz, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]),
+        "aaq_resident_execute": (i, [vp, vp, vp, vp]),
+        "aaq_resident_destroy": (None, [vp]),
         "aaq_sample_workspace_size": (i, [P, i, i, szp]),
         "aaq_sample": (i, [P, i, dp, dp, i, i, vp, vp, sz, vp, sz, vp, vp, vp, dp, dp]),
         "aaq_edge_orbits": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

@@ -339,6 +339,36 @@ def aaq_edge_orbits(n: int, edges, edge_weight=None):
     return of[:m].copy(), rep[:k.value].copy(), size[:k.value].copy()
 
 
+def aaq_resident_workspace_size(prob: Problem, p: int, obs: int, with_grad: bool, checkpoint: bool = False,
+                                prec: int = AAQ_PREC_C64):
+    """(workspace bytes, state bytes) of a resident evaluator."""
+    wb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.lib().aaq_resident_workspace_size(prob.ref(), int(p), int(obs), int(bool(with_grad)),
+                                                  int(bool(checkpoint)), int(prec), ctypes.byref(wb), ctypes.byref(sb)))
+    return wb.value, sb.value
+
+
+def aaq_resident_create(prob: Problem, p: int, obs: int, with_grad: bool, checkpoint: bool, prec: int, d_state, d_lam,
+                        d_ws, stream=None):
+    sp, sb = _dev(d_state)
+    lp, lb = _dev(d_lam)
+    wp, wb = _dev(d_ws)
+    h = ctypes.c_void_p()
+    _check(_lib.lib().aaq_resident_create(prob.ref(), int(p), int(obs), int(bool(with_grad)), int(bool(checkpoint)),
+                                          int(prec), sp, sb, lp, lb, wp, wb, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def aaq_resident_execute(handle, d_params, d_out, stream=None) -> None:
+    pp, _ = _dev(d_params)
+    op, _ = _dev(d_out)
+    _check(_lib.lib().aaq_resident_execute(handle, pp, op, _stream(stream)))
+
+
+def aaq_resident_destroy(handle) -> None:
+    _lib.lib().aaq_resident_destroy(handle)
+
+
 def aaq_lightcone_info(prob: Problem, p: int, obs: int = AAQ_OBS_HRED):
     """(units, largest cone in qubits, total amplitudes of all cone states)."""
     u, mq, amp = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
@@ -546,3 +576,49 @@ class Sampler:
         best, mean = aaq_sample(self.prob, gamma, beta, self.prec, self.uniform, self.state, self.ws, self.samples,
                                 self.cuts, stream)
         return self.samples.cpu().numpy().view(np.uint64), self.cuts.cpu().numpy(), best, mean
+
+
+class Resident:
+    """Device-resident evaluation of one instance (aaq_resident_*): owns the state, lambda
+    and workspace buffers (torch).  ``execute(params, out)`` takes device float64 tensors
+    [2p] (gamma then beta) and [2 + 2p] (energy, norm, dgamma, dbeta) and returns without
+    synchronising."""
+
+    def __init__(self, prob: Problem, p: int, obs: int = AAQ_OBS_HRED, with_grad: bool = True,
+                 checkpoint: bool = False, prec: int = AAQ_PREC_C64, device: str = "cuda", stream=None):
+        import torch
+
+        self.prob, self.p, self.obs, self.with_grad = prob, int(p), obs, with_grad
+        wb, sb = aaq_resident_workspace_size(prob, p, obs, with_grad, checkpoint, prec)
+        self.state = torch.empty(sb, dtype=torch.uint8, device=device)
+        self.lam = torch.empty(aaq_state_bytes(prob, prec), dtype=torch.uint8, device=device) if with_grad else None
+        self.ws = torch.empty(wb, dtype=torch.uint8, device=device)
+        self.handle = aaq_resident_create(prob, p, obs, with_grad, checkpoint, prec, self.state, self.lam, self.ws,
+                                          stream)
+        self.params = torch.zeros(2 * self.p, dtype=torch.float64, device=device)
+        self.out = torch.zeros(2 + 2 * self.p, dtype=torch.float64, device=device)
+
+    def execute(self, params=None, out=None, stream=None):
+        o = self.out if out is None else out
+        aaq_resident_execute(self.handle, self.params if params is None else params, o, stream)
+        return o
+
+    def energy_grad(self, gamma, beta, stream=None):
+        """Synchronous convenience: (energy, dE/dgamma, dE/dbeta, norm) as numpy."""
+        import torch
+
+        g, b = _params(gamma, beta)
+        self.params.copy_(torch.from_numpy(np.concatenate([g, b])))
+        o = self.execute(stream=stream).cpu().numpy()
+        return o[0], o[2:2 + self.p].copy(), o[2 + self.p:].copy(), o[1]
+
+    def close(self):
+        if self.handle:
+            aaq_resident_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

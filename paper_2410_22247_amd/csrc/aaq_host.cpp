@@ -567,6 +567,7 @@ constexpr int kZZBlocks = 1024;
 struct Single {
   int n, p, T, cmax, L, k, nbuf;
   bool dbl, grad;
+  bool weighted = false;  // integer edge weights: the sweeps take the run-time path
   aaq_aggregation agg;
   std::vector<SetSpec> sets;
   std::vector<int4> terms;  // plain term list, then the per-set sorted lists
@@ -594,6 +595,7 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.agg = agg;
   S.T = (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
   S.cmax = total_weight(pr);
+  S.weighted = is_weighted(pr);
   S.L = tile;
   S.sets = make_sets(S.n, S.L);
   S.terms = term_array(pr, obs, S.L, S.sets);
@@ -706,6 +708,101 @@ unsigned char* pinned_staging(size_t bytes) {
   return buf;
 }
 
+// checks the caller's buffers against a host plan
+aaq_status check_buffers(const Single& S, bool grad, void* d_state, size_t state_bytes, void* d_lam, size_t lam_bytes,
+                         void* d_ws, size_t ws_bytes) {
+  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
+  if (state_bytes < need_state * S.nbuf)
+    return fail(AAQ_ERR_BUFFER, S.nbuf > 1 ? "checkpoint buffer smaller than the forward states it holds"
+                                           : "state buffer smaller than 2^n amplitudes");
+  if (grad) {
+    if (!d_lam) return fail(AAQ_ERR_INVALID_ARG, "d_lambda is NULL");
+    if (lam_bytes < need_state) return fail(AAQ_ERR_BUFFER, "lambda buffer smaller than 2^n amplitudes");
+  }
+  if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
+  if (ws_bytes < S.lay.total) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(S.lay.total) + " bytes)");
+  return AAQ_OK;
+}
+
+// the parameter-independent part of the upload block (graph, terms, reduction sources,
+// sweep programs, tile sets) into the staging area `up`
+void stage_static(const Single& S, const aaq_problem* pr, aaq_observable obs, unsigned char* up) {
+  const Layout& L = S.lay;
+  std::memset(up, 0, L.upload_end);
+  GraphDev g = make_graph(pr);
+  g.T = S.T;
+  g.h_is_cut = obs == AAQ_OBS_HC && !g.weighted;
+  std::memcpy(up + L.graph, &g, sizeof(g));
+  if (!S.terms.empty()) std::memcpy(up + L.terms, S.terms.data(), sizeof(int4) * S.terms.size());
+  if (!S.src.empty()) std::memcpy(up + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
+  std::memcpy(up + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
+  std::memcpy(up + L.progs, S.progs.data(), sizeof(SweepProg) * S.progs.size());
+  std::memcpy(up + L.sets, S.sets.data(), sizeof(SetSpec) * S.sets.size());
+}
+
+// One evaluation on the device, asynchronous on `hs`: phase tables from the device
+// parameters, the sweeps, the pass-per-term <ZZ> passes, and the fixed-order reduction
+// into d_out (energy, norm, dgamma[p], dbeta[p], then per-term sums).  The workspace
+// holds the uploaded static block.
+aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, unsigned char* ws, const double* d_gamma,
+                       const double* d_beta, double* d_out, hipStream_t hs) {
+  const Layout& L = S.lay;
+  const int p = S.p;
+  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  const bool weighted = S.weighted;
+  const aaq_aggregation agg = S.agg;
+  {
+    TimedLaunch tl(KC_TABLES, 0.0, hs);
+    HIPCHK(launch_tables(d_gamma, d_beta, p, S.cmax, ws + L.tab, (const SweepProg*)(ws + L.progs), L.nsweep,
+                         (const SetSpec*)(ws + L.sets), (int)S.sets.size(), (SwScale*)(ws + L.scales), S.dbl, hs));
+    tl.done();
+  }
+  for (int sw = 0; sw < L.nsweep; ++sw) {
+    LaunchSweep A;
+    A.psi = d_state;
+    A.lam = grad ? d_lam : nullptr;
+    A.g = (const GraphDev*)(ws + L.graph);
+    A.terms = (const int4*)(ws + L.terms);
+    A.tab = ws + L.tab;
+    A.scale = (const SwScale*)(ws + L.scales) + sw;
+    A.partial = (double*)(ws + L.partial) + (size_t)sw * L.nslot * L.ntiles;
+    A.nslot = L.nslot;
+    A.T = S.T;
+    A.cmax = S.cmax;
+    A.amp = std::exp2(-0.5 * S.n);
+    A.N = (uint64_t)1 << S.n;
+    A.set = S.sets[S.progs[sw].set];
+    A.prog = S.progs[sw];
+    A.two_states = needs_two_states(S.progs[sw]);
+    A.generic = weighted;
+    const SweepProg& pg = S.progs[sw];
+    const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
+                      !!(pg.flags & F_STORE_LAM);
+    TimedLaunch tl(A.two_states ? KC_SWEEP2 : KC_SWEEP1, (double)moves * (double)need_state, hs);
+    HIPCHK(launch_sweep(A, S.dbl, S.L, hs));
+    tl.done();
+  }
+  if (agg == AAQ_AGG_PASS_PER_TERM) {
+    double* zp = (double*)(ws + L.partial) + (size_t)L.nsweep * L.nslot * L.ntiles;
+    for (int t = 0; t < S.T; ++t) {
+      TimedLaunch tl(KC_ZZPASS, (double)need_state, hs);
+      HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, S.terms[t].x, S.terms[t].y,
+                            &((const SwScale*)(ws + L.scales) + L.nsweep)->s_pre,
+                            &((const SwScale*)(ws + L.scales) + L.nsweep)->F_pre, zp + (size_t)t * kZZBlocks, kZZBlocks,
+                            S.dbl, hs));
+      tl.done();
+    }
+  }
+  {
+    TimedLaunch tl(KC_REDUCE, 0.0, hs);
+    HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb),
+                         (double*)(ws + L.stage), d_out, L.nout, hs));
+    tl.done();
+  }
+  return AAQ_OK;
+}
+
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
                       void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
@@ -728,17 +825,7 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
     have_last = true;
   }
   const Single& S = last_plan;
-  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
-  if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
-  if (state_bytes < need_state * S.nbuf)
-    return fail(AAQ_ERR_BUFFER, S.nbuf > 1 ? "checkpoint buffer smaller than the forward states it holds"
-                                           : "state buffer smaller than 2^n amplitudes");
-  if (grad) {
-    if (!d_lam) return fail(AAQ_ERR_INVALID_ARG, "d_lambda is NULL");
-    if (lam_bytes < need_state) return fail(AAQ_ERR_BUFFER, "lambda buffer smaller than 2^n amplitudes");
-  }
-  if (!d_ws) return fail(AAQ_ERR_INVALID_ARG, "workspace is NULL");
-  if (ws_bytes < S.lay.total) return fail(AAQ_ERR_BUFFER, "workspace too small (need " + std::to_string(S.lay.total) + " bytes)");
+  if ((st = check_buffers(S, grad, d_state, state_bytes, d_lam, lam_bytes, d_ws, ws_bytes))) return st;
   const Layout& L = S.lay;
   hipStream_t hs = (hipStream_t)stream;
   unsigned char* ws = (unsigned char*)d_ws;
@@ -746,69 +833,13 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   // asynchronous, and the call ends with a stream synchronisation)
   unsigned char* up = pinned_staging(L.upload_end + sizeof(double) * L.nout);
   if (!up) return fail(AAQ_ERR_HIP, "hipHostMalloc of the staging buffer failed");
-  std::memset(up, 0, L.upload_end);
-  GraphDev g = make_graph(pr);
-  const std::vector<int4>& terms = S.terms;
-  g.T = S.T;
-  g.h_is_cut = obs == AAQ_OBS_HC && !g.weighted;
-  std::memcpy(up + L.graph, &g, sizeof(g));
-  if (!terms.empty()) std::memcpy(up + L.terms, terms.data(), sizeof(int4) * terms.size());
+  stage_static(S, pr, obs, up);
   std::memcpy(up + L.params, gamma, sizeof(double) * p);
   std::memcpy(up + L.params + sizeof(double) * p, beta, sizeof(double) * p);
-  if (!S.src.empty()) std::memcpy(up + L.src, S.src.data(), sizeof(RedSrcHost) * S.src.size());
-  std::memcpy(up + L.srcb, S.srcb.data(), sizeof(int32_t) * S.srcb.size());
-  std::memcpy(up + L.progs, S.progs.data(), sizeof(SweepProg) * S.progs.size());
-  std::memcpy(up + L.sets, S.sets.data(), sizeof(SetSpec) * S.sets.size());
   HIPCHK(hipMemcpyAsync(ws, up, L.upload_end, hipMemcpyHostToDevice, hs));
   const double* dparams = (const double*)(ws + L.params);
-  {
-    TimedLaunch tl(KC_TABLES, 0.0, hs);
-    HIPCHK(launch_tables(dparams, dparams + p, p, S.cmax, ws + L.tab, (const SweepProg*)(ws + L.progs), L.nsweep,
-                         (const SetSpec*)(ws + L.sets), (int)S.sets.size(), (SwScale*)(ws + L.scales), S.dbl, hs));
-    tl.done();
-  }
-  for (int sw = 0; sw < L.nsweep; ++sw) {
-    LaunchSweep A;
-    A.psi = d_state;
-    A.lam = grad ? d_lam : nullptr;
-    A.g = (const GraphDev*)(ws + L.graph);
-    A.terms = (const int4*)(ws + L.terms);
-    A.tab = ws + L.tab;
-    A.scale = (const SwScale*)(ws + L.scales) + sw;
-    A.partial = (double*)(ws + L.partial) + (size_t)sw * L.nslot * L.ntiles;
-    A.nslot = L.nslot;
-    A.T = S.T;
-    A.cmax = S.cmax;
-    A.amp = std::exp2(-0.5 * S.n);
-    A.N = (uint64_t)1 << S.n;
-    A.set = S.sets[S.progs[sw].set];
-    A.prog = S.progs[sw];
-    A.two_states = needs_two_states(S.progs[sw]);
-    A.generic = g.weighted != 0;
-    const SweepProg& pg = S.progs[sw];
-    const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
-                      !!(pg.flags & F_STORE_LAM);
-    TimedLaunch tl(A.two_states ? KC_SWEEP2 : KC_SWEEP1, (double)moves * (double)need_state, hs);
-    HIPCHK(launch_sweep(A, S.dbl, S.L, hs));
-    tl.done();
-  }
-  if (agg == AAQ_AGG_PASS_PER_TERM) {
-    double* zp = (double*)(ws + L.partial) + (size_t)L.nsweep * L.nslot * L.ntiles;
-    for (int t = 0; t < S.T; ++t) {
-      TimedLaunch tl(KC_ZZPASS, (double)need_state, hs);
-      HIPCHK(launch_zz_pass(d_state, (uint64_t)1 << S.n, terms[t].x, terms[t].y,
-                            &((const SwScale*)(ws + L.scales) + L.nsweep)->s_pre,
-                            &((const SwScale*)(ws + L.scales) + L.nsweep)->F_pre, zp + (size_t)t * kZZBlocks, kZZBlocks,
-                            S.dbl, hs));
-      tl.done();
-    }
-  }
-  {
-    TimedLaunch tl(KC_REDUCE, 0.0, hs);
-    HIPCHK(launch_reduce((const double*)(ws + L.partial), ws + L.src, (const int32_t*)(ws + L.srcb),
-                         (double*)(ws + L.stage), (double*)(ws + L.out), L.nout, hs));
-    tl.done();
-  }
+  if ((st = launch_eval(S, grad, d_state, d_lam, ws, dparams, dparams + p, (double*)(ws + L.out), hs))) return st;
+  const std::vector<int4>& terms = S.terms;
   double* down = (double*)(up + L.upload_end);
   HIPCHK(hipMemcpyAsync(down, ws + L.out, sizeof(double) * L.nout, hipMemcpyDeviceToHost, hs));
   HIPCHK(hipStreamSynchronize(hs));
@@ -1247,6 +1278,75 @@ aaq_status aaq_energy_grad_checkpointed(const aaq_problem* prob, int p, const do
   }
   return AAQ_OK;
 }
+
+// ---------------------------------------------------------------- resident evaluator
+}  // extern "C"
+
+struct aaq_resident {
+  Single S;
+  bool grad = false;
+  void* d_state = nullptr;
+  void* d_lam = nullptr;
+  unsigned char* ws = nullptr;
+};
+
+namespace {
+aaq_status resident_plan(const aaq_problem* prob, int p, aaq_observable obs, int with_grad, int checkpoint,
+                         aaq_precision prec, Single& S) {
+  aaq_status s = validate_problem(prob);
+  if (s) return s;
+  if ((s = validate_p(p))) return s;
+  const bool grad = with_grad != 0;
+  const int tile = chosen_tile_bits(prob->n, prec == AAQ_PREC_C128, grad);
+  return plan_single(prob, p, grad, obs, AAQ_AGG_FUSED, prec, tile, S, true, checkpoint != 0 && grad);
+}
+}  // namespace
+
+extern "C" {
+
+aaq_status aaq_resident_workspace_size(const aaq_problem* prob, int p, aaq_observable obs, int with_grad, int checkpoint,
+                                       aaq_precision prec, size_t* ws_bytes, size_t* state_bytes) {
+  if (!ws_bytes || !state_bytes) return fail(AAQ_ERR_INVALID_ARG, "ws_bytes / state_bytes is NULL");
+  Single S;
+  aaq_status s = resident_plan(prob, p, obs, with_grad, checkpoint, prec, S);
+  if (s) return s;
+  *ws_bytes = S.lay.total;
+  *state_bytes = (size_t)S.nbuf * ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  return AAQ_OK;
+}
+
+aaq_status aaq_resident_create(const aaq_problem* prob, int p, aaq_observable obs, int with_grad, int checkpoint,
+                               aaq_precision prec, void* d_state, size_t state_bytes, void* d_lambda,
+                               size_t lambda_bytes, void* d_ws, size_t ws_bytes, void* stream, aaq_resident** out) {
+  if (!out) return fail(AAQ_ERR_INVALID_ARG, "out is NULL");
+  auto R = std::make_unique<aaq_resident>();
+  aaq_status s = resident_plan(prob, p, obs, with_grad, checkpoint, prec, R->S);
+  if (s) return s;
+  R->grad = with_grad != 0;
+  if ((s = check_buffers(R->S, R->grad, d_state, state_bytes, d_lambda, lambda_bytes, d_ws, ws_bytes))) return s;
+  R->d_state = d_state;
+  R->d_lam = R->grad ? d_lambda : nullptr;
+  R->ws = (unsigned char*)d_ws;
+  // the static block goes up once; the copy completes before the staging area is reused
+  const Layout& L = R->S.lay;
+  unsigned char* up = pinned_staging(L.upload_end);
+  if (!up) return fail(AAQ_ERR_HIP, "hipHostMalloc of the staging buffer failed");
+  stage_static(R->S, prob, obs, up);
+  hipStream_t hs = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(R->ws, up, L.upload_end, hipMemcpyHostToDevice, hs));
+  HIPCHK(hipStreamSynchronize(hs));
+  *out = R.release();
+  return AAQ_OK;
+}
+
+aaq_status aaq_resident_execute(aaq_resident* r, const double* d_params, double* d_out, void* stream) {
+  if (!r) return fail(AAQ_ERR_INVALID_ARG, "evaluator is NULL");
+  if (!d_params || !d_out) return fail(AAQ_ERR_INVALID_ARG, "d_params / d_out is NULL");
+  return launch_eval(r->S, r->grad, r->d_state, r->d_lam, r->ws, d_params, d_params + r->S.p, d_out,
+                     (hipStream_t)stream);
+}
+
+void aaq_resident_destroy(aaq_resident* r) { delete r; }
 
 aaq_status aaq_sample_workspace_size(const aaq_problem* prob, int p, aaq_precision prec, size_t* bytes) {
   aaq_status s = validate_problem(prob);
