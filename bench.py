@@ -232,6 +232,11 @@ def main():
         "kernel_timing": {c: {"launches": v["launches"], "ms": round(v["total_ms"], 3),
                               "GB/s": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["bytes"] else None}
                           for c, v in timing.items()},
+        # the stricter per-evaluation figure: the method's lower bound on state traffic for
+        # energy + gradient (6 p S: one read and one write of psi per layer forward, psi and
+        # lambda per layer backward) over the whole evaluation time
+        "eval_lower_bound": {"bytes": 6 * p * (8 << wp.n), "GB/s": round(6 * p * (8 << wp.n) / (ms_per_step * 1e-3) / 1e9, 1),
+                             "frac": round(6 * p * (8 << wp.n) / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "sweep_bytes_per_eval": sweep_bytes / args.steps,
         "sweep_GBps_per_eval": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1) if sweep_ms else None,
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / args.steps, 4),
