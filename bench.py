@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time for the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b", "lc", "sample", "weighted"],
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b", "lc", "sample", "weighted", "adam"],
                     help="c3 (default): the n=26 p=4 energy+gradient headline; the others print their own line")
     ap.add_argument("--grad-mode", default="checkpoint", choices=["checkpoint", "uncompute"],
                     help="checkpoint: forward states kept in HBM, backward sweeps read them (default); "

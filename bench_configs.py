@@ -21,6 +21,9 @@ weighted  the n=26 p=4 tree with integer edge weights 1..4 (seeded): energy + gr
      (checkpoints) through the run-time sweep path, against the same tree unweighted,
      and the weighted light-cone evaluation; parity against the weighted light-cone
      FP64 adjoint.
+adam  the n=26 p=4 tree: 200 Adam steps (lr 0.01) maximising <H_red> from the first seeded
+     point, device-resident (parameters, optimizer and outputs on the GPU) and through the
+     synchronous host API; <H_C> and the expectation ratio at the end.
 """
 import math
 import time
@@ -279,6 +282,37 @@ def weighted(args):
                         "checkpoints)", "unit": "evals/s", "results": res}
 
 
+def adam(args):
+    from paper_2410_22247_amd.autograd import adam_maximize, adam_maximize_resident
+
+    wp, p, gam, bet = C.config3(1)
+    pr = A.Problem.from_workload(wp)
+    steps, lr = 200, 0.01
+    res = A.Resident(pr, p, A.AAQ_OBS_HRED, with_grad=True, checkpoint=True)
+    adam_maximize_resident(res, gam[0], bet[0], steps=3, lr=lr)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g_r, b_r, h_r = adam_maximize_resident(res, gam[0], bet[0], steps=steps, lr=lr)
+    t_res = time.perf_counter() - t
+    res.close()
+    est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g_h, b_h, h_h = adam_maximize(est, gam[0], bet[0], steps=steps, lr=lr)
+    t_host = time.perf_counter() - t
+    e_hc = est.energy_grad(g_r, b_r, obs=A.AAQ_OBS_HC)[0]
+    e_red = est.energy_grad(g_r, b_r)[0]
+    cmax = len(wp.edges())  # trees are bipartite
+    return {"workload": "adam: n=26 p=4 tree, 200 Adam steps (lr 0.01) maximising <H_red> from the first seeded "
+                        "point (complex64, checkpoints)", "unit": "ms/step",
+            "results": {"resident_ms_per_step": round(1e3 * t_res / steps, 3),
+                        "host_api_ms_per_step": round(1e3 * t_host / steps, 3),
+                        "energy_start": float(h_r[0, 0]), "energy_end_H_red": float(e_red),
+                        "energy_end_H_C": float(e_hc), "expectation_ratio_end": float(e_hc / cmax),
+                        "max_abs_diff_trajectories": float(np.max(np.abs(h_r[:, 0] - h_h))),
+                        "gamma_end": g_r.tolist(), "beta_end": b_r.tolist()}}
+
+
 def run(name, args):
     torch.cuda.set_device(0)
-    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc, "sample": sample, "weighted": weighted}[name](args)
+    return {"c1": c1, "c2": c2, "c4": c4, "c5a": c5a, "c5b": c5b, "lc": lc, "sample": sample, "weighted": weighted, "adam": adam}[name](args)

@@ -55,7 +55,28 @@ def adam_maximize(est: "api.Estimator", gamma0, beta0, steps: int = 200, lr: flo
         e = qaoa_energy(gamma, beta, est)
         (-e).backward()
         opt.step()
-        hist.append(float(e))
+        hist.append(float(e.detach()))
         if log_every and k % log_every == 0:
             print(json.dumps({"step": k, "energy": hist[-1]}), flush=True)
     return gamma.detach().cpu().numpy(), beta.detach().cpu().numpy(), np.asarray(hist)
+
+
+def adam_maximize_resident(res: "api.Resident", gamma0, beta0, steps: int = 200, lr: float = 0.01):
+    """The same Adam loop with everything on the device: the parameters are one float64
+    tensor [gamma, beta] on the evaluator's device, each step runs the resident
+    evaluation (aaq_resident_execute) into a row of a device history and feeds
+    -dE/dtheta to torch.optim.Adam, all in stream order with no host synchronisation.
+
+    Returns (gamma, beta, history) with history[k] = [E, norm, dE/dgamma, dE/dbeta] at
+    the parameters before step k (numpy, read once at the end)."""
+    p = res.p
+    x = torch.tensor(np.concatenate([np.asarray(gamma0, dtype=np.float64), np.asarray(beta0, dtype=np.float64)]),
+                     device=res.params.device, requires_grad=True)
+    opt = torch.optim.Adam([x], lr=lr)
+    hist = torch.zeros(steps, 2 + 2 * p, dtype=torch.float64, device=x.device)
+    for k in range(steps):
+        res.execute(x.detach(), hist[k])
+        x.grad = -hist[k, 2:]
+        opt.step()
+    xs = x.detach().cpu().numpy()
+    return xs[:p], xs[p:], hist.cpu().numpy()

@@ -128,3 +128,26 @@ def test_resident_n26_config3():
     r.close()
     del r
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+def test_resident_adam_matches_host_adam():
+    """The device-resident Adam loop follows the host-API loop (identical gradients per
+    evaluation; only the optimizer's own rounding on GPU vs CPU can differ) and raises
+    the expected cut."""
+    from paper_2410_22247_amd.autograd import adam_maximize, adam_maximize_resident
+
+    g = G.binary_tree(15)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    r = A.Resident(pr, 2, OBS_HRED, with_grad=True)
+    est = A.Estimator(pr, 2, OBS_HRED, A.AAQ_PREC_C64, grad=True)
+    g_r, b_r, h_r = adam_maximize_resident(r, [0.4, 0.9], [0.6, 0.3], steps=30, lr=0.05)
+    g_h, b_h, h_h = adam_maximize(est, [0.4, 0.9], [0.6, 0.3], steps=30, lr=0.05)
+    assert np.max(np.abs(h_r[:, 0] - h_h)) <= 1e-9 * np.max(np.abs(h_h))
+    assert np.allclose(np.concatenate([g_r, b_r]), np.concatenate([g_h, b_h]), rtol=0, atol=1e-9)
+    assert h_r[-1, 0] > h_r[0, 0] + 0.5
+    e_end = O.energy(g.n, g.edge_array(), wp.terms(OBS_HRED), g_r, b_r)
+    e_dev = r.energy_grad(g_r, b_r)[0]
+    assert abs(e_dev - e_end) <= EREL * abs(e_end)
+    r.close()
