@@ -54,7 +54,7 @@ typedef enum {
   AAQ_ERR_ORBITS = 3,      /* orbit sizes do not sum to |E|, bad representative */
   AAQ_ERR_PARAMS = 4,      /* non-finite gamma or beta                         */
   AAQ_ERR_BUFFER = 5,      /* state / lambda / workspace buffer too small      */
-  AAQ_ERR_UNSUPPORTED = 6, /* valid request this build does not support        */
+  AAQ_ERR_UNSUPPORTED = 6, /* valid request the library does not support       */
   AAQ_ERR_HIP = 7          /* a HIP runtime call failed                        */
 } aaq_status;
 
