@@ -1,0 +1,104 @@
+"""The method at the limits the library states: the largest depth (p = 64), the largest
+phase table (total cut weight 560 of the 561 allowed, on K_20), single-edge and
+single-vertex instances, and depths whose checkpoint count exceeds the buffer limit.
+
+CPU: the error paths of these limits.
+GPU: parity with the FP64 oracle at the limits (tolerances as in test_gpu_parity, the
+weighted complex64 gradient reading of test_weighted)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2410_22247_amd as A
+from workloads import graphs as G
+from workloads.configs import OBS_HC, OBS_HRED, make_problem
+
+
+def check(e, dg, db, e_ref, dg_ref, db_ref, tol, e_scale=False):
+    assert abs(e - e_ref) <= tol * max(abs(e_ref), 1e-12), (e, e_ref)
+    g, gr = np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref])
+    scale = max(np.linalg.norm(gr), abs(e_ref) if e_scale else 0.0, 1e-12)
+    assert np.linalg.norm(g - gr) <= tol * scale, (g, gr)
+
+
+def k20_weights():
+    # 185 edges of weight 3 and 5 of weight 1: total 560
+    return np.concatenate([np.full(185, 3), np.ones(5)]).astype(np.int32)
+
+
+# ------------------------------------------------------------------ host (CPU)
+def test_limit_errors():
+    pr = A.Problem.from_workload(make_problem(G.binary_tree(7)))
+    A.aaq_validate(pr, 64)
+    with pytest.raises(A.AAQError) as e:
+        A.aaq_validate(pr, 65)
+    assert e.value.status == 1
+    # forward-state checkpoints: one buffer per forward sweep, at most 32
+    big = A.Problem.from_workload(make_problem(G.prufer_tree(26, 3)))
+    A.aaq_checkpoint_bytes(big, 15, A.AAQ_PREC_C64)
+    with pytest.raises(A.AAQError) as e:
+        A.aaq_checkpoint_bytes(big, 20, A.AAQ_PREC_C64)
+    assert e.value.status == 6
+    g = G.complete(20)
+    A.aaq_validate(A.Problem(g.n, g.edge_array(), edge_weight=k20_weights()), 1)
+
+
+# ------------------------------------------------------------------ GPU
+@pytest.mark.gpu
+@pytest.mark.parametrize("g", [G.binary_tree(9), G.prufer_tree(14, 2)], ids=lambda g: g.name)
+def test_depth_64(g):
+    """p = 64: 64 phase tables, 64 layers of sweeps forward and back."""
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(64)
+    gam, bet = rng.uniform(0, 0.3, 64), rng.uniform(0, 0.3, 64)
+    for obs in (OBS_HRED, OBS_HC):
+        e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), wp.terms(obs), gam, bet)
+        for prec, tol in ((A.AAQ_PREC_C128, 1e-10), (A.AAQ_PREC_C64, 1e-5)):
+            est = A.Estimator(pr, 64, obs, prec, grad=True)
+            e, dg, db, nrm = est.energy_grad(gam, bet)
+            check(e, dg, db, e_ref, dg_ref, db_ref, tol)
+            assert abs(nrm - 1) <= (1e-12 if prec == A.AAQ_PREC_C128 else 1e-4)
+
+
+@pytest.mark.gpu
+def test_largest_phase_table_k20_weighted():
+    """Total cut weight 560: 561-entry phase tables in LDS, C(z) up to 560."""
+    import torch
+
+    g = G.complete(20)
+    w = k20_weights()
+    pr = A.Problem(g.n, g.edge_array(), edge_weight=w)
+    ti, tj = g.edge_array()[:, 0], g.edge_array()[:, 1]
+    terms = (ti, tj, w.astype(np.float64))
+    gam, bet = np.array([0.013, 0.021]), np.array([0.4, 0.7])
+    e_ref, dg_ref, db_ref = O.energy_grad(g.n, g.edge_array(), terms, gam, bet, weights=w)
+    for prec, tol in ((A.AAQ_PREC_C128, 1e-10), (A.AAQ_PREC_C64, 1e-5)):
+        est = A.Estimator(pr, 2, OBS_HC, prec, grad=True)
+        e, dg, db, _ = est.energy_grad(gam, bet)
+        check(e, dg, db, e_ref, dg_ref, db_ref, tol, prec == A.AAQ_PREC_C64)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    out = torch.empty(1 << g.n, dtype=torch.int32, device="cuda")
+    A.aaq_cut_values(pr, OBS_HC, ws, out)
+    cut = out.cpu().numpy()
+    assert np.array_equal(cut, O.cut_values(g.n, g.edge_array(), w))
+    assert cut.max() <= 560
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("p", [1, 5, 17])
+def test_single_edge_any_depth(p):
+    """One edge: the p = 1 value is 1/2 + (1/2) sin 4b sin g; any depth against the oracle."""
+    g = G.Graph(2, [(0, 1)])
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(p)
+    gam, bet = rng.uniform(0, math.pi, p), rng.uniform(0, math.pi / 2, p)
+    e_ref, dg_ref, db_ref = O.energy_grad(2, g.edge_array(), wp.terms(OBS_HC), gam, bet)
+    if p == 1:
+        assert abs(e_ref - (0.5 + 0.5 * math.sin(4 * bet[0]) * math.sin(gam[0]))) < 1e-14
+    est = A.Estimator(pr, p, OBS_HC, A.AAQ_PREC_C128, grad=True)
+    e, dg, db, _ = est.energy_grad(gam, bet)
+    check(e, dg, db, e_ref, dg_ref, db_ref, 1e-10)
