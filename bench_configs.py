@@ -45,6 +45,28 @@ def _timed(fn, reps):
     return (time.perf_counter() - t) / reps
 
 
+def _oracle_rate(fn, count, runs=5, threads=0):
+    """Median over `runs` timed runs (after one warm-up call) of `count` oracle
+    evaluations fn(i), as evaluations per second; threads > 0 pins the oracle's thread
+    count for the measurement.  Returns (rate, threads used)."""
+    import oracle as O
+
+    full = O.num_threads()
+    if threads:
+        O.set_num_threads(threads)
+    try:
+        fn(0)
+        ts = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            for i in range(count):
+                fn(i)
+            ts.append(time.perf_counter() - t)
+        return count / float(np.median(ts)), O.num_threads()
+    finally:
+        O.set_num_threads(full)
+
+
 def _plan_rate(units, p, obs, grad, gam, bet, prec=A.AAQ_PREC_C64, reps=10):
     plan = A.Plan(units, p, obs, with_grad=grad, prec=prec)
     plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
@@ -68,8 +90,16 @@ def c1(args):
         res[name + "_energies"] = out[:, 0]
     diff = float(np.max(np.abs(res["H_C_energies"] - res["H_red_energies"])))
     del res["H_C_energies"], res["H_red_energies"]
+    import oracle as O
+
+    terms = wp.terms(A.AAQ_OBS_HRED)
+    ev = lambda i: O.energy(wp.n, wp.edges(), terms, gam[i], bet[i])  # noqa: E731
+    r_all, t_all = _oracle_rate(ev, 256)
+    r_one, _ = _oracle_rate(ev, 256, threads=1)
     return {"workload": "c1: binary tree n=15 p=1, 256-point grid, complex128", "unit": "evals/s", "results": res,
-            "max_abs_HC_minus_Hred": diff}
+            "max_abs_HC_minus_Hred": diff,
+            "cpu_oracle": {"evals_s": round(r_all, 1), "threads": t_all, "evals_s_1_thread": round(r_one, 1),
+                           "kind": "FP64 full-state oracle, H_red energy, all 256 points, median of 5 runs"}}
 
 
 def c2(args):
@@ -100,6 +130,11 @@ def c2(args):
             else:
                 rel = np.abs(outs[oname][idx] - ref_s) / np.abs(ref_s)
             r[oname + "_max_rel_err"] = float(rel.max())
+        terms = wp.terms(A.AAQ_OBS_HRED)
+        cnt = {"K16": 64, "star20": 8}.get(name, 2)
+        rate_o, thr = _oracle_rate(lambda i: O.energy(wp.n, wp.edges(), terms, gam[i], bet[i]), cnt)
+        r["cpu_oracle"] = {"evals_s": round(rate_o, 2), "threads": thr,
+                           "kind": f"FP64 full-state oracle, H_red energy, first {cnt} points, median of 5 runs"}
         res[name] = r
     return {"workload": "c2: K16 p=1, star20 p=2, 3reg22 p=3; 256 points each, complex64, batched plans",
             "unit": "evals/s", "results": res}
@@ -132,7 +167,13 @@ def c4(args):
         rel_e.append(abs(out[i, 0] - e) / abs(e))
         gr = np.concatenate([dg, db])
         rel_g.append(np.linalg.norm(out[i, 2:] - gr) / np.linalg.norm(gr))
+    rate_o, thr = _oracle_rate(lambda k: O.energy_grad(probs[sample[k]].n, probs[sample[k]].edges(),
+                                                       probs[sample[k]].terms(1), gam[sample[k]], bet[sample[k]]),
+                               len(sample))
     return {"workload": "c4: 512 mixed graphs n=8..18, p=2, H_red energy + adjoint gradient", "unit": "evals/s",
+            "cpu_oracle": {"evals_s": round(rate_o, 1), "threads": thr,
+                           "kind": f"FP64 full-state oracle energy + adjoint gradient, every 16th instance "
+                                   f"({len(sample)}), median of 5 runs"},
             "batched_evals_s": round(rate, 1), "plain_evals_s": round(len(prs) / dt_plain, 1),
             "batched_over_plain": round(rate * dt_plain / len(prs), 2),
             "max_rel_err_energy_sample": float(max(rel_e)), "max_rel_err_grad_sample": float(max(rel_g)),

@@ -45,6 +45,8 @@ def lib():
         L.orc_energy_grad.argtypes = [ci, ci, i32p, wp, ci, i32p, i32p, f64p, ci, f64p, f64p, dptr, f64p, f64p,
                                       dptr]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [ci]
+        L.orc_set_num_threads.restype = None
         for f in ("orc_cut_values", "orc_term_values", "orc_state", "orc_zz", "orc_energy", "orc_energy_grad",
                   "orc_num_threads"):
             getattr(L, f).restype = ci
@@ -75,6 +77,11 @@ def _terms(terms):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(int(t))
 
 
 def cut_values(n: int, edges, weights=None) -> np.ndarray:

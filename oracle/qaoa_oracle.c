@@ -236,3 +236,12 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* thread count of the following parallel loops (timing at a fixed count) */
+void orc_set_num_threads(int t) {
+#ifdef _OPENMP
+  if (t > 0) omp_set_num_threads(t);
+#else
+  (void)t;
+#endif
+}
