@@ -274,12 +274,24 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   //   + sum_{edges (v, w) inside m} 2 (2 [b_v != b_w] - 1),
   // d_v = deg v - 2 #{neighbours u with b_u != b_v}.
   template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, const GraphDev* g, int (&cv)[NR]) const {
+    // every index bit is below n: with n <= 32 the masks fit 32-bit registers, which
+    // halves the vector work of the mask arithmetic (uniform branch)
+    if (g->n <= 32)
+      cuts_m<K, uint32_t>(S, zb, g, cv);
+    else
+      cuts_m<K, uint64_t>(S, zb, g, cv);
+  }
+  static __device__ __forceinline__ int popc(uint32_t x) { return __popc(x); }
+  static __device__ __forceinline__ int popc(uint64_t x) { return __popcll(x); }
+  template <int K, class M>
+  __device__ __forceinline__ void cuts_m(const SetSpec& S, uint64_t zb64, const GraphDev* g, int (&cv)[NR]) const {
     constexpr int B0 = G::b0(K);
     const int n = g->n;
+    const M zb = (M)zb64;
     int c0 = 0;
     for (int v = 0; v < n; ++v) {
-      const uint64_t av = g->adj[v];
-      c0 += (int)((zb >> v) & 1u) * __popcll(av & ~zb);
+      const M av = (M)g->adj[v];
+      c0 += (int)((zb >> v) & 1u) * popc((M)(av & ~zb));
     }
     int d[RB];
     uint32_t rr[RB], df[RB];
@@ -290,9 +302,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       rr[b] = 0;
       df[b] = 0;
       if (v != kDummy) {
-        const uint64_t av = g->adj[v];
-        const uint64_t bv = (zb >> v) & 1u;
-        d[b] = g->deg[v] - 2 * __popcll(av & (zb ^ (0ull - bv)));
+        const M av = (M)g->adj[v];
+        const M bv = (zb >> v) & 1u;
+        d[b] = g->deg[v] - 2 * popc((M)(av & (zb ^ ((M)0 - bv))));
 #pragma unroll
         for (int b2 = 0; b2 < RB; ++b2) {
           const uint32_t w = S.pos[B0 + b2];
