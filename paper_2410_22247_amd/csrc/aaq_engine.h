@@ -330,19 +330,30 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // endpoints sit in register bits: with base zb (register bits 0) and x_t the term's
   // value there, h(zb ^ m) = h0 + sum_{b in m} dh_b + sum over both-endpoint terms of
   // the pair correction -2 w (1 - 2x) when m holds both endpoints.
-  template <int K> __device__ __forceinline__ void hvals(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR]) const {
+  template <int K> __device__ __forceinline__ void hvals(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR],
+                                                         bool n32) const {
     static_assert(K == LAST || K == P, "term lists exist for the load and phase arrangements");
     constexpr int KI = (K == LAST) ? 0 : 1;
-    hsum(zb, terms + S.toff[KI], S.tcnt[KI], hv);
+    if (n32)
+      hsum<uint32_t>(zb, terms + S.toff[KI], S.tcnt[KI], hv);
+    else
+      hsum<uint64_t>(zb, terms + S.toff[KI], S.tcnt[KI], hv);
   }
   // the weighted cut C(z) = sum_e w_e [z_u != z_v] from the set's cost-term lists
-  template <int K> __device__ __forceinline__ void wcuts(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR]) const {
+  template <int K> __device__ __forceinline__ void wcuts(const SetSpec& S, uint64_t zb, const int4* terms, int (&hv)[NR],
+                                                         bool n32) const {
     static_assert(K == LAST || K == P, "term lists exist for the load and phase arrangements");
     constexpr int KI = (K == LAST) ? 0 : 1;
-    hsum(zb, terms + S.coff[KI], S.ccnt[KI], hv);
+    if (n32)
+      hsum<uint32_t>(zb, terms + S.coff[KI], S.ccnt[KI], hv);
+    else
+      hsum<uint64_t>(zb, terms + S.coff[KI], S.ccnt[KI], hv);
   }
   // the sum over one grouped term list (counts: the six group sizes)
-  __device__ __forceinline__ void hsum(uint64_t zb, const int4* tp, const uint16_t (&cnt)[6], int (&hv)[NR]) const {
+  // (M: the index mask type, 32 bits when n <= 32)
+  template <class M>
+  __device__ __forceinline__ void hsum(uint64_t zb64, const int4* tp, const uint16_t (&cnt)[6], int (&hv)[NR]) const {
+    const M zb = (M)zb64;
     auto xbit = [&](const int4& tm) -> int { return (int)(((uint32_t)(zb >> tm.x) ^ (uint32_t)(zb >> tm.y)) & 1u); };
     int h0 = 0;
     int dh[RB];
@@ -414,7 +425,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (cx.g->h_is_cut)
         cuts<K>(S, zb, cx.g, hv);
       else
-        hvals<K>(S, zb, cx.terms, hv);
+        hvals<K>(S, zb, cx.terms, hv, cx.g->n <= 32);
       double e = 0.0, nr = 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -756,7 +767,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (cx.g->h_is_cut)
         cuts<K>(S, zb, cx.g, hv);
       else
-        hvals<K>(S, zb, cx.terms, hv);
+        hvals<K>(S, zb, cx.terms, hv, cx.g->n <= 32);
       double e = 0.0, nr = 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -780,7 +791,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
       if (cx.g->weighted)
-        wcuts<K>(S, zb, cx.terms, cv);
+        wcuts<K>(S, zb, cx.terms, cv, cx.g->n <= 32);
       else
         cuts<K>(S, zb, cx.g, cv);
       if (NS == 2 && (ops & OP_GRADG)) {
@@ -1184,7 +1195,7 @@ __global__ __launch_bounds__(1 << (LT - kRegBits)) void k_cuts(const GraphDev* g
   const uint64_t zb = tl.template zbase<KK>(S, tile_base, 0ull);
   int v[G::NR];
   if (use_terms)
-    tl.template hvals<KK>(S, zb, terms, v);
+    tl.template hvals<KK>(S, zb, terms, v, g->n <= 32);
   else
     tl.template cuts<KK>(S, zb, g, v);
   const uint32_t t = threadIdx.x;
