@@ -989,6 +989,18 @@ template <class R> struct SweepArgs {
 // SIMD, the occupancy the tile LDS allows anyway; the generic sweeps are left to the
 // compiler.
 constexpr int sweep_waves_per_eu(uint32_t kind) { return (kind & SK_GENERIC) ? 1 : 4; }
+// partial-sum slots a sweep shape can fill (SLOT_* bits; the generic sweeps: all six)
+constexpr uint32_t sweep_slots(uint32_t kind) {
+  if (kind & SK_GENERIC) return 0x3Fu;
+  const uint32_t ops = sk_pre(kind) | sk_mid(kind);
+  uint32_t m = 0;
+  if (ops & OP_ENERGY) m |= (1u << SLOT_E) | (1u << SLOT_NORM);
+  if (sk_pre(kind) & OP_GRADG) m |= 1u << SLOT_GPRE;
+  if (sk_mid(kind) & OP_GRADG) m |= 1u << SLOT_GMID;
+  if (kind & SK_MIXA) m |= 1u << SLOT_BA;
+  if (kind & SK_MIXB) m |= 1u << SLOT_BB;
+  return m;
+}
 #define AAQ_SWEEP_BOUNDS(KIND) \
   __launch_bounds__(1 << (LT - kRegBits)) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu(KIND))))
 
@@ -1021,14 +1033,22 @@ __global__ AAQ_SWEEP_BOUNDS(KIND) void k_sweep(SweepArgs<R> A) {
   else
     tl.template run<RT, KIND>(A.prog, A.set, sc, tile, cx, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
   const uint32_t nt = A.set.ntiles;
-  // only sweeps with an accumulating step write partial sums (the reduction reads no others)
+  // only sweeps with an accumulating step write partial sums (the reduction reads no
+  // others), and a specialised shape only the slots its steps can fill
   if (((A.prog.pre_ops | A.prog.mid_ops) & (OP_ENERGY | OP_GRADG)) || A.prog.mixA_grad || A.prog.mixB_grad) {
     scale_acc(acc, A.prog, sc);
-    double v[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
-    block_sum<6, G::NT>(v, red);
+    constexpr uint32_t SLOTS = sweep_slots(KIND);
+    constexpr int NV = __builtin_popcount(SLOTS);
+    const double all[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+    double v[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0, k = 0; i < 6; ++i)
+      if ((SLOTS >> i) & 1u) v[k++] = all[i];
+    if constexpr (NV > 0) block_sum<NV, G::NT>(v, red);
     if (threadIdx.x == 0) {
 #pragma unroll
-      for (int i = 0; i < 6; ++i) A.partial[(size_t)i * nt + tile] = v[i];
+      for (int i = 0, k = 0; i < 6; ++i)
+        if ((SLOTS >> i) & 1u) A.partial[(size_t)i * nt + tile] = v[k++];
     }
   }
   if (PT) {
