@@ -213,6 +213,23 @@ def test_energy_grad_n26_config3_point():
     check_energy(est.energy(gams[0], bets[0])[0], e_full)
 
 
+def test_energy_grad_n26_config3_complex128():
+    """The same kernels instantiated for complex128 at the full n = 26, p = 4 size (two
+    1 GiB states, and checkpoints), against the light-cone FP64 adjoint at 1e-10."""
+    from workloads.configs import config3
+
+    wp, p, gams, bets = config3(1)
+    pr = A.Problem.from_workload(wp)
+    e_lc, dg_lc, db_lc, _ = Rd.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(OBS_HRED), gams[0], bets[0])
+    for ckpt in (False, True):
+        est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C128, grad=True, checkpoint=ckpt)
+        e, dg, db, nrm = est.energy_grad(gams[0], bets[0])
+        check_energy(e, e_lc, 1e-10)
+        check_grad(np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc]), 1e-10)
+        assert abs(nrm - 1) < 1e-12
+        _release(est)
+
+
 def _release(*objs):
     for o in objs:
         del o

@@ -155,3 +155,26 @@ def test_sample_n26_config3_full_size():
     assert np.all(np.diff(zs.astype(np.int64)) >= 0)
     del s
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+def test_sample_n33_config5b_full_size():
+    """n = 33, p = 2 (a 64 GiB state): cut values exact, bitstrings in range, mean sampled
+    cut within six standard errors of the light-cone FP64 <H_C>."""
+    import torch
+
+    from workloads.configs import config5b
+
+    wp, p, gams, bets = config5b(1)
+    pr = A.Problem.from_workload(wp)
+    shots = 1 << 14
+    u = np.random.default_rng(33).random(shots)
+    s = A.Sampler(pr, p, shots)
+    z, cuts, best, mean = s.sample(gams[0], bets[0], u)
+    assert np.all(z < (1 << wp.n))
+    assert np.array_equal(cuts, cut_of(wp.edges(), z))
+    assert best == cuts.max()
+    e = Rd.light_cone_energy_grad(wp.n, wp.edges(), wp.terms(OBS_HC), gams[0], bets[0])[0]
+    assert abs(mean - e) <= 6 * cuts.std() / math.sqrt(shots)
+    del s
+    torch.cuda.empty_cache()
