@@ -276,6 +276,19 @@ aaq_status aaq_resident_create(const aaq_problem *prob, int p, aaq_observable ob
 aaq_status aaq_resident_execute(aaq_resident *r, const double *d_params, double *d_out, void *stream);
 void aaq_resident_destroy(aaq_resident *r);
 
+/* ---------------------------------------------------------------- half state
+ * MaxCut QAOA states are invariant under flipping every bit (|+>, the cut phase and the
+ * mixer all commute with the global flip; so are h and lambda = h psi), so the single-
+ * instance and resident evaluations store and sweep only the amplitudes with bit n-1 = 0
+ * and double every sum (the same results up to rounding order, half the state traffic
+ * and half the vector work).  Used when the program has at least two tile sets, every
+ * byte offset of 2^n amplitudes fits 32 bits (n <= 29 complex64, n <= 28 complex128), and
+ * the call neither keeps the final state (sampling) nor passes over it per term.  On by
+ * default; the switch is process-wide and takes effect at the next call (it is part of
+ * the cached host plan's key).  State buffers sized by aaq_state_bytes stay valid. */
+void aaq_set_half_state(int enable);
+int aaq_get_half_state(void);
+
 /* ---------------------------------------------------------------- final-state sampling
  * The read-out the paper's approximation ratios come from: bitstrings z drawn with
  * probability |psi(z)|^2 from the depth-p QAOA state (its results section samples the

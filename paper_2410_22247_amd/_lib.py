@@ -49,7 +49,8 @@ EXPORTS = (
     "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed", "aaq_lightcone_info",
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
     "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample", "aaq_resident_workspace_size",
-    "aaq_resident_create", "aaq_resident_execute", "aaq_resident_destroy",
+    "aaq_resident_create", "aaq_resident_execute", "aaq_resident_destroy", "aaq_set_half_state",
+    "aaq_get_half_state",
 )
 
 
@@ -101,6 +102,8 @@ def lib():
         "aaq_resident_create": (i, [P, i, i, i, i, i, vp, sz, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]),
         "aaq_resident_execute": (i, [vp, vp, vp, vp]),
         "aaq_resident_destroy": (None, [vp]),
+        "aaq_set_half_state": (None, [i]),
+        "aaq_get_half_state": (i, []),
         "aaq_sample_workspace_size": (i, [P, i, i, szp]),
         "aaq_sample": (i, [P, i, dp, dp, i, i, vp, vp, sz, vp, sz, vp, vp, vp, dp, dp]),
         "aaq_edge_orbits": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

@@ -369,6 +369,15 @@ def aaq_resident_destroy(handle) -> None:
     _lib.lib().aaq_resident_destroy(handle)
 
 
+def aaq_set_half_state(enable: bool) -> None:
+    """Process-wide switch of the spin-flip half state (on by default)."""
+    _lib.lib().aaq_set_half_state(int(bool(enable)))
+
+
+def aaq_get_half_state() -> bool:
+    return bool(_lib.lib().aaq_get_half_state())
+
+
 def aaq_lightcone_info(prob: Problem, p: int, obs: int = AAQ_OBS_HRED):
     """(units, largest cone in qubits, total amplitudes of all cone states)."""
     u, mq, amp = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()

@@ -549,14 +549,28 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       __builtin_amdgcn_raw_buffer_store_b128(
           __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0)), x), rs, (int)vo, (int)so, 0);
   }
-  template <int K, bool OFF32> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t toff,
-                                                                         const SetSpec& S) {
+  // Register r's element is index toff + roff[r] (toff = tile_base + the thread's
+  // offset), or, when r is in S.mirror (half state, its index has bit n-1 set), the
+  // mirrored index mfull - (toff + roff[r]): the thread part tmax - thread offset and the
+  // uniform part mfull - tile_base - roff[r] - tmax, both >= 0 (the parts are disjoint
+  // bit fields of the index).
+  template <int K, bool OFF32> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base,
+                                                                         uint64_t toff, const SetSpec& S) {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
-      if (!S.dummy) {
+      if (!S.dummy && !S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[s][r] = buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      } else if (S.mirror) {
+        const uint32_t bm = (uint32_t)(S.tmax - (toff - tile_base)) * (uint32_t)sizeof(V);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const bool m = (S.mirror >> r) & 1u;
+          const uint32_t so = m ? (uint32_t)(S.mfull - tile_base - S.roff[r] - S.tmax) * (uint32_t)sizeof(V)
+                                : (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
+          a[s][r] = buf_load(rs, m ? bm : bo, so);
+        }
       } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -564,23 +578,36 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     } else {
       const V* p = base + toff;
-      if (!S.dummy) {
+      if (!S.dummy && !S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+      } else if (S.mirror) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          a[s][r] = ((S.mirror >> r) & 1u) ? base[S.mfull - toff - S.roff[r]] : p[S.roff[r]];
       } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : p[S.roff[r]];
       }
     }
   }
-  template <int K, bool OFF32> __device__ __forceinline__ void store_regs(int s, V* base, uint64_t toff,
-                                                                          const SetSpec& S) const {
+  template <int K, bool OFF32> __device__ __forceinline__ void store_regs(int s, V* base, uint64_t tile_base,
+                                                                          uint64_t toff, const SetSpec& S) const {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
-      if (!S.dummy) {
+      if (!S.dummy && !S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) buf_store(a[s][r], rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+      } else if (S.mirror) {
+        const uint32_t bm = (uint32_t)(S.tmax - (toff - tile_base)) * (uint32_t)sizeof(V);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const bool m = (S.mirror >> r) & 1u;
+          const uint32_t so = m ? (uint32_t)(S.mfull - tile_base - S.roff[r] - S.tmax) * (uint32_t)sizeof(V)
+                                : (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
+          buf_store(a[s][r], rs, m ? bm : bo, so);
+        }
       } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -588,9 +615,17 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     } else {
       V* p = base + toff;
-      if (!S.dummy) {
+      if (!S.dummy && !S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) p[S.roff[r]] = a[s][r];
+      } else if (S.mirror) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if ((S.mirror >> r) & 1u)
+            base[S.mfull - toff - S.roff[r]] = a[s][r];
+          else
+            p[S.roff[r]] = a[s][r];
+        }
       } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -598,21 +633,21 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     }
   }
-  template <int K> __device__ __forceinline__ void load_all(int s, const V* base, uint64_t toff, const SetSpec& S,
-                                                            bool off32) {
+  template <int K> __device__ __forceinline__ void load_all(int s, const V* base, uint64_t tile_base, uint64_t toff,
+                                                            const SetSpec& S, bool off32) {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
     if (off32)
-      load_regs<K, true>(s, base, toff, S);
+      load_regs<K, true>(s, base, tile_base, toff, S);
     else
-      load_regs<K, false>(s, base, toff, S);
+      load_regs<K, false>(s, base, tile_base, toff, S);
   }
-  template <int K> __device__ __forceinline__ void store_all(int s, V* base, uint64_t toff, const SetSpec& S,
-                                                             bool off32) const {
+  template <int K> __device__ __forceinline__ void store_all(int s, V* base, uint64_t tile_base, uint64_t toff,
+                                                             const SetSpec& S, bool off32) const {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
     if (off32)
-      store_regs<K, true>(s, base, toff, S);
+      store_regs<K, true>(s, base, tile_base, toff, S);
     else
-      store_regs<K, false>(s, base, toff, S);
+      store_regs<K, false>(s, base, tile_base, toff, S);
   }
   template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
 #pragma unroll
@@ -673,9 +708,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
     } else {
       const uint64_t toff = tile_base + thread_off<KL>(S);
-      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, toff, S, cx.off32);
+      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32);
       if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
-        load_all<KL>(NS - 1, cx.lam, toff, S, cx.off32);
+        load_all<KL>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -716,8 +751,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     // opaque to the compiler: the store addresses are formed here, not kept in
     // registers from the loads (that would hold 2 VGPRs per register and state)
     asm volatile("" : "+v"(toff));
-    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N, toff, S, cx.off32);
-    if (st_lam) store_all<LAST>(NS - 1, cx.lam, toff, S, cx.off32);
+    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N, tile_base, toff, S, cx.off32);
+    if (st_lam) store_all<LAST>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
   }
 
   // ================================================================ run-time-flag path
@@ -864,10 +899,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base + thread_off<KL>(S), S, cx.off32);
+      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
-        load_all<KL>(NS - 1, cx.lam, tile_base + thread_off<KL>(S), S, cx.off32);
+        load_all<KL>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -903,8 +938,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
     if ((st_psi || st_lam) && at_p) xchg_rt<P, KL>(lds_x);
-    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N, tile_base + thread_off<KL>(S), S, cx.off32);
-    if (st_lam) store_all<KL>(NS - 1, cx.lam, tile_base + thread_off<KL>(S), S, cx.off32);
+    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+    if (st_lam) store_all<KL>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
   }
   __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                           const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,
@@ -1032,7 +1067,7 @@ __global__ AAQ_SWEEP_BOUNDS(KIND) void k_sweep(SweepArgs<R> A) {
     tl.template run_rt<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
   else
     tl.template run<RT, KIND>(A.prog, A.set, sc, tile, cx, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
-  const uint32_t nt = A.set.ntiles;
+  const uint32_t nt = gridDim.x;  // tiles of this launch (half of the set's with the half state)
   // only sweeps with an accumulating step write partial sums (the reduction reads no
   // others), and a specialised shape only the slots its steps can fill
   if (((A.prog.pre_ops | A.prog.mid_ops) & (OP_ENERGY | OP_GRADG)) || A.prog.mixA_grad || A.prog.mixB_grad) {
@@ -1246,7 +1281,7 @@ template <class R, int RT, int LT>
 static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t dyn, hipStream_t st) {
   const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
   const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
-  const dim3 grid(L.set.ntiles), blk(Geo<R, LT>::NT);
+  const dim3 grid(L.set.ntiles >> (L.half ? 1 : 0)), blk(Geo<R, LT>::NT);
   switch (L.generic ? SK_GENERIC : sweep_kind(L.prog)) {
     case SK_F_FIRST: return sweep_launch_kind<R, RT, LT, SK_F_FIRST>(A, grid, blk, dyn, st);
     case SK_F_PLAIN: return sweep_launch_kind<R, RT, LT, SK_F_PLAIN>(A, grid, blk, dyn, st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -568,6 +569,7 @@ struct Single {
   int n, p, T, cmax, L, k, nbuf;
   bool dbl, grad;
   bool weighted = false;  // integer edge weights: the sweeps take the run-time path
+  bool half = false;      // half state (spin-flip symmetry): 2^(n-1) stored amplitudes
   aaq_aggregation agg;
   std::vector<SetSpec> sets;
   std::vector<int4> terms;  // plain term list, then the per-set sorted lists
@@ -578,11 +580,46 @@ struct Single {
   Layout lay;
 };
 
+// The global spin-flip symmetry of MaxCut QAOA: |+>, the cut phase (C(~z) = C(z)) and the
+// mixer commute with flipping every bit, and so do h and lambda = h psi, so every buffer the
+// sweeps touch (sigma psi(z ^ F), lambda) takes equal values at z and ~z.  The half state
+// keeps the indices below 2^(n-1); each sweep runs the tiles below ntiles / 2.  Sets other
+// than the last hold bit n-1 as the top tile-id bit, so those tiles lie in the stored half;
+// the last set holds bit n-1 as its top tile bit (a register bit at the load arrangement),
+// and the registers with that bit set read and write the mirrored index 2^n - 1 - index,
+// which is the complement tile's stored element.  Every stored amplitude is then touched
+// once per sweep, and every sum counts one of each equal pair.
+std::atomic<bool> g_half_state{true};
+
+bool half_state_ok(const Single& S, aaq_aggregation agg, bool keep_state) {
+  if (!g_half_state || S.k < 2 || agg == AAQ_AGG_PASS_PER_TERM || keep_state) return false;
+  // every byte offset of the full index range within 32 bits (the mirrored offsets)
+  if ((((uint64_t)1 << S.n) * (S.dbl ? 16u : 8u)) > ((uint64_t)1 << 32)) return false;
+  const SetSpec& last = S.sets.back();
+  const int b0l = geo_b0(geo_na(S.L) - 1, S.L);
+  if (last.pos[S.L - 1] != S.n - 1 || b0l + kRegBits != S.L) return false;
+  for (size_t i = 0; i + 1 < S.sets.size(); ++i)  // bit n-1 is the top tile-id bit
+    if (!((S.sets[i].fixmask >> (S.n - 1)) & 1u)) return false;
+  return true;
+}
+
+void mark_mirror(Single& S) {
+  SetSpec& last = S.sets.back();
+  const int b0l = geo_b0(geo_na(S.L) - 1, S.L);
+  last.mirror = 0;
+  for (int r = 0; r < (1 << kRegBits); ++r)
+    if ((last.roff[r] >> (S.n - 1)) & 1u) last.mirror |= (uint16_t)(1u << r);
+  last.tmax = 0;
+  for (int j = 0; j < b0l; ++j)
+    if (last.pos[j] != kDummy) last.tmax |= (uint64_t)1 << last.pos[j];
+  last.mfull = ((uint64_t)1 << S.n) - 1;
+}
+
 // grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
 // sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
 aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aaq_aggregation agg,
                        aaq_precision prec, int tile, Single& S, bool with_grids = false, bool ckpt = false,
-                       bool keep_state = false) {
+                       bool keep_state = false, bool allow_half = true) {
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (agg != AAQ_AGG_FUSED && agg != AAQ_AGG_PER_TERM && agg != AAQ_AGG_PASS_PER_TERM)
     return fail(AAQ_ERR_INVALID_ARG, "bad aggregation");
@@ -604,12 +641,16 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   S.progs = build_progs(S.k, p, grad, eops, agg == AAQ_AGG_PASS_PER_TERM || keep_state, ckpt && grad && S.k >= 2);
   S.nbuf = prog_buffers(S.progs);
   if (S.nbuf > kMaxCkpt) return fail(AAQ_ERR_UNSUPPORTED, "too many checkpoint states for this depth (max 32)");
+  S.half = allow_half && half_state_ok(S, agg, keep_state);
+  if (S.half) mark_mirror(S);
   Layout& L = S.lay;
   L.nsweep = (int)S.progs.size();
   L.T = S.T;
   L.nslot = SLOT_TERMS + (agg == AAQ_AGG_PER_TERM ? S.T : 0);
-  L.ntiles = (int)S.sets[0].ntiles;
+  L.ntiles = (int)S.sets[0].ntiles >> (S.half ? 1 : 0);
   const bool zzp = agg == AAQ_AGG_PASS_PER_TERM;
+  // with the half state every sum covers one of each pair (z, ~z) of equal terms
+  const double hs = S.half ? 2.0 : 1.0;
   L.nout = 2 + 2 * p + ((agg != AAQ_AGG_FUSED) ? S.T : 0);
   // reduction sources
   std::vector<std::vector<RedSrcHost>> per(L.nout);
@@ -618,7 +659,7 @@ aaq_status plan_single(const aaq_problem* pr, int p, bool grad, aaq_observable o
   for (int sw = 0; sw < L.nsweep; ++sw) {
     const SweepProg& s = S.progs[sw];
     const int np = S.grids[sw];
-    auto add = [&](int o, int slot, double scale) { per[o].push_back({part_off(sw, slot), np, o, scale}); };
+    auto add = [&](int o, int slot, double scale) { per[o].push_back({part_off(sw, slot), np, o, hs * scale}); };
     if ((s.pre_ops | s.mid_ops) & OP_ENERGY) {
       add(0, SLOT_E, 1.0);
       add(1, SLOT_NORM, 1.0);
@@ -682,7 +723,7 @@ PlanKey plan_key(const aaq_problem* pr, int p, bool grad, aaq_observable obs, aa
                  int tile, bool ckpt, bool keep_state) {
   PlanKey k;
   k.v = {pr->n, pr->num_edges, pr->num_orbits, p, (int)grad, (int)obs, (int)agg, (int)prec, tile, (int)ckpt,
-         pr->edge_orbit ? 1 : 0, (int)keep_state};
+         pr->edge_orbit ? 1 : 0, (int)keep_state, (int)g_half_state.load()};
   k.v.insert(k.v.end(), pr->edges, pr->edges + 2 * pr->num_edges);
   if (pr->num_orbits > 0) {
     k.v.insert(k.v.end(), pr->orbit_rep, pr->orbit_rep + pr->num_orbits);
@@ -711,7 +752,7 @@ unsigned char* pinned_staging(size_t bytes) {
 // checks the caller's buffers against a host plan
 aaq_status check_buffers(const Single& S, bool grad, void* d_state, size_t state_bytes, void* d_lam, size_t lam_bytes,
                          void* d_ws, size_t ws_bytes) {
-  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  const size_t need_state = ((size_t)1 << (S.n - (S.half ? 1 : 0))) * (S.dbl ? 16 : 8);
   if (!d_state) return fail(AAQ_ERR_INVALID_ARG, "d_state is NULL");
   if (state_bytes < need_state * S.nbuf)
     return fail(AAQ_ERR_BUFFER, S.nbuf > 1 ? "checkpoint buffer smaller than the forward states it holds"
@@ -749,7 +790,8 @@ aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, u
                        const double* d_beta, double* d_out, hipStream_t hs) {
   const Layout& L = S.lay;
   const int p = S.p;
-  const size_t need_state = ((size_t)1 << S.n) * (S.dbl ? 16 : 8);
+  const int nst = S.n - (S.half ? 1 : 0);  // stored amplitudes per state: 2^nst
+  const size_t need_state = ((size_t)1 << nst) * (S.dbl ? 16 : 8);
   const bool weighted = S.weighted;
   const aaq_aggregation agg = S.agg;
   {
@@ -771,11 +813,12 @@ aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, u
     A.T = S.T;
     A.cmax = S.cmax;
     A.amp = std::exp2(-0.5 * S.n);
-    A.N = (uint64_t)1 << S.n;
+    A.N = (uint64_t)1 << nst;
     A.set = S.sets[S.progs[sw].set];
     A.prog = S.progs[sw];
     A.two_states = needs_two_states(S.progs[sw]);
     A.generic = weighted;
+    A.half = S.half;
     const SweepProg& pg = S.progs[sw];
     const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
                       !!(pg.flags & F_STORE_LAM);
@@ -1202,11 +1245,12 @@ aaq_status aaq_workspace_size(const aaq_problem* prob, int p, int with_grad, aaq
   if ((s = validate_p(p))) return s;
   if (!bytes) return fail(AAQ_ERR_INVALID_ARG, "bytes is NULL");
   size_t mx = 0;
-  for (int tile : {12, 13}) {  // any tile choice fits
-    Single S;
-    if ((s = plan_single(prob, p, with_grad != 0, obs, agg, prec, tile, S))) return s;
-    mx = std::max(mx, S.lay.total);
-  }
+  for (int tile : {12, 13})  // any tile choice and either state mode fits
+    for (bool half : {true, false}) {
+      Single S;
+      if ((s = plan_single(prob, p, with_grad != 0, obs, agg, prec, tile, S, false, false, false, half))) return s;
+      mx = std::max(mx, S.lay.total);
+    }
   *bytes = mx;
   return AAQ_OK;
 }
@@ -1347,6 +1391,9 @@ aaq_status aaq_resident_execute(aaq_resident* r, const double* d_params, double*
 }
 
 void aaq_resident_destroy(aaq_resident* r) { delete r; }
+
+void aaq_set_half_state(int enable) { g_half_state = enable != 0; }
+int aaq_get_half_state(void) { return g_half_state ? 1 : 0; }
 
 aaq_status aaq_sample_workspace_size(const aaq_problem* prob, int p, aaq_precision prec, size_t* bytes) {
   aaq_status s = validate_problem(prob);

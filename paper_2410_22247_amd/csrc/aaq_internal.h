@@ -108,6 +108,15 @@ struct SetSpec {
   // cost phase and the gamma gradient of weighted instances (empty otherwise).
   uint16_t coff[2];
   uint16_t ccnt[2][6];
+  // Half state (the global spin-flip symmetry psi(~z) = psi(z)): only indices below
+  // 2^(n-1) are stored.  Registers whose index has bit n-1 set (mask `mirror`) live at
+  // the mirrored index mfull - index (mfull = 2^n - 1); tmax is the largest thread offset
+  // at the load arrangement.  mirror = 0 outside half mode and for sets that hold bit
+  // n-1 in the tile id (their processed tiles are all below 2^(n-1)).
+  uint16_t mirror;
+  uint16_t pad2[3];
+  uint64_t tmax;
+  uint64_t mfull;
 };
 
 struct SweepProg {

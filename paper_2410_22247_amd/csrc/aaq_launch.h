@@ -27,6 +27,7 @@ struct LaunchSweep {
   SweepProg prog;
   bool two_states;
   bool generic = false;  // take every step from the program at run time (weighted instances)
+  bool half = false;     // half state: the grid covers the tiles below ntiles / 2
 };
 
 struct LaunchUnits {
