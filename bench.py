@@ -290,6 +290,22 @@ def main():
                 diff = max(diff, float(np.max(np.abs(got[k] - want) / np.maximum(np.abs(want), 1e-300))))
             out["host_api"] = {"evals_s": round(rate(lambda: est.energy_grad(g0, b0)), 2),
                                "max_rel_diff_vs_resident": diff}
+        if half:
+            # the same evaluation with every amplitude stored and swept (host API both ways)
+            flat = lambda r: np.concatenate([[r[0]], r[1], r[2]])
+            want = flat(est.energy_grad(g0, b0))
+            r_half = rate(lambda: est.energy_grad(g0, b0))
+            A.aaq_set_half_state(0)
+            try:
+                est_full = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=True, checkpoint=ckpt)
+                got = flat(est_full.energy_grad(g0, b0))
+                r_full = rate(lambda: est_full.energy_grad(g0, b0))
+                del est_full
+            finally:
+                A.aaq_set_half_state(1)
+            out["full_state"] = {"evals_s": round(r_full, 2), "half_state_evals_s": round(r_half, 2),
+                                 "speedup": round(r_half / r_full, 3),
+                                 "max_rel_diff_vs_half": float(np.max(np.abs(got - want)) / np.max(np.abs(want)))}
 
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu_baseline:

@@ -533,7 +533,15 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // `base` (stride 0, every offset below 2^32 in range), the thread's byte offset in one
   // vector register and register r's byte offset roff[r] as a scalar offset.
   static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)0xFFFFFFFF, 0x00020000);
+    // the base is the same for every lane; say so, so that the descriptor lives in
+    // scalar registers (a descriptor in vector registers makes every access a loop).
+    // readfirstlane returns a signed int: each half is widened as unsigned, or a low
+    // word with bit 31 set would sign-extend into the high word of the address
+    const uint64_t b = (uint64_t)base;
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)0xFFFFFFFF, 0x00020000);
   }
   static __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(V) == 8)
@@ -554,22 +562,23 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // mirrored index mfull - (toff + roff[r]): the thread part tmax - thread offset and the
   // uniform part mfull - tile_base - roff[r] - tmax, both >= 0 (the parts are disjoint
   // bit fields of the index).
-  template <int K, bool OFF32> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base,
+  template <int K, bool OFF32, bool MIR> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base,
                                                                          uint64_t toff, const SetSpec& S) {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
-      if (!S.dummy && !S.mirror) {
+      if (!S.dummy && !(MIR && S.mirror)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[s][r] = buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
-      } else if (S.mirror) {
+      } else if (MIR && S.mirror) {
         const uint32_t bm = (uint32_t)(S.tmax - (toff - tile_base)) * (uint32_t)sizeof(V);
+        // uniform over the workgroup: the mirrored registers' scalar offsets are su - roff
+        const uint32_t su = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((S.mfull - tile_base - S.tmax) * sizeof(V)));
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
+          const uint32_t ro = (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
           const bool m = (S.mirror >> r) & 1u;
-          const uint32_t so = m ? (uint32_t)(S.mfull - tile_base - S.roff[r] - S.tmax) * (uint32_t)sizeof(V)
-                                : (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
-          a[s][r] = buf_load(rs, m ? bm : bo, so);
+          a[s][r] = buf_load(rs, m ? bm : bo, m ? su - ro : ro);
         }
       } else {
 #pragma unroll
@@ -578,10 +587,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     } else {
       const V* p = base + toff;
-      if (!S.dummy && !S.mirror) {
+      if (!S.dummy && !(MIR && S.mirror)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
-      } else if (S.mirror) {
+      } else if (MIR && S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
           a[s][r] = ((S.mirror >> r) & 1u) ? base[S.mfull - toff - S.roff[r]] : p[S.roff[r]];
@@ -591,22 +600,22 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     }
   }
-  template <int K, bool OFF32> __device__ __forceinline__ void store_regs(int s, V* base, uint64_t tile_base,
+  template <int K, bool OFF32, bool MIR> __device__ __forceinline__ void store_regs(int s, V* base, uint64_t tile_base,
                                                                           uint64_t toff, const SetSpec& S) const {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
-      if (!S.dummy && !S.mirror) {
+      if (!S.dummy && !(MIR && S.mirror)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) buf_store(a[s][r], rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
-      } else if (S.mirror) {
+      } else if (MIR && S.mirror) {
         const uint32_t bm = (uint32_t)(S.tmax - (toff - tile_base)) * (uint32_t)sizeof(V);
+        const uint32_t su = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((S.mfull - tile_base - S.tmax) * sizeof(V)));
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
+          const uint32_t ro = (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
           const bool m = (S.mirror >> r) & 1u;
-          const uint32_t so = m ? (uint32_t)(S.mfull - tile_base - S.roff[r] - S.tmax) * (uint32_t)sizeof(V)
-                                : (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
-          buf_store(a[s][r], rs, m ? bm : bo, so);
+          buf_store(a[s][r], rs, m ? bm : bo, m ? su - ro : ro);
         }
       } else {
 #pragma unroll
@@ -615,10 +624,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     } else {
       V* p = base + toff;
-      if (!S.dummy && !S.mirror) {
+      if (!S.dummy && !(MIR && S.mirror)) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) p[S.roff[r]] = a[s][r];
-      } else if (S.mirror) {
+      } else if (MIR && S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if ((S.mirror >> r) & 1u)
@@ -633,21 +642,25 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     }
   }
-  template <int K> __device__ __forceinline__ void load_all(int s, const V* base, uint64_t tile_base, uint64_t toff,
-                                                            const SetSpec& S, bool off32) {
+  // MIR: the route can hold bit n-1 among the tile bits (sets of high qubits), so the
+  // half state's mirrored registers are possible; false compiles them out
+  template <int K, bool MIR = true>
+  __device__ __forceinline__ void load_all(int s, const V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
+                                           bool off32) {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
     if (off32)
-      load_regs<K, true>(s, base, tile_base, toff, S);
+      load_regs<K, true, MIR>(s, base, tile_base, toff, S);
     else
-      load_regs<K, false>(s, base, tile_base, toff, S);
+      load_regs<K, false, MIR>(s, base, tile_base, toff, S);
   }
-  template <int K> __device__ __forceinline__ void store_all(int s, V* base, uint64_t tile_base, uint64_t toff,
-                                                             const SetSpec& S, bool off32) const {
+  template <int K, bool MIR = true>
+  __device__ __forceinline__ void store_all(int s, V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
+                                            bool off32) const {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
     if (off32)
-      store_regs<K, true>(s, base, tile_base, toff, S);
+      store_regs<K, true, MIR>(s, base, tile_base, toff, S);
     else
-      store_regs<K, false>(s, base, tile_base, toff, S);
+      store_regs<K, false, MIR>(s, base, tile_base, toff, S);
   }
   template <int K> __device__ __forceinline__ void init_at(const SetSpec& S, R amp) {
 #pragma unroll
@@ -708,9 +721,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
     } else {
       const uint64_t toff = tile_base + thread_off<KL>(S);
-      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32);
+      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32);
       if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
-        load_all<KL>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
+        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -751,8 +764,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     // opaque to the compiler: the store addresses are formed here, not kept in
     // registers from the loads (that would hold 2 VGPRs per register and state)
     asm volatile("" : "+v"(toff));
-    if (st_psi) store_all<LAST>(0, cx.psi + pg.st_buf * cx.N, tile_base, toff, S, cx.off32);
-    if (st_lam) store_all<LAST>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
+    if (st_psi) store_all<LAST, RT == ROUTE_HIGH>(0, cx.psi + pg.st_buf * cx.N, tile_base, toff, S, cx.off32);
+    if (st_lam) store_all<LAST, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
   }
 
   // ================================================================ run-time-flag path
@@ -899,10 +912,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load_all<KL>(0, cx.psi + pg.ld_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+      if (pg.flags & F_LOAD_PSI) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
-        load_all<KL>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -938,8 +951,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && (pg.flags & F_STORE_LAM) && cx.lam;
     if ((st_psi || st_lam) && at_p) xchg_rt<P, KL>(lds_x);
-    if (st_psi) store_all<KL>(0, cx.psi + pg.st_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
-    if (st_lam) store_all<KL>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+    if (st_psi) store_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.st_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+    if (st_lam) store_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
   }
   __device__ __forceinline__ void run_any(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                           const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid,

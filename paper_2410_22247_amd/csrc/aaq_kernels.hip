@@ -13,11 +13,15 @@ struct ScaleStage {
   uint64_t gact[kMaxSets];
   uint32_t act[kMaxSets];
   double sb[kMaxP], cb[kMaxP];
+  // scale and flips each stored psi buffer was written with (indexed by buffer: kept in
+  // LDS, so the walk makes no private-memory round trips)
+  double mpr[kMaxCkpt], mpi[kMaxCkpt];
+  uint64_t mF[kMaxCkpt];
 };
 
 // Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
 // the scale corrections (see SwScale).  out[nsweep].s_pre is 1/|sigma|^2 at the end.
-__device__ void build_scales(const ScaleStage& S, int nsweep, SwScale* out) {
+__device__ void build_scales(ScaleStage& S, int nsweep, SwScale* out) {
   const SweepProg* progs = S.progs;
   double sr = 1.0, si = 0.0;  // sigma
   auto position = [&](uint8_t ops, double* rho, double& sx) {
@@ -66,8 +70,10 @@ __device__ void build_scales(const ScaleStage& S, int nsweep, SwScale* out) {
   // scales of the buffers in memory: psi and lambda differ after a sweep that stores
   // only lambda (the last forward sweep leaves psi untouched in memory); with
   // checkpoints every psi buffer keeps the scale and flips it was stored with
-  double mpr[kMaxCkpt], mpi[kMaxCkpt], mlr = 1.0, mli = 0.0;
-  uint64_t mF[kMaxCkpt];
+  double* mpr = S.mpr;
+  double* mpi = S.mpi;
+  uint64_t* mF = S.mF;
+  double mlr = 1.0, mli = 0.0;
   for (int b = 0; b < kMaxCkpt; ++b) {
     mpr[b] = 1.0;
     mpi[b] = 0.0;
