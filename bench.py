@@ -290,6 +290,8 @@ def main():
                 diff = max(diff, float(np.max(np.abs(got[k] - want) / np.maximum(np.abs(want), 1e-300))))
             out["host_api"] = {"evals_s": round(rate(lambda: est.energy_grad(g0, b0)), 2),
                                "max_rel_diff_vs_resident": diff}
+            # the resident evaluations without the per-launch timing events of the timed region
+            out["resident_untimed_evals_s"] = round(rate(lambda: res.execute(dparams[0], dout[0])), 2)
         if half:
             # the same evaluation with every amplitude stored and swept (host API both ways)
             flat = lambda r: np.concatenate([[r[0]], r[1], r[2]])

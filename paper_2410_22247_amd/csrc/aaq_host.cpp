@@ -70,8 +70,11 @@ struct TimedLaunch {
     if (!g_timing) return;
     pe.cls = cls;
     pe.bytes = bytes;
-    if (hipEventCreate(&pe.a) != hipSuccess) return;
-    if (hipEventCreate(&pe.b) != hipSuccess) {
+    // timing-only events: no system-scope fence (no cache writeback and invalidation
+    // between the measured kernels); aaq_timing_read reads them after the caller has
+    // synchronised with the work
+    if (hipEventCreateWithFlags(&pe.a, hipEventDisableSystemFence) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&pe.b, hipEventDisableSystemFence) != hipSuccess) {
       (void)hipEventDestroy(pe.a);
       return;
     }
