@@ -6,8 +6,8 @@ complex64 amplitudes, one MI355X.
 One step = one aaq_energy_grad call (the whole hot path: phase tables, every forward
 and backward statevector sweep, the FP64 reductions) at one of the 32 seeded
 parameter points.  Prints ONE JSON line.  Alongside the headline number it reports
-the roofline of the dominant kernel (HIP events around every launch, on the stream
-the kernel runs on), the FP64 CPU oracle timed on the host cores, and H_red vs H_C
+the roofline of the dominant kernel (HIP start and end events carried in the dispatch
+of every launch, on the stream the kernel runs on), the FP64 CPU oracle timed on the host cores, and H_red vs H_C
 in the three aggregation modes.
 """
 import argparse

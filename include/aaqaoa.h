@@ -366,12 +366,14 @@ aaq_status aaq_lightcone_execute(aaq_lightcone *lc, const double *d_params, doub
 void aaq_lightcone_destroy(aaq_lightcone *lc);
 
 /* ---------------------------------------------------------------- diagnostics */
-/* Per-kernel timing.  While enabled, every kernel launch of the library is bracketed
- * by two HIP events recorded on the stream it is launched on; aaq_timing_read waits
- * for the recorded events and returns, per kernel class ("sweep_1state",
- * "sweep_2state", "tables", "reduce", "zz_pass", "units"), the launch count, the summed
- * event time and the algorithmic bytes of the state buffers the launches read and
- * write.  For measurement only: it adds two event records per launch. */
+/* Per-kernel timing.  While enabled, every kernel launch of the library (outside a
+ * stream capture) carries two HIP events in its dispatch on the stream it is launched
+ * on (the kernel's start and end; a launch of two kernels is timed from the first's
+ * start to the second's end); aaq_timing_read waits for the events and returns, per
+ * kernel class ("sweep_1state", "sweep_2state", "tables", "reduce", "zz_pass",
+ * "units"), the launch count, the summed event time and the algorithmic bytes of the
+ * state buffers the launches read and write.  For measurement only: it creates two
+ * events per launch. */
 typedef struct {
   char name[32];
   long long launches;

@@ -1287,7 +1287,7 @@ static void sweep_launch_kind(const SweepArgs<R>& A, dim3 grid, dim3 blk, size_t
   constexpr int NS = (KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1;
   constexpr bool EN = ((sk_pre(KIND) | sk_mid(KIND)) & OP_ENERGY) != 0;
   constexpr bool PT = ((sk_pre(KIND) | sk_mid(KIND)) & OP_PERTERM) != 0;
-  hipLaunchKernelGGL((k_sweep<R, NS, PT, EN, RT, LT, KIND>), grid, blk, dyn, st, A);
+  launch((k_sweep<R, NS, PT, EN, RT, LT, KIND>), grid, blk, dyn, st, A);
 }
 
 template <class R, int RT, int LT>
@@ -1308,15 +1308,15 @@ static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t 
     default: break;
   }
   if (pt)
-    hipLaunchKernelGGL((k_sweep<R, 1, true, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
+    launch((k_sweep<R, 1, true, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (L.two_states && en)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
+    launch((k_sweep<R, 2, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (L.two_states)
-    hipLaunchKernelGGL((k_sweep<R, 2, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
+    launch((k_sweep<R, 2, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else if (en)
-    hipLaunchKernelGGL((k_sweep<R, 1, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
+    launch((k_sweep<R, 1, false, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
   else
-    hipLaunchKernelGGL((k_sweep<R, 1, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
+    launch((k_sweep<R, 1, false, false, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);
 }
 
 template <class R, int LT> hipError_t sweep_launch_impl(const LaunchSweep& L, hipStream_t st) {
@@ -1363,18 +1363,18 @@ template <class R, int LT> hipError_t units_launch_impl(const LaunchUnits& L, bo
   auto A = unit_args<R>(L);
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)L.tabmax;
   if (grad)
-    hipLaunchKernelGGL((k_units<R, 2, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
+    launch((k_units<R, 2, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
   else
-    hipLaunchKernelGGL((k_units<R, 1, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
+    launch((k_units<R, 1, LT>), dim3(blocks), dim3(Geo<R, LT>::NT), dyn, st, A);
   return hipGetLastError();
 }
 
 template <class R, int NS, bool EN, int LT>
 static void bsweep_launch_t(const BatchArgs<R>& A, int route, dim3 grid, size_t dyn, hipStream_t st) {
   if (route == ROUTE_HIGH)
-    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_HIGH, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
+    launch((k_bsweep<R, NS, EN, ROUTE_HIGH, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
   else
-    hipLaunchKernelGGL((k_bsweep<R, NS, EN, ROUTE_FULL, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
+    launch((k_bsweep<R, NS, EN, ROUTE_FULL, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
 }
 
 template <class R, int LT> hipError_t bsweep_launch_impl(const LaunchBatch& L, hipStream_t st) {
@@ -1392,9 +1392,9 @@ template <class R, int LT>
 hipError_t cuts_launch_impl(const GraphDev* g, const int4* terms, int T, int use_terms, const SetSpec& S, int arr,
                             int32_t* out, hipStream_t st) {
   if (arr == 0)
-    hipLaunchKernelGGL((k_cuts<R, 0, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
+    launch((k_cuts<R, 0, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
   else
-    hipLaunchKernelGGL((k_cuts<R, 1, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
+    launch((k_cuts<R, 1, LT>), dim3(S.ntiles), dim3(Geo<R, LT>::NT), 0, st, g, terms, T, use_terms, S, out);
   return hipGetLastError();
 }
 

@@ -43,6 +43,11 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // the error message of the library's other translation units (aaq_orbits.cpp)
 aaq_status aaq::set_error(aaq_status s, const std::string& msg) { return fail(s, msg); }
 
+aaq::LaunchEvents& aaq::launch_events() {
+  static thread_local LaunchEvents e;
+  return e;
+}
+
 namespace {
 
 // ------------------------------------------------------------------ optional per-kernel timing
@@ -58,6 +63,18 @@ struct Pending {
 std::mutex g_tmu;
 bool g_timing = false;
 std::vector<Pending> g_pending;
+// timing-only events (no system-scope fence), created when timing is switched on and
+// reused, so a timed region creates none; guarded by g_tmu
+std::vector<hipEvent_t> g_evpool;
+constexpr size_t kEventPool = 2048;
+bool take_event(hipEvent_t* e) {
+  if (!g_evpool.empty()) {
+    *e = g_evpool.back();
+    g_evpool.pop_back();
+    return true;
+  }
+  return hipEventCreateWithFlags(e, hipEventDisableSystemFence) == hipSuccess;
+}
 double g_tot_ms[KC_N], g_tot_bytes[KC_N];
 long long g_launches[KC_N];
 
@@ -68,25 +85,47 @@ struct TimedLaunch {
   TimedLaunch(int cls, double bytes, hipStream_t s) : on(false), st(s) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
+    // kernels recorded into a graph carry no dispatch events: no timing while capturing
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     pe.cls = cls;
     pe.bytes = bytes;
     // timing-only events: no system-scope fence (no cache writeback and invalidation
     // between the measured kernels); aaq_timing_read reads them after the caller has
     // synchronised with the work
-    if (hipEventCreateWithFlags(&pe.a, hipEventDisableSystemFence) != hipSuccess) return;
-    if (hipEventCreateWithFlags(&pe.b, hipEventDisableSystemFence) != hipSuccess) {
-      (void)hipEventDestroy(pe.a);
+    if (!take_event(&pe.a)) return;
+    if (!take_event(&pe.b)) {
+      g_evpool.push_back(pe.a);
       return;
     }
-    on = hipEventRecord(pe.a, st) == hipSuccess;
+    // the launches between here and done() take the events into their dispatches
+    aaq::LaunchEvents& le = aaq::launch_events();
+    le.start = pe.a;
+    le.stop = pe.b;
+    le.used = false;
+    on = true;
   }
   void done() {
     if (!on) return;
-    (void)hipEventRecord(pe.b, st);
+    aaq::LaunchEvents& le = aaq::launch_events();
+    if (!le.used) {  // nothing was launched: an empty interval
+      (void)hipEventRecord(pe.a, st);
+      (void)hipEventRecord(pe.b, st);
+    }
+    le = aaq::LaunchEvents{};
     std::lock_guard<std::mutex> lk(g_tmu);
     g_pending.push_back(pe);
     on = false;
   }
+  ~TimedLaunch() {  // an error return before done(): drop the events
+    if (!on) return;
+    aaq::launch_events() = aaq::LaunchEvents{};
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  TimedLaunch(const TimedLaunch&) = delete;
+  TimedLaunch& operator=(const TimedLaunch&) = delete;
 };
 
 // ------------------------------------------------------------------ launch tuning
@@ -1958,6 +1997,13 @@ done:
 aaq_status aaq_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
   g_timing = on != 0;
+  if (g_timing) {
+    while (g_evpool.size() < kEventPool) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) break;
+      g_evpool.push_back(e);
+    }
+  }
   return AAQ_OK;
 }
 
@@ -1971,10 +2017,18 @@ aaq_status aaq_timing_read(aaq_kernel_timing* out, int max, int* count, int rese
     g_tot_ms[pe.cls] += ms;
     g_tot_bytes[pe.cls] += pe.bytes;
     g_launches[pe.cls] += 1;
-    (void)hipEventDestroy(pe.a);
-    (void)hipEventDestroy(pe.b);
+    for (hipEvent_t e : {pe.a, pe.b}) {
+      if (g_timing && g_evpool.size() < kEventPool)
+        g_evpool.push_back(e);
+      else
+        (void)hipEventDestroy(e);
+    }
   }
   g_pending.clear();
+  if (!g_timing) {
+    for (hipEvent_t e : g_evpool) (void)hipEventDestroy(e);
+    g_evpool.clear();
+  }
   int k = 0;
   for (int c = 0; c < KC_N; ++c) {
     if (!g_launches[c]) continue;

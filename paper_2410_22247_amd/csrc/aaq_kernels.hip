@@ -444,10 +444,10 @@ hipError_t launch_tables(const double* gamma, const double* beta, int p, int cma
   const int tot = p * (cmax + 1);
   const int blocks = (tot + 255) / 256;
   if (dbl)
-    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
+    launch(k_tables<double>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
                        reinterpret_cast<double2*>(tab), progs, nsweep, sets, nsets, scales);
   else
-    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
+    launch(k_tables<float>, dim3(blocks), dim3(256), 0, st, gamma, beta, p, cmax,
                        reinterpret_cast<float2*>(tab), progs, nsweep, sets, nsets, scales);
   return hipGetLastError();
 }
@@ -458,66 +458,66 @@ hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* c
   const uint64_t nb = (uint64_t)1 << (n - lb);
   const dim3 gs((unsigned)((shots + 3) / 4));
   if (dbl) {
-    hipLaunchKernelGGL(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum);
-    hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
-    hipLaunchKernelGGL(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, flips, uniform, shots,
+    launch(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum);
+    launch(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
+    launch(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, flips, uniform, shots,
                        g, cost_terms, samples, cuts);
   } else {
-    hipLaunchKernelGGL(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum);
-    hipLaunchKernelGGL(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
-    hipLaunchKernelGGL(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, flips, uniform, shots, g,
+    launch(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum);
+    launch(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
+    launch(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, flips, uniform, shots, g,
                        cost_terms, samples, cuts);
   }
-  hipLaunchKernelGGL(k_samp_stats, dim3(1), dim3(256), 0, st, cuts, shots, stats);
+  launch(k_samp_stats, dim3(1), dim3(256), 0, st, cuts, shots, stats);
   return hipGetLastError();
 }
 
 hipError_t launch_lc_bcast(const double* params, int np, double* rows, int count, hipStream_t st) {
   const int tot = count * np;
-  hipLaunchKernelGGL(k_lc_bcast, dim3((tot + 255) / 256), dim3(256), 0, st, params, np, rows, count);
+  launch(k_lc_bcast, dim3((tot + 255) / 256), dim3(256), 0, st, params, np, rows, count);
   return hipGetLastError();
 }
 
 hipError_t launch_lc_sum(const double* rows, int count, int stride, double* out, hipStream_t st) {
   if (stride > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lc_sum, dim3(1), dim3(256), 0, st, rows, count, stride, out);
+  launch(k_lc_sum, dim3(1), dim3(256), 0, st, rows, count, stride, out);
   return hipGetLastError();
 }
 
 hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t st) {
   if (dbl)
-    hipLaunchKernelGGL(k_plan_tables<double>, dim3(L.count), dim3(256), 0, st, unit_args<double>(L), p, 2 * p);
+    launch(k_plan_tables<double>, dim3(L.count), dim3(256), 0, st, unit_args<double>(L), p, 2 * p);
   else
-    hipLaunchKernelGGL(k_plan_tables<float>, dim3(L.count), dim3(256), 0, st, unit_args<float>(L), p, 2 * p);
+    launch(k_plan_tables<float>, dim3(L.count), dim3(256), 0, st, unit_args<float>(L), p, 2 * p);
   return hipGetLastError();
 }
 
 hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st) {
   if (dbl) {
     BatchArgs<double> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
-    hipLaunchKernelGGL(k_bsweep_out<double>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
+    launch(k_bsweep_out<double>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
   } else {
     BatchArgs<float> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
-    hipLaunchKernelGGL(k_bsweep_out<float>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
+    launch(k_bsweep_out<float>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* partial, const void* src, const int32_t* src_begin, double* stage, double* out,
                          int nout, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce, dim3(nout, kRedChunks), dim3(256), 0, st, partial, reinterpret_cast<const RedSrc*>(src),
+  launch(k_reduce, dim3(nout, kRedChunks), dim3(256), 0, st, partial, reinterpret_cast<const RedSrc*>(src),
                      src_begin, stage);
-  hipLaunchKernelGGL(k_reduce_final, dim3(nout), dim3(64), 0, st, stage, out);
+  launch(k_reduce_final, dim3(nout), dim3(64), 0, st, stage, out);
   return hipGetLastError();
 }
 
 hipError_t launch_zz_pass(const void* psi, uint64_t N, int i, int j, const double* scale, const uint64_t* flips,
                           double* partial, int blocks, bool dbl, hipStream_t st) {
   if (dbl)
-    hipLaunchKernelGGL(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j,
+    launch(k_zz_pass<double>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const double2*>(psi), N, i, j,
                        scale, flips, partial);
   else
-    hipLaunchKernelGGL(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j,
+    launch(k_zz_pass<float>, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const float2*>(psi), N, i, j,
                        scale, flips, partial);
   return hipGetLastError();
 }

@@ -1,5 +1,6 @@
 // Kernel launch interface between the host planner and the HIP kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -11,6 +12,28 @@ namespace aaq {
 
 // sets the message aaq_last_error_message returns; returns s
 aaq_status set_error(aaq_status s, const std::string& msg);
+
+// Timing events for the next launches of this host thread (set by the host's per-kernel
+// timing, null otherwise).  The first launch takes `start` into its dispatch and every
+// launch takes `stop`, so a group of launches is timed from the first kernel's start to
+// the last kernel's end by the dispatches themselves, without event packets between them.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  bool used = false;
+};
+LaunchEvents& launch_events();
+
+// every kernel of the library is launched through here
+template <class F, class... Args>
+inline void launch(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st, Args... args) {
+  LaunchEvents& e = launch_events();
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, st, e.start, e.stop, 0u, args...);
+  if (e.stop) {
+    e.start = nullptr;
+    e.used = true;
+  }
+}
 
 struct LaunchSweep {
   void* psi;
