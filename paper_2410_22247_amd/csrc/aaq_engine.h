@@ -61,6 +61,9 @@ template <int B0, int RB> __device__ __forceinline__ uint32_t tidx(uint32_t t, u
 // disjoint bit sets, P(a | b) = P(a) + P(b), so the slot of (thread part | register
 // part) is a per-thread base plus a compile-time offset.
 __host__ __device__ constexpr uint32_t lds_slot(uint32_t j) { return j + (j >> 4); }
+// the tile index without its bit 3 (the half-tile exchange below); additive over
+// disjoint bit sets that do not hold bit 3, like lds_slot
+__host__ __device__ constexpr uint32_t drop_bit3(uint32_t j) { return (j & 7u) | ((j >> 4) << 3); }
 // thread part of the tile index in an arrangement whose register bits start at B0
 template <int B0, int RB> __device__ __forceinline__ uint32_t tpart(uint32_t t) {
   return (t & ((1u << B0) - 1u)) | ((t >> B0) << (B0 + RB));
@@ -177,21 +180,49 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   static_assert(walks_cover(ROUTE_FULL) && walks_cover(ROUTE_HIGH), "every route bit is mixed exactly once");
 
   // -------------------------------------------------------------- LDS transpose
-  template <int KF, int KT> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
+  // HX: the half-tile exchange.  When both arrangements keep tile bit 3 as a thread bit
+  // (register bits at 4 and up), it is thread bit 3 on both sides, so the half of the
+  // tile with bit 3 = h moves only among the threads with thread bit 3 = h: the two
+  // halves take turns in a buffer of half a tile (slots of the index without bit 3).
+  // Half the LDS per workgroup lets more workgroups share a compute unit.
+  template <int KF, int KT, bool HX = false> __device__ __forceinline__ void xchg1(V (&x)[NR], V* lds) {
     constexpr int BF = G::b0(KF), BT = G::b0(KT);
     const uint32_t t = threadIdx.x;
-    V* wb = lds + lds_slot(tpart<BF, RB>(t));
+    if constexpr (HX) {
+      static_assert(BF > 3 && BT > 3, "tile bit 3 must be a thread bit in both arrangements");
+      const uint32_t h = (t >> 3) & 1u;
+      V* wb = lds + lds_slot(drop_bit3(tpart<BF, RB>(t)));
+      const V* rb = lds + lds_slot(drop_bit3(tpart<BT, RB>(t)));
 #pragma unroll
-    for (int r = 0; r < NR; ++r) wb[lds_slot((uint32_t)r << BF)] = x[r];
-    __syncthreads();
-    const V* rb = lds + lds_slot(tpart<BT, RB>(t));
+      for (uint32_t ph = 0; ph < 2; ++ph) {
+        if (h == ph) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
-    __syncthreads();
+          for (int r = 0; r < NR; ++r) wb[lds_slot(drop_bit3((uint32_t)r << BF))] = x[r];
+        }
+        __syncthreads();
+        if (h == ph) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot(drop_bit3((uint32_t)r << BT))];
+        }
+        __syncthreads();
+      }
+    } else {
+      V* wb = lds + lds_slot(tpart<BF, RB>(t));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) wb[lds_slot((uint32_t)r << BF)] = x[r];
+      __syncthreads();
+      const V* rb = lds + lds_slot(tpart<BT, RB>(t));
+#pragma unroll
+      for (int r = 0; r < NR; ++r) x[r] = rb[lds_slot((uint32_t)r << BT)];
+      __syncthreads();
+    }
   }
+  // one-state sweeps of the high-qubit route exchange half tiles (every arrangement of
+  // that route has its register bits at 4 and up)
+  static constexpr bool half_xchg(int RT) { return NS == 1 && RT == ROUTE_HIGH; }
   // LAM: lambda is live (compile-time, so no per-register branch)
-  template <int KF, int KT, bool LAM> __device__ __forceinline__ void xchg(V* lds) {
-    xchg1<KF, KT>(a[0], lds);
+  template <int KF, int KT, bool LAM, bool HX = false> __device__ __forceinline__ void xchg(V* lds) {
+    xchg1<KF, KT, HX>(a[0], lds);
     if constexpr (NS == 2 && LAM) xchg1<KF, KT>(a[NS - 1], lds);
   }
 
@@ -676,7 +707,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   template <int RT, int K, int PREV, bool LAM>
   __device__ __forceinline__ void fwd_steps(uint32_t act, R k, R w, R& wcur, R& gs, V* lds) {
     if constexpr (K <= P) {
-      xchg<PREV, K, LAM>(lds);
+      xchg<PREV, K, LAM, half_xchg(RT)>(lds);
       mix_at<K, fwd_mask(RT, K), LAM>(act, k, w, wcur, gs);
       fwd_steps<RT, K + 1, K, LAM>(act, k, w, wcur, gs, lds);
     }
@@ -684,7 +715,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   template <int RT, int K, bool LAM>
   __device__ __forceinline__ void bwd_steps(uint32_t act, R k, R w, R& wcur, R& gs, V* lds) {
     if constexpr (K >= first_arr(RT)) {
-      xchg<K + 1, K, LAM>(lds);
+      xchg<K + 1, K, LAM, half_xchg(RT)>(lds);
       mix_at<K, bwd_mask(RT, K), LAM>(act, k, w, wcur, gs);
       bwd_steps<RT, K - 1, LAM>(act, k, w, wcur, gs, lds);
     }
@@ -699,7 +730,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     R wcur = R(1);
     mix_at<P, bwd_mask(RT, P), LAM>(act, k, w, wcur, gs);
     bwd_steps<RT, P - 1, LAM>(act, k, w, wcur, gs, lds);
-    xchg<(FIRST < P ? FIRST : P), LAST, LAM>(lds);
+    xchg<(FIRST < P ? FIRST : P), LAST, LAM, half_xchg(RT)>(lds);
     mix_at<LAST, bwd_mask(RT, LAST), LAM>(act, k, w, wcur, gs);
   }
 
@@ -745,7 +776,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       at_p = true;
     }
     if constexpr ((sk_mid(KIND) != 0 || (KIND & SK_MIXB) != 0) && (KIND & SK_MIXA) == 0) {
-      xchg<LAST, P, LAM0>(lds_x);
+      xchg<LAST, P, LAM0, half_xchg(RT)>(lds_x);
       at_p = true;
     }
     ops_at<P, LAM0, sk_mid(KIND)>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, sc.F_mid, cx, ltab_mid,
@@ -759,7 +790,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && LAM1 && (pg.flags & F_STORE_LAM) && cx.lam;
-    if ((st_psi || st_lam) && at_p) xchg<P, LAST, LAM1>(lds_x);
+    if ((st_psi || st_lam) && at_p) xchg<P, LAST, LAM1, half_xchg(RT)>(lds_x);
     uint64_t toff = tile_base + thread_off<LAST>(S);
     // opaque to the compiler: the store addresses are formed here, not kept in
     // registers from the loads (that would hold 2 VGPRs per register and state)
@@ -1036,7 +1067,14 @@ template <class R> struct SweepArgs {
 // Specialized single-instance sweeps: at most 128 VGPRs per lane, i.e. four waves per
 // SIMD, the occupancy the tile LDS allows anyway; the generic sweeps are left to the
 // compiler.
-constexpr int sweep_waves_per_eu(uint32_t kind) { return (kind & SK_GENERIC) ? 1 : 4; }
+// the specialised one-state sweeps of the high-qubit route exchange half tiles: half the
+// LDS, so six workgroups fit a compute unit (their registers allow six waves per SIMD)
+constexpr bool sweep_half_xchg(int ns, int rt, uint32_t kind) {
+  return ns == 1 && rt == ROUTE_HIGH && !(kind & SK_GENERIC);
+}
+constexpr int sweep_waves_per_eu(int ns, int rt, uint32_t kind) {
+  return (kind & SK_GENERIC) ? 1 : sweep_half_xchg(ns, rt, kind) ? 6 : 4;
+}
 // partial-sum slots a sweep shape can fill (SLOT_* bits; the generic sweeps: all six)
 constexpr uint32_t sweep_slots(uint32_t kind) {
   if (kind & SK_GENERIC) return 0x3Fu;
@@ -1049,15 +1087,15 @@ constexpr uint32_t sweep_slots(uint32_t kind) {
   if (kind & SK_MIXB) m |= 1u << SLOT_BB;
   return m;
 }
-#define AAQ_SWEEP_BOUNDS(KIND) \
-  __launch_bounds__(1 << (LT - kRegBits)) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu(KIND))))
+#define AAQ_SWEEP_BOUNDS(NS, RT, KIND) \
+  __launch_bounds__(1 << (LT - kRegBits)) __attribute__((amdgpu_waves_per_eu(sweep_waves_per_eu(NS, RT, KIND))))
 
 // One workgroup per tile; partial sums per tile: partial[slot][tile].
 template <class R, int NS, bool PT, bool EN, int RT, int LT, uint32_t KIND>
-__global__ AAQ_SWEEP_BOUNDS(KIND) void k_sweep(SweepArgs<R> A) {
+__global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   using G = Geo<R, LT>;
   using V = typename G::V;
-  __shared__ V lds_x[lds_slot(G::TILE)];
+  __shared__ V lds_x[lds_slot(sweep_half_xchg(NS, RT, KIND) ? G::TILE / 2 : G::TILE)];
   __shared__ double red[(G::NT / 64) * 6];
   __shared__ double zz[PT ? kMaxT : 1];
   extern __shared__ unsigned char dyn_lds[];  // two phase tables of cmax+1 entries
