@@ -333,6 +333,26 @@ aaq_status aaq_sample(const aaq_problem *prob, int p, const double *gamma, const
 aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t *edges, const int32_t *edge_weight, int32_t *orbit_of,
                            int32_t *num_orbits, int32_t *orbit_rep, int32_t *orbit_size);
 
+/* The structural descriptor of combined-RCC coverage (the paper's subsection of that name,
+ * Eq. for eta_p):  eta_p = 1 - |U_{e in R} RCC_p(e)| / |E|, the fraction of edges outside
+ * the union of the representatives' reverse causal cones.  RCC_p(e) of e = (i, j) is the
+ * set of cost gates that do not commute through to Z_i Z_j in p layers: the edges with an
+ * endpoint within graph distance p - 1 of {i, j}; the cone's qubits are the vertices within
+ * distance p.
+ *   edges        [2 * num_edges] (u, v) pairs, validated as in aaq_edge_orbits; 1 <= |E| <= 65536
+ *   orbit_of     [num_edges] orbit id of each edge, 0 .. num_orbits - 1 (aaq_edge_orbits output)
+ *   rep          [num_orbits] representative edge of each orbit (an edge of that orbit), or
+ *                NULL: eta_out is then the exact mean over representatives drawn uniformly
+ *                and independently in every orbit (the tables' random selection)
+ *   p            >= 1
+ *   eta_out      out: eta_p
+ *   vertex_cover_out  [n] or NULL (only with rep): 1 for every qubit of the union of the
+ *                cones, else 0
+ * Host only, O(|E| (n + |E|)); errors AAQ_ERR_INVALID_ARG / AAQ_ERR_GRAPH / AAQ_ERR_ORBITS,
+ * outputs untouched on error. */
+aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t *edges, const int32_t *orbit_of, int num_orbits,
+                       const int32_t *rep, int p, double *eta_out, uint8_t *vertex_cover_out);
+
 /* ---------------------------------------------------------------- light cones
  * Light-cone evaluation, the locality reduction the paper names as compounding with the
  * orbit reduction (its discussion of reverse causal cones): the depth-p expectation of a

@@ -12,7 +12,7 @@ from .api import (  # noqa: F401
     aaq_version, aaq_workspace_size, aaq_timing_enable, aaq_timing_read, aaq_set_tile_bits, aaq_get_tile_bits,
     aaq_autotune, aaq_plan_autotune, aaq_checkpoint_bytes, aaq_energy_grad_checkpointed, Estimator, Plan,
     aaq_lightcone_info, aaq_lightcone_workspace_size, aaq_lightcone_create, aaq_lightcone_execute,
-    aaq_lightcone_destroy, LightCone, aaq_edge_orbits, aaq_sample_workspace_size, aaq_sample, Sampler,
+    aaq_lightcone_destroy, LightCone, aaq_edge_orbits, aaq_rcc_eta, aaq_sample_workspace_size, aaq_sample, Sampler,
     aaq_resident_workspace_size, aaq_resident_create, aaq_resident_execute, aaq_resident_destroy, Resident,
     aaq_set_half_state, aaq_get_half_state,
 )

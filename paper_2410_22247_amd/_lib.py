@@ -50,7 +50,7 @@ EXPORTS = (
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
     "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample", "aaq_resident_workspace_size",
     "aaq_resident_create", "aaq_resident_execute", "aaq_resident_destroy", "aaq_set_half_state",
-    "aaq_get_half_state",
+    "aaq_get_half_state", "aaq_rcc_eta",
 )
 
 
@@ -109,6 +109,8 @@ def lib():
         "aaq_edge_orbits": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+        "aaq_rcc_eta": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i,
+                            ctypes.POINTER(ctypes.c_int32), i, dp, ctypes.POINTER(ctypes.c_uint8)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

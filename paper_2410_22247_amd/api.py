@@ -339,6 +339,26 @@ def aaq_edge_orbits(n: int, edges, edge_weight=None):
     return of[:m].copy(), rep[:k.value].copy(), size[:k.value].copy()
 
 
+def aaq_rcc_eta(n: int, edges, orbit_of, p: int, rep=None, vertex_cover: bool = False):
+    """eta_p, the fraction of edges outside the union of the representatives' reverse causal
+    cones; with ``rep=None`` the exact mean over uniformly drawn representatives.  With
+    ``vertex_cover`` (needs ``rep``) returns (eta, uint8[n] qubits of the union)."""
+    e = _i32(edges)
+    m = e.size // 2
+    of = _i32(orbit_of)
+    if of.size != m:
+        raise ValueError("one orbit id per edge")
+    k = int(of.max()) + 1 if m else 0
+    r = None if rep is None else _i32(rep)
+    if r is not None and r.size != k:
+        raise ValueError("one representative per orbit")
+    eta = ctypes.c_double()
+    cov = np.zeros(max(int(n), 1), dtype=np.uint8) if vertex_cover else None
+    _check(_lib.lib().aaq_rcc_eta(int(n), m, _ptr_i32(e), _ptr_i32(of), k, _ptr_i32(r), int(p), ctypes.byref(eta),
+                                  cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if cov is not None else None))
+    return (eta.value, cov[:n].copy()) if vertex_cover else eta.value
+
+
 def aaq_resident_workspace_size(prob: Problem, p: int, obs: int, with_grad: bool, checkpoint: bool = False,
                                 prec: int = AAQ_PREC_C64):
     """(workspace bytes, state bytes) of a resident evaluator."""

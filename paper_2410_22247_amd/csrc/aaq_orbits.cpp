@@ -230,3 +230,97 @@ extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges
   }
   return AAQ_OK;
 }
+
+// ---------------------------------------------------------------- combined-RCC coverage
+// eta_p = 1 - |U_{e in R} RCC_p(e)| / |E| (the structural descriptor of the paper's
+// combined-RCC coverage subsection).  RCC_p(e), e = (i, j), holds the cost gates that do
+// not commute through to Z_i Z_j in p layers: the edges with an endpoint within graph
+// distance p - 1 of {i, j} (layer p: the gates on i or j; each earlier layer one hop
+// further); its qubits are the vertices within distance p.
+extern "C" aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t* edges, const int32_t* orbit_of,
+                                  int num_orbits, const int32_t* rep, int p, double* eta_out,
+                                  uint8_t* vertex_cover_out) {
+  if (n < 1 || n > 4096) return aaq::set_error(AAQ_ERR_INVALID_ARG, "n must be in [1, 4096]");
+  if (num_edges < 1 || num_edges > (1 << 16)) return aaq::set_error(AAQ_ERR_GRAPH, "num_edges must be in [1, 65536]");
+  if (!edges || !orbit_of || !eta_out) return aaq::set_error(AAQ_ERR_INVALID_ARG, "edges / orbit_of / eta_out is NULL");
+  if (p < 1) return aaq::set_error(AAQ_ERR_INVALID_ARG, "p must be >= 1");
+  if (vertex_cover_out && !rep)
+    return aaq::set_error(AAQ_ERR_INVALID_ARG, "the vertex cover is defined for given representatives");
+  if (num_orbits < 1 || num_orbits > num_edges) return aaq::set_error(AAQ_ERR_ORBITS, "num_orbits must be in [1, |E|]");
+  std::vector<std::vector<int>> adj(n);
+  std::set<std::pair<int, int>> seen;
+  for (int e = 0; e < num_edges; ++e) {
+    const int u = edges[2 * e], v = edges[2 * e + 1];
+    if (u < 0 || u >= n || v < 0 || v >= n)
+      return aaq::set_error(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " has a vertex out of range");
+    if (u == v) return aaq::set_error(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a self-loop");
+    if (!seen.emplace(std::min(u, v), std::max(u, v)).second)
+      return aaq::set_error(AAQ_ERR_GRAPH, "edge " + std::to_string(e) + " is a duplicate");
+    adj[u].push_back(v);
+    adj[v].push_back(u);
+  }
+  std::vector<std::vector<int>> members(num_orbits);
+  for (int e = 0; e < num_edges; ++e) {
+    if (orbit_of[e] < 0 || orbit_of[e] >= num_orbits)
+      return aaq::set_error(AAQ_ERR_ORBITS, "edge " + std::to_string(e) + " has an orbit id out of range");
+    members[orbit_of[e]].push_back(e);
+  }
+  for (int m = 0; m < num_orbits; ++m) {
+    if (members[m].empty()) return aaq::set_error(AAQ_ERR_ORBITS, "orbit " + std::to_string(m) + " is empty");
+    if (rep && (rep[m] < 0 || rep[m] >= num_edges || orbit_of[rep[m]] != m))
+      return aaq::set_error(AAQ_ERR_ORBITS, "representative of orbit " + std::to_string(m) + " is not in it");
+  }
+  // distances from {i, j} of edge e by breadth-first search, up to p
+  const int far = p + 1;
+  std::vector<int> dist(n), queue(n);
+  auto cone = [&](int e) {
+    std::fill(dist.begin(), dist.end(), far);
+    int head = 0, tail = 0;
+    for (int s : {edges[2 * e], edges[2 * e + 1]}) {
+      dist[s] = 0;
+      queue[tail++] = s;
+    }
+    while (head < tail) {
+      const int u = queue[head++];
+      if (dist[u] + 1 > p) continue;
+      for (int w : adj[u])
+        if (dist[w] == far) {
+          dist[w] = dist[u] + 1;
+          queue[tail++] = w;
+        }
+    }
+  };
+  auto in_cone = [&](int f) { return std::min(dist[edges[2 * f]], dist[edges[2 * f + 1]]) <= p - 1; };
+  double outside = 0.0;  // edges outside the union (expected count without rep)
+  if (rep) {
+    std::vector<char> covered(num_edges, 0), vcov(n, 0);
+    for (int m = 0; m < num_orbits; ++m) {
+      cone(rep[m]);
+      for (int f = 0; f < num_edges; ++f)
+        if (in_cone(f)) covered[f] = 1;
+      for (int v = 0; v < n; ++v)
+        if (dist[v] <= p) vcov[v] = 1;
+    }
+    for (int f = 0; f < num_edges; ++f) outside += covered[f] ? 0.0 : 1.0;
+    if (vertex_cover_out)
+      for (int v = 0; v < n; ++v) vertex_cover_out[v] = (uint8_t)vcov[v];
+  } else {
+    // representatives drawn uniformly and independently per orbit: edge f lies outside
+    // the union with probability prod_m (1 - c_mf / |m|), c_mf = the edges of orbit m
+    // whose cone holds f
+    std::vector<double> miss(num_edges, 1.0);
+    std::vector<int> cnt(num_edges);
+    for (int m = 0; m < num_orbits; ++m) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int e : members[m]) {
+        cone(e);
+        for (int f = 0; f < num_edges; ++f) cnt[f] += in_cone(f) ? 1 : 0;
+      }
+      const double sz = (double)members[m].size();
+      for (int f = 0; f < num_edges; ++f) miss[f] *= 1.0 - cnt[f] / sz;
+    }
+    for (int f = 0; f < num_edges; ++f) outside += miss[f];
+  }
+  *eta_out = outside / num_edges;
+  return AAQ_OK;
+}
