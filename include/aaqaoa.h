@@ -346,12 +346,17 @@ aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t *edges, const int
  *                and independently in every orbit (the tables' random selection)
  *   p            >= 1
  *   eta_out      out: eta_p
+ *   qubit_elim_out  out or NULL: the qubit-elimination fraction shown beside eta_1 in the
+ *                paper's figure of structural descriptors, read as the share of the n qubits
+ *                outside the union of the cones' qubits (mean over the random choice when
+ *                rep is NULL)
  *   vertex_cover_out  [n] or NULL (only with rep): 1 for every qubit of the union of the
  *                cones, else 0
  * Host only, O(|E| (n + |E|)); errors AAQ_ERR_INVALID_ARG / AAQ_ERR_GRAPH / AAQ_ERR_ORBITS,
  * outputs untouched on error. */
 aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t *edges, const int32_t *orbit_of, int num_orbits,
-                       const int32_t *rep, int p, double *eta_out, uint8_t *vertex_cover_out);
+                       const int32_t *rep, int p, double *eta_out, double *qubit_elim_out,
+                       uint8_t *vertex_cover_out);
 
 /* ---------------------------------------------------------------- light cones
  * Light-cone evaluation, the locality reduction the paper names as compounding with the

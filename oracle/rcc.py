@@ -74,15 +74,30 @@ def vertex_cover(n: int, edges: Sequence[Tuple[int, int]], reps: Sequence[int], 
     return cov
 
 
-def eta_mean(n: int, edges: Sequence[Tuple[int, int]], orbit_of: Sequence[int], p: int) -> Fraction:
-    """Mean of eta_p over every choice of one representative per orbit (brute force: the
-    product of the orbit sizes must stay small)."""
+def qubit_elimination(n: int, edges: Sequence[Tuple[int, int]], reps: Sequence[int], p: int) -> Fraction:
+    """Share of the n qubits outside the union of the representatives' cone qubits (the
+    qubit-elimination fraction of the structural-descriptor figure, under that reading)."""
+    return 1 - Fraction(len(vertex_cover(n, edges, reps, p)), n)
+
+
+def _mean(fn, n, edges, orbit_of, p) -> Fraction:
     orbits: Dict[int, List[int]] = {}
     for f, m in enumerate(orbit_of):
         orbits.setdefault(int(m), []).append(f)
     groups = [orbits[m] for m in sorted(orbits)]
     total, count = Fraction(0), 0
     for choice in itertools.product(*groups):
-        total += eta(n, edges, choice, p)
+        total += fn(n, edges, choice, p)
         count += 1
     return total / count
+
+
+def eta_mean(n: int, edges: Sequence[Tuple[int, int]], orbit_of: Sequence[int], p: int) -> Fraction:
+    """Mean of eta_p over every choice of one representative per orbit (brute force: the
+    product of the orbit sizes must stay small)."""
+    return _mean(eta, n, edges, orbit_of, p)
+
+
+def qubit_elimination_mean(n: int, edges: Sequence[Tuple[int, int]], orbit_of: Sequence[int], p: int) -> Fraction:
+    """Mean of the qubit-elimination fraction over every choice of representatives."""
+    return _mean(qubit_elimination, n, edges, orbit_of, p)

@@ -110,7 +110,7 @@ def lib():
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
         "aaq_rcc_eta": (i, [i, i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), i,
-                            ctypes.POINTER(ctypes.c_int32), i, dp, ctypes.POINTER(ctypes.c_uint8)]),
+                            ctypes.POINTER(ctypes.c_int32), i, dp, dp, ctypes.POINTER(ctypes.c_uint8)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -339,10 +339,11 @@ def aaq_edge_orbits(n: int, edges, edge_weight=None):
     return of[:m].copy(), rep[:k.value].copy(), size[:k.value].copy()
 
 
-def aaq_rcc_eta(n: int, edges, orbit_of, p: int, rep=None, vertex_cover: bool = False):
+def aaq_rcc_eta(n: int, edges, orbit_of, p: int, rep=None, vertex_cover: bool = False, qubits: bool = False):
     """eta_p, the fraction of edges outside the union of the representatives' reverse causal
     cones; with ``rep=None`` the exact mean over uniformly drawn representatives.  With
-    ``vertex_cover`` (needs ``rep``) returns (eta, uint8[n] qubits of the union)."""
+    ``qubits`` also the qubit-elimination fraction, with ``vertex_cover`` (needs ``rep``)
+    also uint8[n], the qubits of the union: returns eta, or a tuple in that order."""
     e = _i32(edges)
     m = e.size // 2
     of = _i32(orbit_of)
@@ -352,11 +353,13 @@ def aaq_rcc_eta(n: int, edges, orbit_of, p: int, rep=None, vertex_cover: bool = 
     r = None if rep is None else _i32(rep)
     if r is not None and r.size != k:
         raise ValueError("one representative per orbit")
-    eta = ctypes.c_double()
+    eta, qe = ctypes.c_double(), ctypes.c_double()
     cov = np.zeros(max(int(n), 1), dtype=np.uint8) if vertex_cover else None
     _check(_lib.lib().aaq_rcc_eta(int(n), m, _ptr_i32(e), _ptr_i32(of), k, _ptr_i32(r), int(p), ctypes.byref(eta),
+                                  ctypes.byref(qe) if qubits else None,
                                   cov.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if cov is not None else None))
-    return (eta.value, cov[:n].copy()) if vertex_cover else eta.value
+    out = (eta.value,) + ((qe.value,) if qubits else ()) + ((cov[:n].copy(),) if vertex_cover else ())
+    return out if len(out) > 1 else out[0]
 
 
 def aaq_resident_workspace_size(prob: Problem, p: int, obs: int, with_grad: bool, checkpoint: bool = False,

@@ -236,10 +236,11 @@ extern "C" aaq_status aaq_edge_orbits(int n, int num_edges, const int32_t* edges
 // combined-RCC coverage subsection).  RCC_p(e), e = (i, j), holds the cost gates that do
 // not commute through to Z_i Z_j in p layers: the edges with an endpoint within graph
 // distance p - 1 of {i, j} (layer p: the gates on i or j; each earlier layer one hop
-// further); its qubits are the vertices within distance p.
+// further); its qubits are the vertices within distance p.  The qubit-elimination
+// fraction is the share of the n qubits outside the union of the cones' qubits.
 extern "C" aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t* edges, const int32_t* orbit_of,
                                   int num_orbits, const int32_t* rep, int p, double* eta_out,
-                                  uint8_t* vertex_cover_out) {
+                                  double* qubit_elim_out, uint8_t* vertex_cover_out) {
   if (n < 1 || n > 4096) return aaq::set_error(AAQ_ERR_INVALID_ARG, "n must be in [1, 4096]");
   if (num_edges < 1 || num_edges > (1 << 16)) return aaq::set_error(AAQ_ERR_GRAPH, "num_edges must be in [1, 65536]");
   if (!edges || !orbit_of || !eta_out) return aaq::set_error(AAQ_ERR_INVALID_ARG, "edges / orbit_of / eta_out is NULL");
@@ -291,7 +292,7 @@ extern "C" aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t* edges, co
     }
   };
   auto in_cone = [&](int f) { return std::min(dist[edges[2 * f]], dist[edges[2 * f + 1]]) <= p - 1; };
-  double outside = 0.0;  // edges outside the union (expected count without rep)
+  double outside = 0.0, qout = 0.0;  // edges / qubits outside the union (expected counts without rep)
   if (rep) {
     std::vector<char> covered(num_edges, 0), vcov(n, 0);
     for (int m = 0; m < num_orbits; ++m) {
@@ -302,25 +303,32 @@ extern "C" aaq_status aaq_rcc_eta(int n, int num_edges, const int32_t* edges, co
         if (dist[v] <= p) vcov[v] = 1;
     }
     for (int f = 0; f < num_edges; ++f) outside += covered[f] ? 0.0 : 1.0;
+    for (int v = 0; v < n; ++v) qout += vcov[v] ? 0.0 : 1.0;
     if (vertex_cover_out)
       for (int v = 0; v < n; ++v) vertex_cover_out[v] = (uint8_t)vcov[v];
   } else {
     // representatives drawn uniformly and independently per orbit: edge f lies outside
     // the union with probability prod_m (1 - c_mf / |m|), c_mf = the edges of orbit m
     // whose cone holds f
-    std::vector<double> miss(num_edges, 1.0);
-    std::vector<int> cnt(num_edges);
+    // (and qubit v likewise, with the edges whose cone's qubits hold v)
+    std::vector<double> miss(num_edges, 1.0), vmiss(n, 1.0);
+    std::vector<int> cnt(num_edges), vcnt(n);
     for (int m = 0; m < num_orbits; ++m) {
       std::fill(cnt.begin(), cnt.end(), 0);
+      std::fill(vcnt.begin(), vcnt.end(), 0);
       for (int e : members[m]) {
         cone(e);
         for (int f = 0; f < num_edges; ++f) cnt[f] += in_cone(f) ? 1 : 0;
+        for (int v = 0; v < n; ++v) vcnt[v] += dist[v] <= p ? 1 : 0;
       }
       const double sz = (double)members[m].size();
       for (int f = 0; f < num_edges; ++f) miss[f] *= 1.0 - cnt[f] / sz;
+      for (int v = 0; v < n; ++v) vmiss[v] *= 1.0 - vcnt[v] / sz;
     }
     for (int f = 0; f < num_edges; ++f) outside += miss[f];
+    for (int v = 0; v < n; ++v) qout += vmiss[v];
   }
   *eta_out = outside / num_edges;
+  if (qubit_elim_out) *qubit_elim_out = qout / n;
   return AAQ_OK;
 }

@@ -8,7 +8,8 @@ Oracle pins (oracle/rcc.py, brute force over every choice of representatives):
 * closed forms: the cycle C_n has eta_p = 1 - (2p + 1)/n; K_n (one orbit) has
   eta_1 = 1 - (2n - 3)/C(n, 2), rising with n as the paper says; a star has eta_p = 0; a graph
   with trivial automorphism group (every edge its own orbit) has eta_p = 0; eta_p never
-  grows with p.
+  grows with p; the qubit-elimination fraction is 0 for K_n, stars and trivial groups (as
+  the paper's figure of descriptors states) and 1 - (2p + 2)/n for cycles.
 Library (aaq_rcc_eta) against the oracle: exact means and single choices on trees, cycles,
 circulants, Petersen-type, complete, star, random 3-regular and random graphs; the vertex
 cover; the argument errors."""
@@ -79,6 +80,14 @@ def test_oracle_closed_forms():
     g = G.random_regular(3, 16, seed=3)
     assert len(set(orbits_of(g))) == g.m  # trivial group
     assert R.eta(g.n, g.edges, list(range(g.m)), 1) == 0
+    # qubit elimination (share of qubits outside the cones): the paper's figure has it
+    # identically 0 for K_n, stars and trivial groups, rising for edge-transitive families
+    for g in (G.complete(9), G.complete(14), G.star(10), G.random_regular(3, 16, seed=3)):
+        assert R.qubit_elimination_mean(g.n, g.edges, orbits_of(g), 1) == 0
+    for n in (9, 13, 30):
+        g = G.cycle(n)
+        for p in (1, 2, 3):
+            assert R.qubit_elimination_mean(g.n, g.edges, orbits_of(g), p) == 1 - Fraction(2 * p + 2, n)
     for g in (G.binary_tree(20), G.balanced_tree(3, 2), G.prufer_tree(18, 2)):
         of = orbits_of(g)
         vals = [R.eta_mean(g.n, g.edges, of, p) for p in (1, 2, 3, 4)]
@@ -99,11 +108,15 @@ def test_library_matches_oracle(g):
     rng = np.random.default_rng(g.n)
     for p in (1, 2, 3):
         if combos <= 4096:
-            assert abs(A.aaq_rcc_eta(g.n, e, of, p) - float(R.eta_mean(g.n, g.edges, of, p))) <= 1e-12
+            eta, qe = A.aaq_rcc_eta(g.n, e, of, p, qubits=True)
+            assert abs(eta - float(R.eta_mean(g.n, g.edges, of, p))) <= 1e-12
+            assert abs(qe - float(R.qubit_elimination_mean(g.n, g.edges, of, p))) <= 1e-12
+            assert A.aaq_rcc_eta(g.n, e, of, p) == eta
         for _ in range(3):
             reps = [int(rng.choice([f for f, m in enumerate(of) if m == k])) for k in range(max(of) + 1)]
-            eta, cov = A.aaq_rcc_eta(g.n, e, of, p, rep=reps, vertex_cover=True)
+            eta, qe, cov = A.aaq_rcc_eta(g.n, e, of, p, rep=reps, vertex_cover=True, qubits=True)
             assert abs(eta - float(R.eta(g.n, g.edges, reps, p))) <= 1e-12
+            assert abs(qe - float(R.qubit_elimination(g.n, g.edges, reps, p))) <= 1e-12
             assert sorted(np.flatnonzero(cov).tolist()) == sorted(R.vertex_cover(g.n, g.edges, reps, p))
 
 
