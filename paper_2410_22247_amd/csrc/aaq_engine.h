@@ -574,11 +574,16 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
     return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)0xFFFFFFFF, 0x00020000);
   }
+  // cache policy of the state loads: a sweep reads every amplitude once and the next
+  // sweep reads what this one stores, not what it loaded, so the loads are marked
+  // non-temporal (the nt bit of the gfx950 cache-policy field); the stores keep the
+  // default policy, so freshly written state can stay in the last-level cache
+  static constexpr int kStreamPolicy = 2;
   static __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(V) == 8)
-      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, 0));
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, kStreamPolicy));
     else
-      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)so, 0));
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)so, kStreamPolicy));
   }
   static __device__ __forceinline__ void buf_store(V x, __amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(V) == 8)
