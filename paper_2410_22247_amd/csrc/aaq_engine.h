@@ -122,6 +122,8 @@ template <class R> struct Ctx {
   int cmax;
   uint64_t N = 0;  // amplitudes per state (stride between checkpoint buffers)
   bool off32 = false;  // every byte offset inside one state buffer fits in 32 bits
+  bool nt = false;     // 64-bit path: non-temporal state loads (the single-instance sweeps,
+                       // whose states stream through HBM; the batched units keep theirs cached)
 };
 
 // Per-thread accumulators for one sweep.
@@ -579,6 +581,12 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // non-temporal (the nt bit of the gfx950 cache-policy field); the stores keep the
   // default policy, so freshly written state can stay in the last-level cache
   static constexpr int kStreamPolicy = 2;
+  // the same non-temporal load through a 64-bit address (states beyond 4 GiB)
+  static __device__ __forceinline__ V gload(const V* q) {
+    using E = R __attribute__((ext_vector_type(2)));
+    const E x = __builtin_nontemporal_load(reinterpret_cast<const E*>(q));
+    return mkv<R>(x.x, x.y);
+  }
   static __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(V) == 8)
       return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, kStreamPolicy));
@@ -599,7 +607,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // uniform part mfull - tile_base - roff[r] - tmax, both >= 0 (the parts are disjoint
   // bit fields of the index).
   template <int K, bool OFF32, bool MIR> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base,
-                                                                         uint64_t toff, const SetSpec& S) {
+                                                                         uint64_t toff, const SetSpec& S, bool nt) {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
@@ -624,8 +632,13 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     } else {
       const V* p = base + toff;
       if (!S.dummy && !(MIR && S.mirror)) {
+        if (nt) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+          for (int r = 0; r < NR; ++r) a[s][r] = gload(p + S.roff[r]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
+        }
       } else if (MIR && S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -682,12 +695,12 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // half state's mirrored registers are possible; false compiles them out
   template <int K, bool MIR = true>
   __device__ __forceinline__ void load_all(int s, const V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
-                                           bool off32) {
+                                           bool off32, bool nt = false) {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
     if (off32)
-      load_regs<K, true, MIR>(s, base, tile_base, toff, S);
+      load_regs<K, true, MIR>(s, base, tile_base, toff, S, true);
     else
-      load_regs<K, false, MIR>(s, base, tile_base, toff, S);
+      load_regs<K, false, MIR>(s, base, tile_base, toff, S, nt);
   }
   template <int K, bool MIR = true>
   __device__ __forceinline__ void store_all(int s, V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
@@ -757,9 +770,9 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
     } else {
       const uint64_t toff = tile_base + thread_off<KL>(S);
-      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32);
+      if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32, cx.nt);
       if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
-        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32);
+        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32, cx.nt);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -948,10 +961,11 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       init_at<KL>(S, cx.amp);
       lam_live = false;
     } else if (io) {
-      if (pg.flags & F_LOAD_PSI) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+      if (pg.flags & F_LOAD_PSI) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, tile_base + thread_off<KL>(S), S, cx.off32,
+                                                 cx.nt);
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
-        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32);
+        load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32, cx.nt);
         if (sc.fix_lam) {
           const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
 #pragma unroll
@@ -1114,7 +1128,7 @@ __global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V)};
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), true};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
