@@ -122,8 +122,9 @@ template <class R> struct Ctx {
   int cmax;
   uint64_t N = 0;  // amplitudes per state (stride between checkpoint buffers)
   bool off32 = false;  // every byte offset inside one state buffer fits in 32 bits
-  bool nt = false;     // 64-bit path: non-temporal state loads (the single-instance sweeps,
-                       // whose states stream through HBM; the batched units keep theirs cached)
+  bool nt = false;     // non-temporal state loads: set for single-instance evaluations that
+                       // stream more state than the last-level cache holds (the batched
+                       // units and small energy-only evaluations keep their state cached)
 };
 
 // Per-thread accumulators for one sweep.
@@ -577,9 +578,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)0xFFFFFFFF, 0x00020000);
   }
   // cache policy of the state loads: a sweep reads every amplitude once and the next
-  // sweep reads what this one stores, not what it loaded, so the loads are marked
-  // non-temporal (the nt bit of the gfx950 cache-policy field); the stores keep the
-  // default policy, so freshly written state can stay in the last-level cache
+  // sweep reads what this one stores, not what it loaded, so when the evaluation streams
+  // more state than the last-level cache holds the loads are marked non-temporal (the nt
+  // bit of the gfx950 cache-policy field); the stores keep the default policy, so freshly
+  // written state can stay in the last-level cache
   static constexpr int kStreamPolicy = 2;
   // the same non-temporal load through a 64-bit address (states beyond 4 GiB)
   static __device__ __forceinline__ V gload(const V* q) {
@@ -587,11 +589,13 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const E x = __builtin_nontemporal_load(reinterpret_cast<const E*>(q));
     return mkv<R>(x.x, x.y);
   }
+  template <bool NT>
   static __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
+    constexpr int pol = NT ? kStreamPolicy : 0;
     if constexpr (sizeof(V) == 8)
-      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, kStreamPolicy));
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, (int)so, pol));
     else
-      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)so, kStreamPolicy));
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)so, pol));
   }
   static __device__ __forceinline__ void buf_store(V x, __amdgpu_buffer_rsrc_t rs, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(V) == 8)
@@ -606,14 +610,14 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // mirrored index mfull - (toff + roff[r]): the thread part tmax - thread offset and the
   // uniform part mfull - tile_base - roff[r] - tmax, both >= 0 (the parts are disjoint
   // bit fields of the index).
-  template <int K, bool OFF32, bool MIR> __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base,
-                                                                         uint64_t toff, const SetSpec& S, bool nt) {
+  template <int K, bool OFF32, bool MIR, bool NT>
+  __device__ __forceinline__ void load_regs(int s, const V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S) {
     if constexpr (OFF32) {
       const __amdgpu_buffer_rsrc_t rs = rsrc(base);
       const uint32_t bo = (uint32_t)toff * (uint32_t)sizeof(V);
       if (!S.dummy && !(MIR && S.mirror)) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) a[s][r] = buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+        for (int r = 0; r < NR; ++r) a[s][r] = buf_load<NT>(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
       } else if (MIR && S.mirror) {
         const uint32_t bm = (uint32_t)(S.tmax - (toff - tile_base)) * (uint32_t)sizeof(V);
         // uniform over the workgroup: the mirrored registers' scalar offsets are su - roff
@@ -622,23 +626,18 @@ template <class R, int NS, bool EN, int LT> struct Tile {
         for (int r = 0; r < NR; ++r) {
           const uint32_t ro = (uint32_t)S.roff[r] * (uint32_t)sizeof(V);
           const bool m = (S.mirror >> r) & 1u;
-          a[s][r] = buf_load(rs, m ? bm : bo, m ? su - ro : ro);
+          a[s][r] = buf_load<NT>(rs, m ? bm : bo, m ? su - ro : ro);
         }
       } else {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : buf_load(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
+          a[s][r] = is_dummy<K>(S, r) ? mkv<R>(R(0), R(0)) : buf_load<NT>(rs, bo, (uint32_t)S.roff[r] * (uint32_t)sizeof(V));
       }
     } else {
       const V* p = base + toff;
       if (!S.dummy && !(MIR && S.mirror)) {
-        if (nt) {
 #pragma unroll
-          for (int r = 0; r < NR; ++r) a[s][r] = gload(p + S.roff[r]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < NR; ++r) a[s][r] = p[S.roff[r]];
-        }
+        for (int r = 0; r < NR; ++r) a[s][r] = NT ? gload(p + S.roff[r]) : p[S.roff[r]];
       } else if (MIR && S.mirror) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -697,10 +696,17 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   __device__ __forceinline__ void load_all(int s, const V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
                                            bool off32, bool nt = false) {
     static_assert(K == LAST, "global I/O happens at the load arrangement");
-    if (off32)
-      load_regs<K, true, MIR>(s, base, tile_base, toff, S, true);
-    else
-      load_regs<K, false, MIR>(s, base, tile_base, toff, S, nt);
+    if (off32) {
+      if (nt)
+        load_regs<K, true, MIR, true>(s, base, tile_base, toff, S);
+      else
+        load_regs<K, true, MIR, false>(s, base, tile_base, toff, S);
+    } else {
+      if (nt)
+        load_regs<K, false, MIR, true>(s, base, tile_base, toff, S);
+      else
+        load_regs<K, false, MIR, false>(s, base, tile_base, toff, S);
+    }
   }
   template <int K, bool MIR = true>
   __device__ __forceinline__ void store_all(int s, V* base, uint64_t tile_base, uint64_t toff, const SetSpec& S,
@@ -1080,6 +1086,7 @@ template <class R> struct SweepArgs {
   uint64_t N;  // amplitudes per state
   SetSpec set;
   SweepProg prog;
+  int nt;  // non-temporal state loads
 };
 
 #define AAQ_TILE_BOUNDS __launch_bounds__(1 << (LT - kRegBits))
@@ -1128,7 +1135,7 @@ __global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), true};
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), A.nt != 0};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
@@ -1392,6 +1399,7 @@ template <class R, int LT> hipError_t sweep_launch_impl(const LaunchSweep& L, hi
   A.N = L.N;
   A.set = L.set;
   A.prog = L.prog;
+  A.nt = L.nt ? 1 : 0;
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)(L.cmax + 1);
   if (L.set.route == ROUTE_HIGH)
     sweep_launch_rt<R, ROUTE_HIGH, LT>(A, L, dyn, st);

@@ -861,6 +861,9 @@ aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, u
     A.two_states = needs_two_states(S.progs[sw]);
     A.generic = weighted;
     A.half = S.half;
+    // non-temporal loads unless the whole evaluation is one state that fits the 256 MB
+    // last-level cache (in-place energy sweeps then reuse it from sweep to sweep)
+    A.nt = grad || need_state > ((size_t)256 << 20);
     const SweepProg& pg = S.progs[sw];
     const int moves = !!(pg.flags & F_LOAD_PSI) + !!(pg.flags & F_LOAD_LAM) + !!(pg.flags & F_STORE_PSI) +
                       !!(pg.flags & F_STORE_LAM);

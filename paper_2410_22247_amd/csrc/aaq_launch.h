@@ -51,6 +51,7 @@ struct LaunchSweep {
   bool two_states;
   bool generic = false;  // take every step from the program at run time (weighted instances)
   bool half = false;     // half state: the grid covers the tiles below ntiles / 2
+  bool nt = true;        // non-temporal state loads
 };
 
 struct LaunchUnits {
