@@ -3,9 +3,11 @@
 estimator on the 26-vertex random tree (Pruefer sequence, seed 3), H_red observable,
 complex64 amplitudes, one MI355X.
 
-One step = one aaq_energy_grad call (the whole hot path: phase tables, every forward
-and backward statevector sweep, the FP64 reductions) at one of the 32 seeded
-parameter points.  Prints ONE JSON line.  Alongside the headline number it reports
+One step = one energy + adjoint-gradient evaluation (the whole hot path: phase tables,
+every forward and backward statevector sweep, the FP64 reductions) at one of the 32
+seeded parameter points, through the resident evaluator (aaq_resident_execute: device
+parameters and outputs, forward-state checkpoints); ``--api host`` times the synchronous
+aaq_energy_grad_checkpointed call instead, ``--grad-mode uncompute`` the two-buffer mode.  Prints ONE JSON line.  Alongside the headline number it reports
 the roofline of the dominant kernel (HIP start and end events carried in the dispatch
 of every launch, on the stream the kernel runs on), the FP64 CPU oracle timed on the host cores, and H_red vs H_C
 in the three aggregation modes.
