@@ -17,7 +17,54 @@ struct ScaleStage {
   // LDS, so the walk makes no private-memory round trips)
   double mpr[kMaxCkpt], mpi[kMaxCkpt];
   uint64_t mF[kMaxCkpt];
+  // per sweep and mixer (2 i + 0: mixer A, 2 i + 1: mixer B), computed by the whole
+  // workgroup before the walk: k, w = |phi|^2, the flip flag and u = 1 / phi^m (the
+  // factor the walk multiplies sigma by), so the sequential walk does no division or
+  // power for a mixer
+  struct Mix {
+    double k, w, ur, ui;
+    uint32_t flip, pad;
+  } mix[kMaxSweeps * 2];
 };
+
+// the mixer quantities of sweep i's mixer X (0 = A, 1 = B) for a set with m mixed qubits:
+// e^{-i beta X} = phi (I - i k X) per qubit, with phi = cos(beta) and k = tan(beta) when
+// |cos| >= |sin|, else phi = -i dir sin(beta), k = -dir cot(beta) and a flip of the qubit
+__device__ void mixer_factors(ScaleStage& S, int i, int X) {
+  const SweepProg& pg = S.progs[i];
+  const int layer = X ? pg.mixB_layer : pg.mixA_layer;
+  const int dir = X ? pg.mixB_dir : pg.mixA_dir;
+  ScaleStage::Mix& o = S.mix[2 * i + X];
+  o.k = 0.0;
+  o.w = 1.0;
+  o.ur = 1.0;
+  o.ui = 0.0;
+  o.flip = 0;
+  o.pad = 0;
+  if (!dir) return;
+  const double sn = S.sb[layer], cs = S.cb[layer];
+  double pr, pi;  // phi
+  if (fabs(cs) >= fabs(sn)) {
+    o.k = dir * sn / cs;
+    pr = cs;
+    pi = 0.0;
+  } else {
+    o.k = -dir * cs / sn;
+    pr = 0.0;
+    pi = -dir * sn;
+    o.flip = 1;
+  }
+  o.w = pr * pr + pi * pi;
+  double qr = 1.0, qi = 0.0;  // phi^m
+  for (int j = __popc(S.act[pg.set]); j > 0; --j) {
+    const double tr = qr * pr - qi * pi;
+    qi = qr * pi + qi * pr;
+    qr = tr;
+  }
+  const double q2 = qr * qr + qi * qi;
+  o.ur = qr / q2;  // 1 / q = conj(q) / |q|^2
+  o.ui = -qi / q2;
+}
 
 // Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
 // the scale corrections (see SwScale).  out[nsweep].s_pre is 1/|sigma|^2 at the end.
@@ -37,33 +84,14 @@ __device__ void build_scales(ScaleStage& S, int nsweep, SwScale* out) {
     }
   };
   uint64_t F = 0;  // flip mask in registers
-  auto mixer = [&](int layer, int dir, uint32_t act, uint64_t gact, double& k, double& w, double& sx) {
-    k = 0.0;
-    w = 1.0;
+  auto mixer = [&](const ScaleStage::Mix& m, int dir, uint64_t gact, double& k, double& w, double& sx) {
+    k = m.k;
+    w = m.w;
     sx = 1.0 / (sr * sr + si * si);
     if (!dir) return;
-    const double sn = S.sb[layer], cs = S.cb[layer];
-    double pr, pi;  // phi
-    if (fabs(cs) >= fabs(sn)) {
-      k = dir * sn / cs;
-      pr = cs;
-      pi = 0.0;
-    } else {
-      k = -dir * cs / sn;
-      pr = 0.0;
-      pi = -dir * sn;
-      F ^= gact;
-    }
-    w = pr * pr + pi * pi;
-    // sigma /= phi^m
-    double qr = 1.0, qi = 0.0;
-    for (int i = __popc(act); i > 0; --i) {
-      const double tr = qr * pr - qi * pi;
-      qi = qr * pi + qi * pr;
-      qr = tr;
-    }
-    const double q2 = qr * qr + qi * qi;
-    const double nr = (sr * qr + si * qi) / q2, ni = (si * qr - sr * qi) / q2;
+    if (m.flip) F ^= gact;
+    // sigma /= phi^m, as sigma * u
+    const double nr = sr * m.ur - si * m.ui, ni = sr * m.ui + si * m.ur;
     sr = nr;
     si = ni;
   };
@@ -102,14 +130,13 @@ __device__ void build_scales(ScaleStage& S, int nsweep, SwScale* out) {
       r.lam_fix[1] = fi;
       r.fix_lam = (fr != 1.0 || fi != 0.0) ? 1u : 0u;
     }
-    const uint32_t act = S.act[pg.set];
     const uint64_t gact = S.gact[pg.set];
     r.F_pre = F;
     position(pg.pre_ops, r.rho_pre, r.s_pre);
-    mixer(pg.mixA_layer, pg.mixA_dir, act, gact, r.kA, r.wA, r.s_A);
+    mixer(S.mix[2 * i], pg.mixA_dir, gact, r.kA, r.wA, r.s_A);
     r.F_mid = F;
     position(pg.mid_ops, r.rho_mid, r.s_mid);
-    mixer(pg.mixB_layer, pg.mixB_dir, act, gact, r.kB, r.wB, r.s_B);
+    mixer(S.mix[2 * i + 1], pg.mixB_dir, gact, r.kB, r.wB, r.s_B);
     if (pg.flags & F_STORE_PSI) {
       mpr[pg.st_buf] = sr;
       mpi[pg.st_buf] = si;
@@ -144,6 +171,8 @@ __device__ void stage_and_build_scales(ScaleStage& S, const SweepProg* progs, in
     S.gact[s] = sets[s].gact;
   }
   for (int l = threadIdx.x; l < p; l += blockDim.x) sincos(beta[l], &S.sb[l], &S.cb[l]);
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nsweep; t += blockDim.x) mixer_factors(S, t >> 1, t & 1);
   __syncthreads();
   if (threadIdx.x == 0) build_scales(S, nsweep, out);
 }
