@@ -112,3 +112,25 @@ def test_half_does_not_apply_to_small_or_sampling():
     s = A.Sampler(pr2, 2, u.size)
     h, f = both(lambda: s.sample([0.3, 0.4], [0.5, 0.6], u))
     assert np.array_equal(h[0], f[0]) and np.array_equal(h[1], f[1])
+
+
+@pytest.mark.gpu
+def test_n26_energy_both_state_modes():
+    """The n = 26, p = 4 tree, energy only: the half state (one 256 MiB state, default-policy
+    loads) and the full state (512 MiB, non-temporal loads) both give the light-cone FP64
+    value, and agree with each other within rounding."""
+    import torch
+
+    from oracle import reduced as Rd
+    from workloads.configs import config3
+
+    wp, p, gams, bets = config3(1)
+    pr = A.Problem.from_workload(wp)
+    est = A.Estimator(pr, p, OBS_HRED, A.AAQ_PREC_C64, grad=False)
+    h, f = both(lambda: est.energy(gams[0], bets[0]))
+    e_ref = Rd.light_cone_energy(wp.n, wp.edges(), wp.terms(OBS_HRED), gams[0], bets[0])
+    for e in (h[0], f[0]):
+        assert abs(e - e_ref) <= 1e-5 * abs(e_ref), (e, e_ref)
+    assert abs(h[0] - f[0]) <= 2e-6 * abs(e_ref)
+    del est
+    torch.cuda.empty_cache()
