@@ -125,6 +125,13 @@ template <class R> struct Ctx {
   bool nt = false;     // non-temporal state loads: set for single-instance evaluations that
                        // stream more state than the last-level cache holds (the batched
                        // units and small energy-only evaluations keep their state cached)
+  // Centre of h and C for the adjoint sums: cmax / 2, the mean of both under |+>.  lambda
+  // is made as (h - cen) psi and the gamma gradient sums (C - cen) Im(conj(lambda) psi).
+  // Neither changes a gradient: <psi|G|psi> is real for a Hermitian generator G, and
+  // <lambda|psi> = <psi_f|H|psi_f> is real at every position (both states are moved by
+  // the same unitaries), so the shifts drop out of 2 Im <lambda|G|psi>.  They shrink the
+  // magnitudes that cancel in those sums, and with them the float32 rounding.
+  R cen = R(0);
 };
 
 // Per-thread accumulators for one sweep.
@@ -475,7 +482,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (NS == 2 && make_lam) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const R h = (R)hv[r];
+          const R h = (R)hv[r] - cx.cen;
           a[NS - 1][r] = mkv<R>(h * a[0][r].x, h * a[0][r].y);
         }
         lam_live = true;
@@ -488,7 +495,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
         if (ops & OP_GRADG) {
           R gs = R(0);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+          for (int r = 0; r < NR; ++r) gs += ((R)cv[r] - cx.cen) * imcm(a[NS - 1][r], a[0][r]);
           // formed before the phase step below overwrites the states (ordered with its
           // table reads), so the pre-phase values are not kept alive
           asm volatile("" : "+v"(gs));
@@ -512,28 +519,49 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
   }
 
-  // <Z_i Z_j> partial sums per term, reduced per wave and added into LDS
+  // <Z_i Z_j> partial sums per term, in a fixed order: each term's wave sum is kept by
+  // lane (t mod 64) of the wave, and the waves then add their sums into the workgroup's
+  // LDS accumulator one after another (wave 0 first), so repeated runs give identical bits.
   template <int K> __device__ __forceinline__ void perterm(const SetSpec& S, uint64_t zb, const Ctx<R>& cx, double* zz_lds) const {
     constexpr int B0 = G::b0(K);
+    constexpr int NC = (kMaxT + 63) / 64;
     R p2[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) p2[r] = a[0][r].x * a[0][r].x + a[0][r].y * a[0][r].y;
-    for (int t = 0; t < cx.T; ++t) {
-      const int4 tm = cx.terms[t];
-      int ri = -1, rj = -1;
+    const int lane = threadIdx.x & 63;
+    double mine[NC];
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        if (S.pos[B0 + b] == (uint32_t)tm.x) ri = b;
-        if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
+    for (int c = 0; c < NC; ++c) {
+      mine[c] = 0.0;
+      const int tend = min(cx.T - c * 64, 64);
+      for (int j = 0; j < tend; ++j) {
+        const int4 tm = cx.terms[c * 64 + j];
+        int ri = -1, rj = -1;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          if (S.pos[B0 + b] == (uint32_t)tm.x) ri = b;
+          if (S.pos[B0 + b] == (uint32_t)tm.y) rj = b;
+        }
+        const uint32_t sm = (ri >= 0 ? (1u << ri) : 0u) ^ (rj >= 0 ? (1u << rj) : 0u);
+        R acc = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc += (__popc((uint32_t)r & sm) & 1) ? -p2[r] : p2[r];
+        const int odd = (int)(((zb >> tm.x) ^ (zb >> tm.y)) & 1u);
+        double v = odd ? -(double)acc : (double)acc;
+        v = wave_sum(v);
+        if (lane == j) mine[c] = v;
       }
-      const uint32_t sm = (ri >= 0 ? (1u << ri) : 0u) ^ (rj >= 0 ? (1u << rj) : 0u);
-      R acc = R(0);
+    }
+    const int wave = threadIdx.x >> 6;
+    for (int w = 0; w < (1 << LB) / 64; ++w) {
+      if (wave == w) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc += (__popc((uint32_t)r & sm) & 1) ? -p2[r] : p2[r];
-      const int odd = (int)(((zb >> tm.x) ^ (zb >> tm.y)) & 1u);
-      double v = odd ? -(double)acc : (double)acc;
-      v = wave_sum(v);
-      if ((threadIdx.x & 63) == 0) atomicAdd(&zz_lds[t], v);
+        for (int c = 0; c < NC; ++c) {
+          const int t = c * 64 + lane;
+          if (t < cx.T) zz_lds[t] += mine[c];
+        }
+      }
+      __syncthreads();
     }
   }
 
@@ -885,7 +913,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (NS == 2 && make_lam) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const R h = (R)hv[r];
+          const R h = (R)hv[r] - cx.cen;
           a[NS - 1][r] = mkv<R>(h * a[0][r].x, h * a[0][r].y);
         }
         lam_live = true;
@@ -900,7 +928,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (NS == 2 && (ops & OP_GRADG)) {
         R gs = R(0);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gs += (R)cv[r] * imcm(a[NS - 1][r], a[0][r]);
+        for (int r = 0; r < NR; ++r) gs += ((R)cv[r] - cx.cen) * imcm(a[NS - 1][r], a[0][r]);
         asm volatile("" : "+v"(gs));  // formed here (see ops_at)
         gacc += (double)gs;
       }
@@ -1135,7 +1163,8 @@ __global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   if (PT)
     for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
   __syncthreads();
-  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), A.nt != 0};
+  Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), A.nt != 0,
+            (R)(0.5 * A.cmax)};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
@@ -1220,6 +1249,7 @@ template <class R, int NS, int LT> __global__ AAQ_TILE_BOUNDS void k_units(UnitA
     V* psi = big ? reinterpret_cast<V*>(A.ws + D->state_off) : A.psi_io;
     V* lam = big ? psi + ((size_t)1 << D->n) : nullptr;
     Ctx<R> cx{g, terms, tab, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+    cx.cen = (R)(0.5 * D->cmax);
     Tile<R, NS, true, LT> tl;
     tl.lam_live = false;
     const int ns = D->nsweep;
@@ -1300,6 +1330,7 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
   V* lam = psi + ((size_t)1 << D->n);
   Ctx<R> cx{g, terms, tab, psi, NS == 2 ? lam : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+  cx.cen = (R)(0.5 * D->cmax);
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();

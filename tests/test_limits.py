@@ -3,8 +3,7 @@ phase table (total cut weight 560 of the 561 allowed, on K_20), single-edge and
 single-vertex instances, and depths whose checkpoint count exceeds the buffer limit.
 
 CPU: the error paths of these limits.
-GPU: parity with the FP64 oracle at the limits (tolerances as in test_gpu_parity, the
-weighted complex64 gradient reading of test_weighted)."""
+GPU: parity with the FP64 oracle at the limits (tolerances as in test_gpu_parity)."""
 import math
 
 import numpy as np
@@ -16,10 +15,10 @@ from workloads import graphs as G
 from workloads.configs import OBS_HC, OBS_HRED, make_problem
 
 
-def check(e, dg, db, e_ref, dg_ref, db_ref, tol, e_scale=False):
+def check(e, dg, db, e_ref, dg_ref, db_ref, tol):
     assert abs(e - e_ref) <= tol * max(abs(e_ref), 1e-12), (e, e_ref)
     g, gr = np.concatenate([dg, db]), np.concatenate([dg_ref, db_ref])
-    scale = max(np.linalg.norm(gr), abs(e_ref) if e_scale else 0.0, 1e-12)
+    scale = max(np.linalg.norm(gr), 1e-12)
     assert np.linalg.norm(g - gr) <= tol * scale, (g, gr)
 
 
@@ -60,7 +59,7 @@ def test_depth_64(g):
             est = A.Estimator(pr, 64, obs, prec, grad=True)
             e, dg, db, nrm = est.energy_grad(gam, bet)
             check(e, dg, db, e_ref, dg_ref, db_ref, tol)
-            assert abs(nrm - 1) <= (1e-12 if prec == A.AAQ_PREC_C128 else 1e-4)
+            assert abs(nrm - 1) <= (1e-12 if prec == A.AAQ_PREC_C128 else 1e-5)
 
 
 @pytest.mark.gpu
@@ -78,7 +77,7 @@ def test_largest_phase_table_k20_weighted():
     for prec, tol in ((A.AAQ_PREC_C128, 1e-10), (A.AAQ_PREC_C64, 1e-5)):
         est = A.Estimator(pr, 2, OBS_HC, prec, grad=True)
         e, dg, db, _ = est.energy_grad(gam, bet)
-        check(e, dg, db, e_ref, dg_ref, db_ref, tol, prec == A.AAQ_PREC_C64)
+        check(e, dg, db, e_ref, dg_ref, db_ref, tol)
     ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
     out = torch.empty(1 << g.n, dtype=torch.int32, device="cuda")
     A.aaq_cut_values(pr, OBS_HC, ws, out)

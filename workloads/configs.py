@@ -100,13 +100,13 @@ def _points(seed: int, count: int, p: int):
 def config2():
     """Orbit-reduction diagnostics, complex64, 256 points per graph drawn from
     default_rng(0): gamma ~ U[0,pi]^(256,p), then beta ~ U[0,pi/2]^(256,p).
-    (a) K_16, p=1; (b) star with 19 leaves (n=20), p=2; (c) random 3-regular
-    n=22 seed 7, p=3."""
+    (a) K_16, p=1; (b) star with 19 leaves (n=20), p=2; (c) the random 3-regular
+    graph networkx.random_regular_graph(3, 22, seed=7) (frozen edge list), p=3."""
     out = []
     for name, g, p in (
         ("K16", G.complete(16), 1),
         ("star20", G.star(19), 2),
-        ("3reg22", G.random_regular(3, 22, seed=7), 3),
+        ("3reg22", G.networkx_random_regular_3_22_seed7(), 3),
     ):
         gam, bet = _points(0, 256, p)
         out.append((name, make_problem(g), p, gam, bet))

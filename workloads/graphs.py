@@ -9,6 +9,8 @@ Vertices are 0..n-1 and vertex v is qubit v, i.e. bit v of a basis index z.
 """
 from __future__ import annotations
 
+import json
+import os
 from dataclasses import dataclass, field
 from typing import List, Sequence, Tuple
 
@@ -192,3 +194,16 @@ def random_regular(d: int, n: int, seed: int | None = None, rng: np.random.Gener
         if ok:
             return Graph(n, sorted(es), name=f"random_{d}_regular(n={n},seed={seed})")
     raise RuntimeError("pairing model did not produce a simple graph")
+
+
+FROZEN_RR_3_22_SEED7 = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                                    "random_regular_3_22_seed7.json")
+
+
+def networkx_random_regular_3_22_seed7() -> Graph:
+    """The 3-regular graph on 22 vertices that ``networkx.random_regular_graph(3, 22, seed=7)``
+    returns, read from its frozen edge list (written by tests/golden/make_references.py), so
+    the instance does not depend on the installed networkx."""
+    with open(FROZEN_RR_3_22_SEED7) as f:
+        d = json.load(f)
+    return Graph(int(d["n"]), [tuple(e) for e in d["edges"]], name="random_3_regular(n=22,seed=7,networkx)")
