@@ -155,6 +155,24 @@ aaq_status aaq_energy_grad_checkpointed(const aaq_problem *prob, int p, const do
                                         void *stream, double *energy_out, double *dgamma_out, double *dbeta_out,
                                         double *norm_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same energy and adjoint gradient as
+ * aaq_energy_grad, bit for bit, with the workspace taken from a static device array of
+ * AAQ_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends (its device address is looked up once per device).  The call allocates
+ * no device memory and no pinned host memory: the upload goes through ordinary host
+ * memory, so the call synchronises the stream like aaq_energy_grad.
+ *   d_state, d_lambda  caller buffers as for aaq_energy_grad
+ *   returns AAQ_ERR_BUFFER before any HIP call when the problem's workspace
+ *   (aaq_workspace_size with gradients) exceeds AAQ_NOALLOC_SCRATCH_BYTES.
+ * Every call on one GPU uses that GPU's array: calls that overlap in time on one GPU
+ * (several host threads or streams) race and must be serialised by the caller. */
+#define AAQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+aaq_status aaq_energy_grad_noalloc(const aaq_problem *prob, int p, const double *gamma, const double *beta,
+                                   aaq_observable obs, aaq_precision prec, void *d_state, size_t state_bytes,
+                                   void *d_lambda, size_t lambda_bytes, void *stream, double *energy_out,
+                                   double *dgamma_out, double *dbeta_out, double *norm_out);
+
 /* Exact integer values of the observable's diagonal for every z in [0, 2^n):
  * C(z) for AAQ_OBS_HC, h_red(z) = sum_m |S_m| [z_{i_m} != z_{j_m}] for AAQ_OBS_HRED
  * (the diagonal of H_C and H_red without the 1/2 (1 - ZZ) rewriting), computed by the

@@ -14,5 +14,5 @@ from .api import (  # noqa: F401
     aaq_lightcone_info, aaq_lightcone_workspace_size, aaq_lightcone_create, aaq_lightcone_execute,
     aaq_lightcone_destroy, LightCone, aaq_edge_orbits, aaq_rcc_eta, aaq_sample_workspace_size, aaq_sample, Sampler,
     aaq_resident_workspace_size, aaq_resident_create, aaq_resident_execute, aaq_resident_destroy, Resident,
-    aaq_set_half_state, aaq_get_half_state,
+    aaq_set_half_state, aaq_get_half_state, aaq_energy_grad_noalloc,
 )

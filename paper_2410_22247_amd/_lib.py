@@ -50,7 +50,7 @@ EXPORTS = (
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
     "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample", "aaq_resident_workspace_size",
     "aaq_resident_create", "aaq_resident_execute", "aaq_resident_destroy", "aaq_set_half_state",
-    "aaq_get_half_state", "aaq_rcc_eta",
+    "aaq_get_half_state", "aaq_rcc_eta", "aaq_energy_grad_noalloc",
 )
 
 
@@ -73,6 +73,7 @@ def lib():
         "aaq_workspace_size": (i, [P, i, i, i, i, i, szp]),
         "aaq_energy": (i, [P, i, dp, dp, i, i, i, vp, sz, vp, sz, vp, dp, dp, dp]),
         "aaq_energy_grad": (i, [P, i, dp, dp, i, i, vp, sz, vp, sz, vp, sz, vp, dp, dp, dp, dp]),
+        "aaq_energy_grad_noalloc": (i, [P, i, dp, dp, i, i, vp, sz, vp, sz, vp, dp, dp, dp, dp]),
         "aaq_cut_values": (i, [P, i, vp, sz, vp, vp]),
         "aaq_cut_values_layout": (i, [P, i, i, i, i, vp, sz, vp, vp]),
         "aaq_num_sets": (i, [i, i]),

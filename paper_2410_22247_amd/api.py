@@ -172,6 +172,20 @@ def aaq_energy_grad(prob: Problem, gamma, beta, obs: int, prec: int, d_state, d_
     return e.value, dg, db, nrm.value
 
 
+def aaq_energy_grad_noalloc(prob: Problem, gamma, beta, obs: int, prec: int, d_state, d_lambda, stream=None):
+    """aaq_energy_grad with the library's static per-GPU workspace (no workspace argument, no
+    allocation inside the call); returns (energy, dE/dgamma[p], dE/dbeta[p], norm)."""
+    g, b = _params(gamma, beta)
+    p = g.size
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    dg, db = np.zeros(p), np.zeros(p)
+    sp, sb = _dev(d_state)
+    lp, lb = _dev(d_lambda)
+    _check(_lib.lib().aaq_energy_grad_noalloc(prob.ref(), p, _dp(g), _dp(b), int(obs), int(prec), sp, sb, lp, lb,
+                                              _stream(stream), ctypes.byref(e), _dp(dg), _dp(db), ctypes.byref(nrm)))
+    return e.value, dg, db, nrm.value
+
+
 def aaq_checkpoint_bytes(prob: Problem, p: int, prec: int = AAQ_PREC_C64) -> int:
     out = ctypes.c_size_t()
     _check(_lib.lib().aaq_checkpoint_bytes(prob.ref(), int(p), int(prec), ctypes.byref(out)))

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libaaqaoa.so")
 
 
 def sources():
-    return ([os.path.join(CSRC, "aaq_kernels.hip")] + sorted(glob.glob(os.path.join(CSRC, "aaq_inst_*.hip")))
+    return ([os.path.join(CSRC, "aaq_kernels.hip"), os.path.join(CSRC, "aaq_noalloc.hip")]
+            + sorted(glob.glob(os.path.join(CSRC, "aaq_inst_*.hip")))
             + [os.path.join(CSRC, "aaq_host.cpp"), os.path.join(CSRC, "aaq_orbits.cpp")])
 
 

@@ -791,6 +791,14 @@ unsigned char* pinned_staging(size_t bytes) {
   return buf;
 }
 
+// the same role in ordinary host memory, for calls that must not allocate pinned memory;
+// it grows on the host heap as needed and is kept for the life of the thread
+unsigned char* pageable_staging(size_t bytes) {
+  thread_local std::vector<unsigned char> buf;
+  if (buf.size() < bytes) buf.resize(std::max(align_up(bytes, 4096), (size_t)65536));
+  return buf.data();
+}
+
 // checks the caller's buffers against a host plan
 aaq_status check_buffers(const Single& S, bool grad, void* d_state, size_t state_bytes, void* d_lam, size_t lam_bytes,
                          void* d_ws, size_t ws_bytes) {
@@ -894,7 +902,8 @@ aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, u
 aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_observable obs,
                       aaq_aggregation agg, aaq_precision prec, bool grad, void* d_state, size_t state_bytes,
                       void* d_lam, size_t lam_bytes, void* d_ws, size_t ws_bytes, void* stream, std::vector<double>& res,
-                      int tile = 0, bool ckpt = false, bool keep_state = false, Single* plan_out = nullptr) {
+                      int tile = 0, bool ckpt = false, bool keep_state = false, Single* plan_out = nullptr,
+                      bool pageable = false) {
   aaq_status st = validate_problem(pr);
   if (st) return st;
   if ((st = validate_p(p))) return st;
@@ -919,7 +928,8 @@ aaq_status run_single(const aaq_problem* pr, int p, const double* gamma, const d
   unsigned char* ws = (unsigned char*)d_ws;
   // host staging of everything that is uploaded (pinned, reused: the copies are
   // asynchronous, and the call ends with a stream synchronisation)
-  unsigned char* up = pinned_staging(L.upload_end + sizeof(double) * L.nout);
+  unsigned char* up = pageable ? pageable_staging(L.upload_end + sizeof(double) * L.nout)
+                               : pinned_staging(L.upload_end + sizeof(double) * L.nout);
   if (!up) return fail(AAQ_ERR_HIP, "hipHostMalloc of the staging buffer failed");
   stage_static(S, pr, obs, up);
   std::memcpy(up + L.params, gamma, sizeof(double) * p);
@@ -990,6 +1000,32 @@ aaq_status run_sample(const aaq_problem* pr, int p, const double* gamma, const d
 }
 
 }  // namespace
+
+aaq_status aaq::validate_call(const aaq_problem* prob, int p, const double* gamma, const double* beta) {
+  aaq_status st = validate_problem(prob);
+  if (st) return st;
+  if ((st = validate_p(p))) return st;
+  return validate_params(p, gamma, beta);
+}
+
+aaq_status aaq::energy_grad_pageable(const aaq_problem* prob, int p, const double* gamma, const double* beta,
+                                     aaq_observable obs, aaq_precision prec, void* d_state, size_t state_bytes,
+                                     void* d_lambda, size_t lambda_bytes, void* d_ws, size_t ws_bytes, void* stream,
+                                     double* energy_out, double* dgamma_out, double* dbeta_out, double* norm_out) {
+  if (!energy_out || !dgamma_out || !dbeta_out) return fail(AAQ_ERR_INVALID_ARG, "output pointer is NULL");
+  std::vector<double> res;
+  aaq_status s = run_single(prob, p, gamma, beta, obs, AAQ_AGG_FUSED, prec, true, d_state, state_bytes, d_lambda,
+                            lambda_bytes, d_ws, ws_bytes, stream, res, 0, false, false, nullptr, true);
+  if (s) return s;
+  *energy_out = res[0];
+  if (norm_out) *norm_out = res[1];
+  for (int l = 0; l < p; ++l) {
+    dgamma_out[l] = res[2 + l];
+    dbeta_out[l] = res[2 + p + l];
+  }
+  return AAQ_OK;
+}
+
 
 // ====================================================================== plans
 struct aaq_plan {

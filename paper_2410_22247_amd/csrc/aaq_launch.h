@@ -13,6 +13,16 @@ namespace aaq {
 // sets the message aaq_last_error_message returns; returns s
 aaq_status set_error(aaq_status s, const std::string& msg);
 
+// host validation of a problem, depth and parameter arrays (no HIP call)
+aaq_status validate_call(const aaq_problem* prob, int p, const double* gamma, const double* beta);
+
+// aaq_energy_grad on a given workspace, staging the upload and the results in ordinary
+// (pageable) host memory: no device or pinned host allocation
+aaq_status energy_grad_pageable(const aaq_problem* prob, int p, const double* gamma, const double* beta,
+                                aaq_observable obs, aaq_precision prec, void* d_state, size_t state_bytes,
+                                void* d_lambda, size_t lambda_bytes, void* d_ws, size_t ws_bytes, void* stream,
+                                double* energy_out, double* dgamma_out, double* dbeta_out, double* norm_out);
+
 // Timing events for the next launches of this host thread (set by the host's per-kernel
 // timing, null otherwise).  The first launch takes `start` into its dispatch and every
 // launch takes `stop`, so a group of launches is timed from the first kernel's start to
