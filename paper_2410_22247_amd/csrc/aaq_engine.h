@@ -26,6 +26,20 @@
 
 namespace aaq {
 
+// Read-only uniform data (graph masks, term lists, per-sweep scale records) is read
+// through the constant address space: with a uniform address such a load is one scalar
+// load for the whole wave (no vector registers, no wait on the vector memory counter).
+// No kernel writes the data it reads this way; it comes from host uploads or from an
+// earlier kernel of the stream.
+// (The host compilation pass sees these device functions too; address spaces exist only
+// in the device pass.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T> using cptr = const __attribute__((address_space(4))) T*;
+#else
+template <class T> using cptr = const T*;
+#endif
+template <class T> __device__ __forceinline__ cptr<T> cst(const T* p) { return (cptr<T>)p; }
+
 template <class R> struct Cx;
 template <> struct Cx<float> {
   using V = float2;
@@ -268,24 +282,63 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (NS == 2 && LAM) {
+      // The register bits mixed here are taken two at a time where possible: for qubits
+      // b1, b2 and the four registers r0 = r, r1 = r ^ b1, r2 = r ^ b2, r3 = r ^ b1 ^ b2 the
+      // eight pair terms of both qubits add up to
+      //   Im(conj(lam0 + lam3) (psi1 + psi2)) + Im(conj(lam1 + lam2) (psi0 + psi3)),
+      // twelve operations where the two qubits' terms one by one take sixteen.  A pair with
+      // a qubit the set does not mix (uniform test) takes the single-qubit form.
+      constexpr uint32_t MB = (MASK >> B0) & ((1u << RB) - 1u);
       R gt = R(0);
+      uint32_t left = MB;
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        if (!((MASK >> (B0 + b)) & 1u)) continue;
-        // sum over pairs of Im(conj(lam_r) psi_r1) + Im(conj(lam_r1) psi_r): two chains
-        // of fused multiply-adds (four per pair)
-        R g0 = R(0), g1 = R(0);
+      for (int b1 = 0; b1 < RB; ++b1) {
+        if (!((left >> b1) & 1u)) continue;
+        int b2 = -1;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          if (r & (1 << b)) continue;
-          const int r1 = r | (1 << b);
-          const V &l0 = a[NS - 1][r], &l1 = a[NS - 1][r1], &p0 = a[0][r], &p1 = a[0][r1];
-          g0 = fmar(l0.x, p1.y, g0);
-          g0 = fmar(-l0.y, p1.x, g0);
-          g1 = fmar(l1.x, p0.y, g1);
-          g1 = fmar(-l1.y, p0.x, g1);
+        for (int c = b1 + 1; c < RB; ++c)
+          if (b2 < 0 && ((left >> c) & 1u)) b2 = c;
+        left &= ~(1u << b1);
+        if (b2 >= 0) left &= ~(1u << b2);
+        const bool on1 = ((act >> (B0 + b1)) & 1u) != 0;
+        const bool on2 = b2 >= 0 && ((act >> (B0 + b2)) & 1u) != 0;
+        if (b2 >= 0 && on1 && on2) {
+          R g0 = R(0), g1 = R(0);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            if (r & ((1 << b1) | (1 << b2))) continue;
+            const int r1 = r | (1 << b1), r2 = r | (1 << b2), r3 = r1 | r2;
+            const V la = mkv<R>(a[NS - 1][r].x + a[NS - 1][r3].x, a[NS - 1][r].y + a[NS - 1][r3].y);
+            const V lb = mkv<R>(a[NS - 1][r1].x + a[NS - 1][r2].x, a[NS - 1][r1].y + a[NS - 1][r2].y);
+            const V pa = mkv<R>(a[0][r1].x + a[0][r2].x, a[0][r1].y + a[0][r2].y);
+            const V pb = mkv<R>(a[0][r].x + a[0][r3].x, a[0][r].y + a[0][r3].y);
+            g0 = fmar(la.x, pa.y, g0);
+            g0 = fmar(-la.y, pa.x, g0);
+            g1 = fmar(lb.x, pb.y, g1);
+            g1 = fmar(-lb.y, pb.x, g1);
+          }
+          gt += g0 + g1;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int b = q == 0 ? b1 : b2;
+            if (b < 0) continue;
+            // sum over pairs of Im(conj(lam_r) psi_r1) + Im(conj(lam_r1) psi_r): two chains
+            // of fused multiply-adds (four per pair)
+            R g0 = R(0), g1 = R(0);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+              if (r & (1 << b)) continue;
+              const int r1 = r | (1 << b);
+              const V &l0 = a[NS - 1][r], &l1 = a[NS - 1][r1], &p0 = a[0][r], &p1 = a[0][r1];
+              g0 = fmar(l0.x, p1.y, g0);
+              g0 = fmar(-l0.y, p1.x, g0);
+              g1 = fmar(l1.x, p0.y, g1);
+              g1 = fmar(-l1.y, p0.x, g1);
+            }
+            gt += ((act >> (B0 + b)) & 1u) ? g0 + g1 : R(0);
+          }
         }
-        gt += ((act >> (B0 + b)) & 1u) ? g0 + g1 : R(0);
       }
       gsum += wcur * gt;
       // the terms are formed here, before a following transpose: the empty volatile asm
@@ -295,45 +348,66 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   }
 
   // -------------------------------------------------------------- z of register 0
+  // the global bits of this thread's register 0 at arrangement K (the load or the phase
+  // arrangement): the thread index scattered by the set's runs (two VALU per run)
+  template <int K> __device__ __forceinline__ uint64_t tbits(const SetSpec& S) const {
+    static_assert(K == LAST || K == P, "thread-bit runs exist for the load and phase arrangements");
+    constexpr int KI = (K == LAST) ? 0 : 1;
+    const uint32_t t = threadIdx.x;
+    if (!S.tr64) {
+      uint32_t z = 0;
+#pragma unroll
+      for (int i = 0; i < kMaxRuns; ++i) {
+        const uint32_t r = S.trun[KI][i];
+        z |= __builtin_amdgcn_ubfe(t, r & 0xFFu, (r >> 8) & 0xFFu) << (r >> 16);
+      }
+      return z;
+    }
+    uint64_t z = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxRuns; ++i) {
+      const uint32_t r = S.trun[KI][i];
+      z |= (uint64_t)__builtin_amdgcn_ubfe(t, r & 0xFFu, (r >> 8) & 0xFFu) << (r >> 16);
+    }
+    return z;
+  }
   // index z of register 0 at arrangement K, XOR the flip mask F: the register-0
   // amplitude is the one of basis state zbase ^ F (register bits set where F has them)
   template <int K> __device__ __forceinline__ uint64_t zbase(const SetSpec& S, uint64_t tile_base, uint64_t F) const {
-    constexpr int B0 = G::b0(K);
-    const uint32_t t = threadIdx.x;
-    uint64_t z = tile_base;
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int tb = (i < B0) ? i : i + RB;
-      const uint32_t p = S.pos[tb];
-      if (p != kDummy) z |= (uint64_t)((t >> i) & 1u) << p;
-    }
-    return z ^ F;
+    return (tile_base | tbits<K>(S)) ^ F;
   }
 
-  // C(z) for every register amplitude at arrangement K.  With base b = zb and m the
-  // register bits flipped relative to it: C(b ^ m) = C(b) + sum_{v in m} d_v
+  // C(z) for every register amplitude at arrangement K.  With base b = zb (register bits
+  // at their values in the flip mask F, which is uniform) and m the register bits flipped
+  // relative to it: C(b ^ m) = C(b) + sum_{v in m} d_v
   //   + sum_{edges (v, w) inside m} 2 (2 [b_v != b_w] - 1),
-  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.
-  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, const GraphDev* g, int (&cv)[NR]) const {
-    // every index bit is below n: with n <= 32 the masks fit 32-bit registers, which
-    // halves the vector work of the mask arithmetic (uniform branch)
-    if (g->n <= 32)
-      cuts_m<K, uint32_t>(S, zb, g, cv);
-    else
-      cuts_m<K, uint64_t>(S, zb, g, cv);
-  }
-  static __device__ __forceinline__ int popc(uint32_t x) { return __popc(x); }
-  static __device__ __forceinline__ int popc(uint64_t x) { return __popcll(x); }
-  template <int K, class M>
-  __device__ __forceinline__ void cuts_m(const SetSpec& S, uint64_t zb64, const GraphDev* g, int (&cv)[NR]) const {
-    constexpr int B0 = G::b0(K);
+  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.  C(b) = sum_v [b_v] popc(adj_v & ~b):
+  // per vertex a sign-extended bit, a three-input AND and a population count.  The masks
+  // come from scalar loads; everything about the register bits is uniform (scalar).
+  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, uint64_t F, const GraphDev* g0,
+                                                        int (&cv)[NR]) const {
+    const cptr<GraphDev> g = cst(g0);
     const int n = g->n;
-    const M zb = (M)zb64;
+    // every index bit is below n: with n <= 32 the masks fit 32-bit registers (uniform branch)
     int c0 = 0;
-    for (int v = 0; v < n; ++v) {
-      const M av = (M)g->adj[v];
-      c0 += (int)((zb >> v) & 1u) * popc((M)(av & ~zb));
+    if (n <= 32) {
+      const uint32_t z = (uint32_t)zb;
+      const cptr<uint4> a4 = (cptr<uint4>)&g->adj32[0];
+      for (int v = 0; v < n; v += 4) {
+        const uint4 a = a4[v >> 2];
+        // bit v of z sign-extended to a mask (v_bfe_i32), then one three-input AND
+        c0 = __popc(a.x & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v, 1)) + c0;
+        c0 = __popc(a.y & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v + 1, 1)) + c0;
+        c0 = __popc(a.z & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v + 2, 1)) + c0;
+        c0 = __popc(a.w & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v + 3, 1)) + c0;
+      }
+    } else {
+      for (int v = 0; v < n; ++v) {
+        const uint64_t m = 0ull - ((zb >> v) & 1ull);
+        c0 += __popcll(g->adj[v] & ~zb & m);
+      }
     }
+    constexpr int B0 = G::b0(K);
     int d[RB];
     uint32_t rr[RB], df[RB];
 #pragma unroll
@@ -343,15 +417,16 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       rr[b] = 0;
       df[b] = 0;
       if (v != kDummy) {
-        const M av = (M)g->adj[v];
-        const M bv = (zb >> v) & 1u;
-        d[b] = g->deg[v] - 2 * popc((M)(av & (zb ^ ((M)0 - bv))));
+        const uint64_t av = g->adj[v];
+        const uint64_t bm = 0ull - ((F >> v) & 1ull);  // the base bit of v, uniform
+        d[b] = g->deg[v] - 2 * (n <= 32 ? __popc(g->adj32[v] & ((uint32_t)zb ^ (uint32_t)bm))
+                                        : __popcll(av & (zb ^ bm)));
 #pragma unroll
         for (int b2 = 0; b2 < RB; ++b2) {
           const uint32_t w = S.pos[B0 + b2];
           if (w != kDummy && ((av >> w) & 1u)) {
             rr[b] |= 1u << b2;
-            if (((zb >> w) & 1u) != bv) df[b] |= 1u << b2;  // register bits of zb are uniform
+            if (((F >> w) & 1u) != (bm & 1u)) df[b] |= 1u << b2;
           }
         }
       }
@@ -393,7 +468,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // the sum over one grouped term list (counts: the six group sizes)
   // (M: the index mask type, 32 bits when n <= 32)
   template <class M>
-  __device__ __forceinline__ void hsum(uint64_t zb64, const int4* tp, const uint16_t (&cnt)[6], int (&hv)[NR]) const {
+  __device__ __forceinline__ void hsum(uint64_t zb64, const int4* tp0, const uint16_t (&cnt)[6], int (&hv)[NR]) const {
+    cptr<int4> tp = cst(tp0);
     const M zb = (M)zb64;
     auto xbit = [&](const int4& tm) -> int { return (int)(((uint32_t)(zb >> tm.x) ^ (uint32_t)(zb >> tm.y)) & 1u); };
     int h0 = 0;
@@ -463,10 +539,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     asm volatile("" : "+v"(zb));
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
-      if (cx.g->h_is_cut)
-        cuts<K>(S, zb, cx.g, hv);
+      if (cst(cx.g)->h_is_cut)
+        cuts<K>(S, zb, F, cx.g, hv);
       else
-        hvals<K>(S, zb, cx.terms, hv, cx.g->n <= 32);
+        hvals<K>(S, zb, cx.terms, hv, cst(cx.g)->n <= 32);
       double e = 0.0, nr = 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -490,7 +566,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
-      cuts<K>(S, zb, cx.g, cv);
+      cuts<K>(S, zb, F, cx.g, cv);
       if constexpr (NS == 2 && LAM) {
         if (ops & OP_GRADG) {
           R gs = R(0);
@@ -571,17 +647,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // amplitudes (>= 256 bytes).  Dummy tile bits (whole state smaller than a tile) have no
   // global position: amplitudes with a dummy bit set are neither loaded (they are zero)
   // nor stored.
-  template <int K> __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const {
-    constexpr int B0 = G::b0(K);
-    const uint32_t t = threadIdx.x;
-    uint64_t toff = 0;
-#pragma unroll
-    for (int i = 0; i < LB; ++i) {
-      const int tb = (i < B0) ? i : i + RB;
-      if (S.pos[tb] != kDummy) toff |= (uint64_t)((t >> i) & 1u) << S.pos[tb];
-    }
-    return toff;
-  }
+  template <int K> __device__ __forceinline__ uint64_t thread_off(const SetSpec& S) const { return tbits<K>(S); }
   template <int K> __device__ __forceinline__ bool is_dummy(const SetSpec& S, int r) const {
     return S.dummy && (tidx<G::b0(K), RB>(threadIdx.x, r) & S.dummy);
   }
@@ -795,6 +861,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                       const Ctx<R>& cx, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
                                       double* zz_lds) {
+    const cptr<SwScale> scp = cst(&sc);  // uniform: scalar loads
     static_assert((KIND & SK_GENERIC) == 0, "generic sweeps take run_rt");
     static_assert(NS == ((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), "state count of the shape");
     static_assert(!((KIND & SK_MAKE_LAM) && (sk_pre(KIND) & OP_ENERGY)), "lambda is made at the mid position");
@@ -807,8 +874,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32, cx.nt);
       if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
         load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32, cx.nt);
-        if (sc.fix_lam) {
-          const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
+        if (scp->fix_lam) {
+          const R fr = (R)scp->lam_fix[0], fi = (R)scp->lam_fix[1];
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const V x = a[NS - 1][r];
@@ -819,11 +886,11 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     constexpr bool LAM0 = NS == 2 && (KIND & SK_LAM_IN) != 0;
     lam_live = LAM0;
-    ops_at<KL, LAM0, sk_pre(KIND)>(pg.pre_ops, false, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    ops_at<KL, LAM0, sk_pre(KIND)>(pg.pre_ops, false, S, tile_base, scp->F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
     bool at_p = false;
     if constexpr ((KIND & SK_MIXA) != 0) {
       R gs = R(0);
-      mix_fwd<RT, LAM0>(S.act, (R)sc.kA, (R)sc.wA, gs, lds_x);
+      mix_fwd<RT, LAM0>(S.act, (R)scp->kA, (R)scp->wA, gs, lds_x);
       if (pg.mixA_grad) acc.ba += (double)gs;
       at_p = true;
     }
@@ -831,12 +898,12 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       xchg<LAST, P, LAM0, half_xchg(RT)>(lds_x);
       at_p = true;
     }
-    ops_at<P, LAM0, sk_mid(KIND)>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, sc.F_mid, cx, ltab_mid,
+    ops_at<P, LAM0, sk_mid(KIND)>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, scp->F_mid, cx, ltab_mid,
                                   acc.gmid, acc, zz_lds);
     constexpr bool LAM1 = LAM0 || (NS == 2 && (KIND & SK_MAKE_LAM) != 0);
     if constexpr ((KIND & SK_MIXB) != 0) {
       R gs = R(0);
-      mix_bwd<RT, LAM1>(S.act, (R)sc.kB, (R)sc.wB, gs, lds_x);
+      mix_bwd<RT, LAM1>(S.act, (R)scp->kB, (R)scp->wB, gs, lds_x);
       if (pg.mixB_grad) acc.bb += (double)gs;
       at_p = false;
     }
@@ -895,10 +962,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     const uint64_t zb = zbase<K>(S, tile_base, F);
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
-      if (cx.g->h_is_cut)
-        cuts<K>(S, zb, cx.g, hv);
+      if (cst(cx.g)->h_is_cut)
+        cuts<K>(S, zb, F, cx.g, hv);
       else
-        hvals<K>(S, zb, cx.terms, hv, cx.g->n <= 32);
+        hvals<K>(S, zb, cx.terms, hv, cst(cx.g)->n <= 32);
       double e = 0.0, nr = 0.0;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -921,10 +988,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
-      if (cx.g->weighted)
-        wcuts<K>(S, zb, cx.terms, cv, cx.g->n <= 32);
+      if (cst(cx.g)->weighted)
+        wcuts<K>(S, zb, cx.terms, cv, cst(cx.g)->n <= 32);
       else
-        cuts<K>(S, zb, cx.g, cv);
+        cuts<K>(S, zb, F, cx.g, cv);
       if (NS == 2 && (ops & OP_GRADG)) {
         R gs = R(0);
 #pragma unroll
@@ -989,6 +1056,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   __device__ __forceinline__ void run_rt(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                       const Ctx<R>& cx, bool io, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
                                       double* zz_lds) {
+    const cptr<SwScale> scp = cst(&sc);  // uniform: scalar loads
     constexpr int KL = LAST;
     const uint64_t tile_base = pdep64(tile, S.fixmask);
     if (pg.flags & F_INIT) {
@@ -1000,8 +1068,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       lam_live = (pg.flags & F_LAM_LIVE) != 0;
       if (NS == 2 && (pg.flags & F_LOAD_LAM)) {
         load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, tile_base + thread_off<KL>(S), S, cx.off32, cx.nt);
-        if (sc.fix_lam) {
-          const R fr = (R)sc.lam_fix[0], fi = (R)sc.lam_fix[1];
+        if (scp->fix_lam) {
+          const R fr = (R)scp->lam_fix[0], fi = (R)scp->lam_fix[1];
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const V x = a[NS - 1][r];
@@ -1011,12 +1079,12 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       }
     }
     const bool make_lam = (pg.flags & F_MAKE_LAM) != 0;
-    ops_at_rt<KL>(pg.pre_ops, make_lam, S, tile_base, sc.F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    ops_at_rt<KL>(pg.pre_ops, make_lam, S, tile_base, scp->F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
     bool at_p = false;
     if (pg.mixA_dir) {
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      mix_fwd_rt<RT>(todo, (R)sc.kA, (R)sc.wA, wcur, pg.mixA_grad != 0, gs, lds_x);
+      mix_fwd_rt<RT>(todo, (R)scp->kA, (R)scp->wA, wcur, pg.mixA_grad != 0, gs, lds_x);
       acc.ba += (double)gs;
       at_p = true;
     }
@@ -1024,11 +1092,11 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       xchg_rt<KL, P>(lds_x);
       at_p = true;
     }
-    ops_at_rt<P>(pg.mid_ops, make_lam, S, tile_base, sc.F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
+    ops_at_rt<P>(pg.mid_ops, make_lam, S, tile_base, scp->F_mid, cx, ltab_mid, acc.gmid, acc, zz_lds);
     if (pg.mixB_dir) {
       R wcur = R(1), gs = R(0);
       uint32_t todo = S.act;
-      mix_bwd_rt<RT>(todo, (R)sc.kB, (R)sc.wB, wcur, pg.mixB_grad != 0, gs, lds_x);
+      mix_bwd_rt<RT>(todo, (R)scp->kB, (R)scp->wB, wcur, pg.mixB_grad != 0, gs, lds_x);
       acc.bb += (double)gs;
       at_p = false;
     }
@@ -1077,7 +1145,7 @@ __device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename
                                          bool conj, const double* rho) {
   if (layer < 0) return;
   const typename Cx<R>::V* src = tab + (size_t)layer * (cmax + 1);
-  const double rr = rho[0], ri = rho[1];
+  const double rr = cst(rho)[0], ri = cst(rho)[1];
   for (int c = threadIdx.x; c <= cmax; c += blockDim.x) {
     const double tr = (double)src[c].x, ti = conj ? -(double)src[c].y : (double)src[c].y;
     ltab[c] = mkv<R>((R)(tr * rr - ti * ri), (R)(tr * ri + ti * rr));
@@ -1085,14 +1153,15 @@ __device__ __forceinline__ void load_tab(typename Cx<R>::V* ltab, const typename
 }
 
 // apply a sweep's scale corrections to the per-thread sums
-__device__ __forceinline__ void scale_acc(Acc& acc, const SweepProg& pg, const SwScale& sc) {
-  const double se = (pg.pre_ops & OP_ENERGY) ? sc.s_pre : sc.s_mid;
+__device__ __forceinline__ void scale_acc(Acc& acc, const SweepProg& pg, const SwScale& sc0) {
+  const cptr<SwScale> sc = cst(&sc0);
+  const double se = (pg.pre_ops & OP_ENERGY) ? sc->s_pre : sc->s_mid;
   acc.e *= se;
   acc.nrm *= se;
-  acc.gpre *= sc.s_pre;
-  acc.gmid *= sc.s_mid;
-  acc.ba *= sc.s_A;
-  acc.bb *= sc.s_B;
+  acc.gpre *= sc->s_pre;
+  acc.gmid *= sc->s_mid;
+  acc.ba *= sc->s_A;
+  acc.bb *= sc->s_B;
 }
 
 // Walk a unit's sweep programs and record, per sweep, the butterfly coefficients and
@@ -1127,7 +1196,8 @@ constexpr bool sweep_half_xchg(int ns, int rt, uint32_t kind) {
   return ns == 1 && rt == ROUTE_HIGH && !(kind & SK_GENERIC);
 }
 constexpr int sweep_waves_per_eu(int ns, int rt, uint32_t kind) {
-  return (kind & SK_GENERIC) ? 1 : sweep_half_xchg(ns, rt, kind) ? 6 : 4;
+  // the per-term shape keeps a term sum per lane and chunk of 64 terms: four waves
+  return (kind & SK_GENERIC) ? 1 : ((sk_mid(kind) & OP_PERTERM) != 0) ? 4 : sweep_half_xchg(ns, rt, kind) ? 6 : 4;
 }
 // partial-sum slots a sweep shape can fill (SLOT_* bits; the generic sweeps: all six)
 constexpr uint32_t sweep_slots(uint32_t kind) {
@@ -1358,9 +1428,9 @@ __global__ __launch_bounds__(1 << (LT - kRegBits)) void k_cuts(const GraphDev* g
   const uint64_t zb = tl.template zbase<KK>(S, tile_base, 0ull);
   int v[G::NR];
   if (use_terms)
-    tl.template hvals<KK>(S, zb, terms, v, g->n <= 32);
+    tl.template hvals<KK>(S, zb, terms, v, cst(g)->n <= 32);
   else
-    tl.template cuts<KK>(S, zb, g, v);
+    tl.template cuts<KK>(S, zb, 0ull, g, v);
   const uint32_t t = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < G::NR; ++r) {

@@ -239,6 +239,7 @@ GraphDev make_graph(const aaq_problem* pr) {
     g.deg[u]++;
     g.deg[v]++;
   }
+  for (int v = 0; v < kAdjPad; ++v) g.adj32[v] = (uint32_t)g.adj[v];
   return g;
 }
 
@@ -327,6 +328,32 @@ void finish_set(SetSpec& s, int L, bool first) {
     for (int b = 0; b < kRegBits; ++b)
       if (((r >> b) & 1) && s.pos[b0 + b] != kDummy) o |= 1ull << s.pos[b0 + b];
     s.roff[r] = o;
+  }
+  // runs of thread bits at the load and phase arrangements (see SetSpec::trun)
+  const int na = geo_na(L), lb = L - kRegBits;
+  s.tr64 = 0;
+  for (int ki = 0; ki < 2; ++ki) {
+    const int bk = geo_b0(ki == 0 ? na - 1 : na - 2, L);
+    int nr = 0, rs[16], rw[16], rd[16];
+    for (int i = 0; i < lb; ++i) {
+      const int tb = i < bk ? i : i + kRegBits;
+      const int d = s.pos[tb];
+      if (d == kDummy) continue;
+      if (nr > 0 && rs[nr - 1] + rw[nr - 1] == i && rd[nr - 1] + rw[nr - 1] == d) {
+        rw[nr - 1]++;
+      } else {
+        rs[nr] = i;
+        rw[nr] = 1;
+        rd[nr] = d;
+        ++nr;
+      }
+      if (d >= 32) s.tr64 = 1;
+    }
+    // every set the planner builds holds its active qubits as one run of global bits
+    // next to at most the five lowest bits, which gives at most three runs
+    if (nr > kMaxRuns) std::abort();
+    for (int i = 0; i < kMaxRuns; ++i)
+      s.trun[ki][i] = i < nr ? (uint32_t)rs[i] | ((uint32_t)rw[i] << 8) | ((uint32_t)rd[i] << 16) : 0u;
   }
 }
 

@@ -117,7 +117,16 @@ struct SetSpec {
   uint16_t pad2[3];
   uint64_t tmax;
   uint64_t mfull;
+  // The thread bits of the load (index 0) and phase (index 1) arrangements scattered to
+  // their global bits, as at most kMaxRuns runs of consecutive thread bits that land on
+  // consecutive global bits (tile positions ascend, so a set has two or three): run i is
+  // packed as (first thread bit) | (width << 8) | (first global bit << 16); unused runs
+  // are 0 (width 0 contributes nothing).  tr64: some run reaches bit 32 or above.
+  uint32_t trun[2][4];
+  uint32_t tr64;
+  uint32_t pad3;
 };
+constexpr int kMaxRuns = 4;
 
 struct SweepProg {
   int8_t set;
@@ -172,14 +181,16 @@ struct SwScale {
   uint32_t fix_lam, pad;  // nonzero when lam_fix != 1
 };
 
-// graph block in device memory (uniform, read with scalar loads)
+// graph block in device memory (uniform and read-only for the kernels that read it:
+// scalar loads through the constant address space)
+constexpr int kAdjPad = (kMaxN + 3) / 4 * 4;  // masks padded with zeros to a multiple of 4
 struct GraphDev {
   int32_t n, m, T, cmax;   // cmax = |E| = last phase-table index
   int32_t h_is_cut;        // the observable is H_C: h(z) = C(z), computed from the adjacency masks
   int32_t weighted;        // integer edge weights: C(z) comes from the sets' cost-term lists
-  uint64_t adj[kMaxN];     // adjacency bitmasks
-  int32_t deg[kMaxN];
-  int32_t pad[2];
+  uint64_t adj[kAdjPad];   // adjacency bitmasks
+  uint32_t adj32[kAdjPad]; // their low 32 bits (all of them when n <= 32)
+  int32_t deg[kAdjPad];
 };
 
 // one batched unit (instance x parameter point)

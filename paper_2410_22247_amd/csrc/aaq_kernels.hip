@@ -123,12 +123,25 @@ __device__ void build_scales(ScaleStage& S, int nsweep, SwScale* out) {
       si = mpi[pg.ld_buf];
       F = mF[pg.ld_buf];
     }
-    if (pg.flags & F_LOAD_LAM) {  // lambda <- lambda * sigma_psi / sigma_lam
+    // lambda's scale relative to psi's: rho = sigma_psi / sigma_lam.  Both states take the
+    // same gates, and a mixer and its inverse have factors whose product is real and
+    // positive (cos^2 or sin^2 of beta), so rho is real and positive; it only drifts in
+    // magnitude.  While it stays within 2^+-24 lambda is left as loaded and rho is folded
+    // into the sweep's gradient scale factors (its sums carry conj(sigma_lam) sigma_psi =
+    // |sigma_psi|^2 / rho; such sweeps have no energy step); otherwise (or if rho were not
+    // real) lambda is multiplied by rho on load.
+    double gs = 1.0;
+    if (pg.flags & F_LOAD_LAM) {
       const double d = mlr * mlr + mli * mli;
       const double fr = (sr * mlr + si * mli) / d, fi = (si * mlr - sr * mli) / d;
-      r.lam_fix[0] = fr;
-      r.lam_fix[1] = fi;
-      r.fix_lam = (fr != 1.0 || fi != 0.0) ? 1u : 0u;
+      const bool real = fabs(fi) <= 1e-12 * fabs(fr);
+      if (real && fr > 0x1p-24 && fr < 0x1p24 && !((pg.pre_ops | pg.mid_ops) & OP_ENERGY)) {
+        gs = fr;
+      } else {
+        r.lam_fix[0] = fr;
+        r.lam_fix[1] = fi;
+        r.fix_lam = 1u;
+      }
     }
     const uint64_t gact = S.gact[pg.set];
     r.F_pre = F;
@@ -137,14 +150,20 @@ __device__ void build_scales(ScaleStage& S, int nsweep, SwScale* out) {
     r.F_mid = F;
     position(pg.mid_ops, r.rho_mid, r.s_mid);
     mixer(S.mix[2 * i + 1], pg.mixB_dir, gact, r.kB, r.wB, r.s_B);
+    if (gs != 1.0) {  // lambda loaded with scale sigma_psi / gs (no energy step here)
+      r.s_pre *= gs;
+      r.s_mid *= gs;
+      r.s_A *= gs;
+      r.s_B *= gs;
+    }
     if (pg.flags & F_STORE_PSI) {
       mpr[pg.st_buf] = sr;
       mpi[pg.st_buf] = si;
       mF[pg.st_buf] = F;
     }
     if (pg.flags & F_STORE_LAM) {
-      mlr = sr;
-      mli = si;
+      mlr = sr / gs;
+      mli = si / gs;
     }
     out[i] = r;
   }
