@@ -67,6 +67,17 @@ def kernel_class(name: str):
     return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def write_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 512 << 20):
     """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch) of `bench.py --copy-calibration`: each counter is scaled by the ratio of the
@@ -104,7 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time for the oracle sample")
+    ap.add_argument("--cpu-runs", type=int, default=5, help="timed oracle evaluations (median reported)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run 3 plain 512 MiB device copies (reference for HBM byte counters)")
     ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5a", "c5b", "lc", "sample", "weighted", "adam"],
@@ -254,16 +265,20 @@ def main():
     # ---------------------------------------------------------------- H_red vs H_C
     if not args.no_extras:
         ext = {}
-        reps = 10
 
-        def rate(fn):
+        def rate(fn, reps=10, blocks=5):
+            """Calls per second: the median over `blocks` timed blocks of `reps` calls, after
+            one untimed call."""
             fn()
             torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(reps):
-                fn()
-            torch.cuda.synchronize()
-            return reps / (time.perf_counter() - t)
+            rates = []
+            for _ in range(blocks):
+                t = time.perf_counter()
+                for _ in range(reps):
+                    fn()
+                torch.cuda.synchronize()
+                rates.append(reps / (time.perf_counter() - t))
+            return float(np.median(rates))
 
         g0, b0 = gams[0], bets[0]
         ests = {agg: A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=False, agg=agg)
@@ -316,23 +331,31 @@ def main():
         import oracle as O
 
         terms = wp.terms(1)
-        n_done = 0
-        t = time.perf_counter()
-        while True:
-            O.energy_grad(wp.n, wp.edges(), terms, gams[n_done % 32], bets[n_done % 32])
-            n_done += 1
-            el = time.perf_counter() - t
-            if el >= args.cpu_seconds or el / n_done * (n_done + 1) > 2.5 * args.cpu_seconds:
-                break
+        runs = max(1, args.cpu_runs)
+        O.energy_grad(wp.n, wp.edges(), terms, gams[0], bets[0])  # warm-up (page-in, thread start)
+        ts = []
+        for k in range(runs):
+            t = time.perf_counter()
+            O.energy_grad(wp.n, wp.edges(), terms, gams[(k + 1) % 32], bets[(k + 1) % 32])
+            ts.append(time.perf_counter() - t)
+        med = float(np.median(ts))
         out["cpu_baseline"] = {
-            "value": round(n_done / el, 4),
+            "value": round(1.0 / med, 4),
             "unit": "evals/s",
             "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"{n_done} full-state FP64 energy + adjoint-gradient evaluation(s) of the same workload "
-                      f"(n=26, p=4, H_red), first {n_done} of the 32 points, {el:.1f} s",
+            "sample": f"median of {runs} timed full-state FP64 energy + adjoint-gradient evaluations of the same "
+                      f"workload (n=26, p=4, H_red) at points 2..{runs + 1} of the 32, after one untimed evaluation; "
+                      f"{sum(ts):.1f} s timed",
+            "runs": runs,
+            "median_s": round(med, 3),
+            "min_s": round(min(ts), 3),
+            "max_s": round(max(ts), 3),
+            "threads": O.num_threads(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": cpu_model(),
         }
-        out["gpu_over_cpu"] = round(value / (n_done / el), 1)
+        out["gpu_over_cpu"] = round(value * med, 1)
 
     out["kernel_sha"] = kernel_hash()
     print(json.dumps(out), flush=True)

@@ -218,7 +218,11 @@ aaq_status aaq_autotune(const aaq_problem *prob, int p, int with_grad, aaq_obser
  * a device work counter (largest n first) and runs its whole forward (and backward)
  * sweep sequence in registers, one launch per tile size.  Larger units are grouped by
  * tile size and tile-set count, and each sweep step is one launch over every tile of
- * every unit of the group.  Replays are captured once in a HIP graph.
+ * every unit of the group; the persistent small-unit launches run concurrently with
+ * that chain (a second stream, a fork and a join in the captured graph).  With
+ * single_launch every unit runs in the persistent kernel (a large unit is swept tile by
+ * tile by the one workgroup that takes it), so the whole batch is one launch after the
+ * phase tables.  Replays are captured once in a HIP graph.
  *   probs[count]  the instance of every unit (the same instance may repeat)
  *   d_params      device double[count][2p]: gamma_0..gamma_{p-1}, beta_0..beta_{p-1}
  *   d_out         device double[count][2 + 2p]: energy, norm, dE/dgamma[p], dE/dbeta[p]
@@ -234,6 +238,8 @@ typedef struct {
                               with n > 13; 0 = fewest sweeps, then 12 (default) */
   int min_tile_bits_small; /* units with n <= 13 run on the smallest compiled tile (10, 12 or 13
                               amplitude bits) that is >= max(n, this); 0 = 10 (default) */
+  int single_launch;       /* 1 = every unit in the persistent kernel (one launch per tile size);
+                              0 = units with n > 13 as batched sweep steps (default) */
 } aaq_plan_opts;
 
 /* Fills opts with the defaults above. */
@@ -256,9 +262,10 @@ aaq_status aaq_plan_execute(aaq_plan *plan, const double *d_params, double *d_ou
 void aaq_plan_destroy(aaq_plan *plan);
 
 /* Plan autotuner: builds the plan with every candidate of tile_bits_large (12, 13; when
- * some unit has n > 13), min_tile_bits_small (10, 12, 13; when some unit has n <= 12)
- * and workgroups (automatic, one and four per compute unit; when some unit has
- * n <= 13) on top of `base` (NULL = defaults), times `reps` executions of each with HIP
+ * some unit has n > 13), min_tile_bits_small (10, 12, 13; when some unit has n <= 12),
+ * workgroups (automatic, one and four per compute unit; when some unit has n <= 13) and
+ * single_launch (0, 1; when some unit has n > 13) on top of `base` (NULL = defaults),
+ * times `reps` executions of each with HIP
  * events on `stream` (after one warm-up execution) and returns the fastest options in
  * *best and their time per execution in *best_ms (may be NULL).  Candidates whose
  * workspace exceeds ws_bytes are skipped.  d_params / d_out as for aaq_plan_execute;

@@ -38,6 +38,7 @@ class CPlanOpts(ctypes.Structure):
         ("prec", ctypes.c_int),
         ("tile_bits_large", ctypes.c_int),
         ("min_tile_bits_small", ctypes.c_int),
+        ("single_launch", ctypes.c_int),
     ]
 
 

@@ -1416,6 +1416,67 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
   (void)p;
 }
 
+// The same batched sweep step compiled for its sweep shape KIND (every unit of a group runs
+// the same program, so the step's shape is uniform over the launch): the specialised tile
+// engine of the single-instance sweeps, with 32-bit buffer offsets within each unit's
+// state.  The unit's descriptor, set and program are read through the constant address
+// space (uploaded by the host, never written by a kernel).
+template <class R, int RT, int LT, uint32_t KIND>
+__global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KIND) void k_bsweep_k(BatchArgs<R> A) {
+  constexpr int NS = (KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1;
+  constexpr bool EN = ((sk_pre(KIND) | sk_mid(KIND)) & OP_ENERGY) != 0;
+  using G = Geo<R, LT>;
+  using V = typename G::V;
+  __shared__ V lds_x[lds_slot(sweep_half_xchg(NS, RT, KIND) ? G::TILE / 2 : G::TILE)];
+  __shared__ double red[(G::NT / 64) * 6];
+  extern __shared__ unsigned char dyn_lds[];
+  const int u = __builtin_amdgcn_readfirstlane(cst(A.list)[blockIdx.y]);
+  const cptr<UnitDesc> D = cst(A.units + u);
+  const uint32_t tile = blockIdx.x;
+  if (tile >= (uint32_t)D->ntiles || A.step >= D->nsweep) return;
+  V* ltab0 = reinterpret_cast<V*>(dyn_lds);
+  V* ltab1 = ltab0 + A.tabmax;
+  const GraphDev* g = reinterpret_cast<const GraphDev*>(A.ws + D->graph_off);
+  const int4* terms = reinterpret_cast<const int4*>(A.ws + D->terms_off);
+  const V* tab = reinterpret_cast<const V*>(A.ws + D->tab_off);
+  const size_t amp = sizeof(V);
+  const SwScale& sc = reinterpret_cast<const SwScale*>(A.ws + D->tab_off + amp * (size_t)D->p * (D->cmax + 1))[A.step];
+  const SweepProg pg = cst(A.progs)[D->prog_off + A.step];
+  const SetSpec S = D->sets[pg.set];
+  if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+  if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+    load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  __syncthreads();
+  V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
+  const uint64_t N = (uint64_t)1 << D->n;
+  Ctx<R> cx{g, terms, tab, psi, NS == 2 ? psi + N : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax, N,
+            N <= ((uint64_t)1 << 32) / sizeof(V), false, (R)(0.5 * D->cmax)};
+  Tile<R, NS, EN, LT> tl;
+  Acc acc;
+  acc.zero();
+  tl.template run<RT, KIND>(pg, S, sc, tile, cx, lds_x, ltab0, ltab1, acc, nullptr);
+  scale_acc(acc, pg, sc);
+  constexpr uint32_t SLOTS = sweep_slots(KIND);
+  constexpr int NV = __builtin_popcount(SLOTS);
+  double* part = reinterpret_cast<double*>(A.ws + D->part_off) + (size_t)A.step * 6 * D->ntiles;
+  if constexpr (NV > 0) {
+    const double all[6] = {acc.e, acc.nrm, acc.gpre, acc.gmid, acc.ba, acc.bb};
+    double v[NV];
+#pragma unroll
+    for (int i = 0, k = 0; i < 6; ++i)
+      if ((SLOTS >> i) & 1u) v[k++] = all[i];
+    block_sum<NV, G::NT>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0, k = 0; i < 6; ++i) part[(size_t)i * D->ntiles + tile] = ((SLOTS >> i) & 1u) ? v[k++] : 0.0;
+    }
+  } else if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) part[(size_t)i * D->ntiles + tile] = 0.0;
+  }
+}
+
 // per-unit fixed-order sums of the batched sweeps' partials into d_out rows
 
 template <class R, int K, int LT>
@@ -1543,10 +1604,31 @@ static void bsweep_launch_t(const BatchArgs<R>& A, int route, dim3 grid, size_t 
     launch((k_bsweep<R, NS, EN, ROUTE_FULL, LT>), grid, dim3(Geo<R, LT>::NT), dyn, st, A);
 }
 
+template <class R, int RT, int LT>
+static bool bsweep_launch_kind(const BatchArgs<R>& A, uint32_t kind, dim3 grid, size_t dyn, hipStream_t st) {
+  const dim3 blk(Geo<R, LT>::NT);
+  switch (kind) {
+    case SK_F_FIRST: launch((k_bsweep_k<R, RT, LT, SK_F_FIRST>), grid, blk, dyn, st, A); return true;
+    case SK_F_PLAIN: launch((k_bsweep_k<R, RT, LT, SK_F_PLAIN>), grid, blk, dyn, st, A); return true;
+    case SK_F_BOUNDARY: launch((k_bsweep_k<R, RT, LT, SK_F_BOUNDARY>), grid, blk, dyn, st, A); return true;
+    case SK_F_ENERGY: launch((k_bsweep_k<R, RT, LT, SK_F_ENERGY>), grid, blk, dyn, st, A); return true;
+    case SK_TURNAROUND: launch((k_bsweep_k<R, RT, LT, SK_TURNAROUND>), grid, blk, dyn, st, A); return true;
+    case SK_B_PLAIN: launch((k_bsweep_k<R, RT, LT, SK_B_PLAIN>), grid, blk, dyn, st, A); return true;
+    case SK_B_BOUNDARY: launch((k_bsweep_k<R, RT, LT, SK_B_BOUNDARY>), grid, blk, dyn, st, A); return true;
+    case SK_B_LAST: launch((k_bsweep_k<R, RT, LT, SK_B_LAST>), grid, blk, dyn, st, A); return true;
+    default: return false;
+  }
+}
+
 template <class R, int LT> hipError_t bsweep_launch_impl(const LaunchBatch& L, hipStream_t st) {
   const dim3 grid(L.max_tiles, L.nlist);
   BatchArgs<R> A{L.units, L.progs, L.list, L.ws, L.step, L.tabmax};
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)L.tabmax;
+  if (L.kind != SK_GENERIC) {
+    const bool done = L.route == ROUTE_HIGH ? bsweep_launch_kind<R, ROUTE_HIGH, LT>(A, L.kind, grid, dyn, st)
+                                            : bsweep_launch_kind<R, ROUTE_FULL, LT>(A, L.kind, grid, dyn, st);
+    if (done) return hipGetLastError();
+  }
   if (L.two_states)
     (L.energy ? bsweep_launch_t<R, 2, true, LT> : bsweep_launch_t<R, 2, false, LT>)(A, L.route, grid, dyn, st);
   else

@@ -662,8 +662,15 @@ std::atomic<bool> g_half_state{true};
 
 bool half_state_ok(const Single& S, aaq_aggregation agg, bool keep_state) {
   if (!g_half_state || S.k < 2 || agg == AAQ_AGG_PASS_PER_TERM || keep_state) return false;
-  // every byte offset of the full index range within 32 bits (the mirrored offsets)
-  if ((((uint64_t)1 << S.n) * (S.dbl ? 16u : 8u)) > ((uint64_t)1 << 32)) return false;
+  // The sweeps address a stored state with 32-bit buffer offsets when its 2^(n-1)
+  // amplitudes span at most 4 GiB; the mirrored offsets of that path are formed over the
+  // full index range, so it needs 2^n amplitudes within 4 GiB.  Larger states take 64-bit
+  // addresses, mirrored offsets included.  Only the size in between (2^n amplitudes above
+  // 4 GiB, their half within it: n = 30 in complex64) keeps the full state.
+  const uint64_t amp = S.dbl ? 16u : 8u;
+  const bool full32 = (((uint64_t)1 << S.n) * amp) <= ((uint64_t)1 << 32);
+  const bool half64 = (((uint64_t)1 << (S.n - 1)) * amp) > ((uint64_t)1 << 32);
+  if (!full32 && !half64) return false;
   const SetSpec& last = S.sets.back();
   const int b0l = geo_b0(geo_na(S.L) - 1, S.L);
   if (last.pos[S.L - 1] != S.n - 1 || b0l + kRegBits != S.L) return false;
@@ -1077,8 +1084,12 @@ struct aaq_plan {
     int nlist, max_tiles, nsweep;
     std::vector<SweepProg> progs;  // the group's common program (for launch shapes)
     std::vector<uint8_t> routes;   // route of the set of each step
+    bool weighted = false;         // some unit has edge weights (run-time sweep path)
   };
   std::vector<Group> groups;
+  // the small-unit launches run on `aux`, forked from and joined to the caller's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // captured graph
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1120,6 +1131,7 @@ aaq_status check_opts(const aaq_plan_opts& o) {
   if (o.min_tile_bits_small < 0 || o.min_tile_bits_small > kMaxUnitTile)
     return fail(AAQ_ERR_INVALID_ARG, "min_tile_bits_small must be in 0..13");
   if (o.workgroups < 0) return fail(AAQ_ERR_INVALID_ARG, "workgroups must be >= 0");
+  if (o.single_launch != 0 && o.single_launch != 1) return fail(AAQ_ERR_INVALID_ARG, "single_launch must be 0 or 1");
   return AAQ_OK;
 }
 
@@ -1231,7 +1243,10 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
       D.ntiles = (int32_t)(1u << (D.n - D.L));
       D.part_off = (int64_t)off;
       off = align_up(off + sizeof(double) * 6 * (size_t)D.nsweep * D.ntiles);
-      by_group[std::make_pair((int)D.L, D.nsets)].push_back(i);
+      if (o.single_launch)  // swept tile by tile by one workgroup of the persistent kernel
+        by_small[D.L].push_back(i);
+      else
+        by_group[std::make_pair((int)D.L, D.nsets)].push_back(i);
     } else {
       D.state_off = -1;
       D.ntiles = 1;
@@ -1273,15 +1288,24 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));  // every unit; also resets the counters
     tl.done();
   }
+  // the persistent small-unit kernels and the chain of batched sweep steps touch disjoint
+  // units: with both present, the small units run on the auxiliary stream, concurrently
+  const bool fork = !P->small.empty() && !P->groups.empty() && P->aux;
+  hipStream_t su = fork ? P->aux : hs;
+  if (fork) {
+    HIPCHK(hipEventRecord(P->ev_fork, hs));
+    HIPCHK(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+  }
   for (const auto& sc : P->small) {
     LaunchUnits V = U;
     V.order = (const int32_t*)(P->ws + sc.order_off);
     V.counter = (int32_t*)(P->ws + P->counter_off) + sc.counter;
     V.count = sc.count;
-    TimedLaunch tl(KC_UNITS, 0.0, hs);
-    HIPCHK(launch_units(V, P->grad, P->dbl, sc.L, sc.blocks, hs));
+    TimedLaunch tl(KC_UNITS, 0.0, su);
+    HIPCHK(launch_units(V, P->grad, P->dbl, sc.L, sc.blocks, su));
     tl.done();
   }
+  if (fork) HIPCHK(hipEventRecord(P->ev_join, P->aux));
   for (const auto& Gp : P->groups) {
     LaunchBatch B;
     B.units = U.units;
@@ -1297,6 +1321,8 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
       B.route = Gp.routes[s];
       B.two_states = P->grad && needs_two_states(pg);
       B.energy = ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) != 0;
+      // the specialised shapes for unweighted groups (weighted costs take the run-time path)
+      B.kind = Gp.weighted ? SK_GENERIC : sweep_kind(pg);
       TimedLaunch tl(B.two_states ? KC_SWEEP2 : KC_SWEEP1, 0.0, hs);
       HIPCHK(launch_bsweep(B, P->dbl, Gp.L, hs));
       tl.done();
@@ -1305,6 +1331,7 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     HIPCHK(launch_bsweep_out(B, d_out, 2 + 2 * P->p, P->grad, P->dbl, hs));
     tl.done();
   }
+  if (fork) HIPCHK(hipStreamWaitEvent(hs, P->ev_join, 0));
   return AAQ_OK;
 }
 
@@ -1577,6 +1604,7 @@ void aaq_plan_default_opts(aaq_plan_opts* o) {
   o->prec = AAQ_PREC_C64;
   o->tile_bits_large = 0;
   o->min_tile_bits_small = 0;
+  o->single_launch = 0;
 }
 
 aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
@@ -1648,6 +1676,7 @@ aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_obse
       Gp.nsweep = D0.nsweep;
       Gp.progs.assign(PL.progs_v.begin() + D0.prog_off, PL.progs_v.begin() + D0.prog_off + D0.nsweep);
       for (const SweepProg& pg : Gp.progs) Gp.routes.push_back(D0.sets[pg.set].route);
+      for (int u : units) Gp.weighted = Gp.weighted || is_weighted(&probs[u]);
       P->groups.push_back(Gp);
     }
   }
@@ -1669,6 +1698,15 @@ aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_obse
   P->progs_off = PL.progs;
   P->counter_off = PL.counter;
   for (int i = 0; i < count; ++i) P->tabmax = std::max(P->tabmax, PL.ud[i].cmax + 1);
+  if (!P->small.empty() && !P->groups.empty()) {  // fork / join of the small-unit launches
+    e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      aaq_plan_destroy(P);
+      return fail(AAQ_ERR_HIP, std::string("plan stream / events: ") + hipGetErrorString(e));
+    }
+  }
   *out = P;
   return AAQ_OK;
 }
@@ -2009,6 +2047,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   std::vector<int> larges = any_large ? std::vector<int>{12, 13} : std::vector<int>{b0.tile_bits_large};
   std::vector<int> smalls = any_tiny ? std::vector<int>{10, 12, 13} : std::vector<int>{b0.min_tile_bits_small};
   std::vector<int> wgs = any_small ? std::vector<int>{0, device_cus(), 4 * device_cus()} : std::vector<int>{b0.workgroups};
+  std::vector<int> singles = any_large ? std::vector<int>{0, 1} : std::vector<int>{b0.single_launch};
   hipStream_t hs = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -2020,6 +2059,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   aaq_status st = AAQ_OK;
   double bms = -1.0;
   aaq_plan_opts bo = b0;
+  for (int sl : singles)
   for (int tl : larges)
     for (int ts : smalls)
       for (int wg : wgs) {
@@ -2027,6 +2067,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
         o.tile_bits_large = tl;
         o.min_tile_bits_small = ts;
         o.workgroups = wg;
+        o.single_launch = sl;
         size_t need = 0;
         if ((st = aaq_plan_workspace_size(probs, count, p, obs, with_grad, &o, &need))) goto done;
         if (need > ws_bytes) continue;  // this candidate does not fit the caller's workspace
@@ -2116,6 +2157,12 @@ void aaq_plan_destroy(aaq_plan* P) {
   if (!P) return;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->aux) {
+    (void)hipStreamSynchronize(P->aux);
+    (void)hipStreamDestroy(P->aux);
+  }
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   delete P;
 }
 

@@ -85,6 +85,7 @@ struct LaunchBatch {
   unsigned char* ws;
   int nlist, max_tiles, step, tabmax, route;
   bool two_states, energy;
+  uint32_t kind;  // the step's sweep shape (SK_*; SK_GENERIC: the run-time-flag engine)
 };
 
 // Tile sizes (log2 amplitudes per workgroup tile) with compiled kernels: sweeps and

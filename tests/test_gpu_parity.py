@@ -132,6 +132,27 @@ def test_per_term_aggregation(agg, g, p):
         assert np.ptp(zz[orb]) <= 2e-6
 
 
+def test_per_term_reduction_is_bitwise_deterministic():
+    """Per-term <ZZ> sums are added in a fixed order (waves in turn, then tiles in order):
+    repeated calls give identical bits, for both observables and tile sizes."""
+    g = G.prufer_tree(20, 5)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    gam, bet = np.array([0.9, 2.3]), np.array([0.4, 1.2])
+    for obs in (OBS_HC, OBS_HRED):
+        for tile in (12, 13):
+            A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, False, tile)
+            try:
+                est = A.Estimator(pr, 2, obs, A.AAQ_PREC_C64, grad=False, agg=A.AAQ_AGG_PER_TERM)
+                runs = [est.energy(gam, bet) for _ in range(3)]
+            finally:
+                A.aaq_set_tile_bits(g.n, A.AAQ_PREC_C64, False, 0)
+            for e, zz, nrm in runs[1:]:
+                assert e == runs[0][0] and nrm == runs[0][2] and np.array_equal(zz, runs[0][1])
+            zz_ref = O.energy(g.n, g.edge_array(), wp.terms(obs), gam, bet, full=True)[2]
+            assert np.max(np.abs(runs[0][1] - zz_ref)) <= 1e-5
+
+
 # ------------------------------------------------------------------ gradients
 GRAD_CASES = [
     (G.Graph(2, [(0, 1)]), 1), (G.binary_tree(6), 2), (rand_graph(9, 0.5, 2), 3), (G.complete(10), 2),
@@ -403,8 +424,11 @@ def test_plan_groups_of_tile_sets(obs, grad):
     plan.close()
 
 
-@pytest.mark.parametrize("tl,ts,wg", [(12, 10, 0), (13, 13, 0), (12, 12, 7), (13, 10, 1)])
-def test_plan_tile_options_match_oracle(tl, ts, wg):
+@pytest.mark.parametrize("tl,ts,wg,sl", [(12, 10, 0, 0), (13, 13, 0, 0), (12, 12, 7, 0), (13, 10, 1, 0), (12, 10, 0, 1),
+                                         (13, 12, 3, 1)])
+def test_plan_tile_options_match_oracle(tl, ts, wg, sl):
+    """Tile sizes, workgroup counts and the single-launch mode (units with n > 13 swept tile
+    by tile inside the persistent kernel) against the oracle, with graph replays."""
     graphs = [G.prufer_tree(9, 1), G.star(11), G.complete(12), G.binary_tree(13), G.prufer_tree(16, 2),
               G.random_regular(3, 20, seed=5)]
     wps = [make_problem(g) for g in graphs]
@@ -413,14 +437,16 @@ def test_plan_tile_options_match_oracle(tl, ts, wg):
     rng = np.random.default_rng(tl * 100 + ts + wg)
     gam = rng.uniform(0, math.pi, (len(units), p))
     bet = rng.uniform(0, math.pi / 2, (len(units), p))
-    plan = A.Plan(units, p, OBS_HRED, with_grad=True, tile_bits_large=tl, min_tile_bits_small=ts, workgroups=wg)
+    plan = A.Plan(units, p, OBS_HRED, with_grad=True, tile_bits_large=tl, min_tile_bits_small=ts, workgroups=wg,
+                  single_launch=bool(sl))
     plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
-    out = plan.execute().cpu().numpy()
-    for u in range(len(units)):
-        w = wps[u % len(wps)]
-        e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
-        check_energy(out[u, 0], e_ref)
-        check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
+    for rep in range(2):
+        out = plan.execute().cpu().numpy()
+        for u in range(len(units)):
+            w = wps[u % len(wps)]
+            e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+            check_energy(out[u, 0], e_ref)
+            check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
     plan.close()
 
 

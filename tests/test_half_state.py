@@ -134,3 +134,38 @@ def test_n26_energy_both_state_modes():
     assert abs(h[0] - f[0]) <= 2e-6 * abs(e_ref)
     del est
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,p,prec", [(30, 1, A.AAQ_PREC_C64), (31, 1, A.AAQ_PREC_C64), (29, 1, A.AAQ_PREC_C128)],
+                         ids=["c64-n30-full", "c64-n31-64bit", "c128-n29-full"])
+def test_half_state_with_64bit_addresses(n, p, prec):
+    """States whose stored half exceeds 4 GiB (n = 31 in complex64) take 64-bit addresses
+    with the mirrored registers; n = 30 (complex64) and n = 29 (complex128), whose full
+    index range exceeds 4 GiB but whose half does not, keep the full state.  Energy and
+    gradient with the switch on and off, against each other and the light-cone FP64
+    adjoint."""
+    import torch
+    from oracle import reduced as Rd
+
+    g = G.prufer_tree(n, 7)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    gam, bet = np.array([0.83]), np.array([0.37])
+    e_lc, dg_lc, db_lc, _ = Rd.light_cone_energy_grad(n, wp.edges(), wp.terms(OBS_HRED), gam, bet)
+    tol = 1e-5 if prec == A.AAQ_PREC_C64 else 1e-10
+
+    def run():
+        est = A.Estimator(pr, p, OBS_HRED, prec, grad=True)
+        r = est.energy_grad(gam, bet)
+        del est
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return r
+
+    h, f = both(run)
+    for e, dg, db, nrm in (h, f):
+        assert abs(e - e_lc) <= tol * abs(e_lc)
+        gr, gv = np.concatenate([dg_lc, db_lc]), np.concatenate([dg, db])
+        assert np.linalg.norm(gv - gr) <= tol * np.linalg.norm(gr)
+        assert abs(nrm - 1) <= (1e-5 if prec == A.AAQ_PREC_C64 else 1e-12)

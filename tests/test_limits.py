@@ -47,7 +47,7 @@ def test_limit_errors():
 # ------------------------------------------------------------------ GPU
 @pytest.mark.gpu
 @pytest.mark.parametrize("g", [G.binary_tree(9), G.prufer_tree(14, 2)], ids=lambda g: g.name)
-def test_depth_64(g):
+def test_depth_64(g, record_property):
     """p = 64: 64 phase tables, 64 layers of sweeps forward and back."""
     wp = make_problem(g)
     pr = A.Problem.from_workload(wp)
@@ -59,6 +59,8 @@ def test_depth_64(g):
             est = A.Estimator(pr, 64, obs, prec, grad=True)
             e, dg, db, nrm = est.energy_grad(gam, bet)
             check(e, dg, db, e_ref, dg_ref, db_ref, tol)
+            if prec == A.AAQ_PREC_C64:
+                record_property(f"c64_norm_err_obs{obs}", abs(nrm - 1))
             assert abs(nrm - 1) <= (1e-12 if prec == A.AAQ_PREC_C128 else 1e-5)
 
 
