@@ -58,7 +58,10 @@ typedef enum {
   AAQ_ERR_HIP = 7          /* a HIP runtime call failed                        */
 } aaq_status;
 
-typedef enum { AAQ_OBS_HC = 0, AAQ_OBS_HRED = 1 } aaq_observable;
+/* The selector arguments below are plain 32-bit integers with named values, so any value
+ * a caller passes is well defined and is checked (AAQ_ERR_INVALID_ARG when unknown). */
+typedef int32_t aaq_observable;
+enum { AAQ_OBS_HC = 0, AAQ_OBS_HRED = 1 };
 
 /* How the expectation is aggregated (estimator cost section):
  *   FUSED          -- one integer h(z) per amplitude, one pass (default);
@@ -67,9 +70,11 @@ typedef enum { AAQ_OBS_HC = 0, AAQ_OBS_HRED = 1 } aaq_observable;
  *   PASS_PER_TERM  -- the final state is written and every term's <Z_i Z_j> is a
  *                     separate O(2^n) pass over it (the per-term estimator structure
  *                     the paper describes; its cost grows with the number of terms). */
-typedef enum { AAQ_AGG_FUSED = 0, AAQ_AGG_PER_TERM = 1, AAQ_AGG_PASS_PER_TERM = 2 } aaq_aggregation;
+typedef int32_t aaq_aggregation;
+enum { AAQ_AGG_FUSED = 0, AAQ_AGG_PER_TERM = 1, AAQ_AGG_PASS_PER_TERM = 2 };
 
-typedef enum { AAQ_PREC_C64 = 0, AAQ_PREC_C128 = 1 } aaq_precision;
+typedef int32_t aaq_precision;
+enum { AAQ_PREC_C64 = 0, AAQ_PREC_C128 = 1 };
 
 /* A MaxCut instance with its Aut(G) edge orbits (Algorithm 1 output).
  *   n           qubits = vertices, 1 <= n <= 34

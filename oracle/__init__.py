@@ -26,12 +26,14 @@ _LIB = None
 
 
 def lib():
-    """Load liboracle.so, building it with gcc if it is not there yet."""
+    """Load liboracle.so, building it with gcc if it is not there yet (ORACLE_LIB names
+    another build of the same source, e.g. a sanitizer build from ``oracle/build.py``)."""
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_build.LIB):
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         dptr = ctypes.POINTER(ctypes.c_double)

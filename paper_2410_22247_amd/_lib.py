@@ -3,7 +3,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libaaqaoa.so")
+# AAQAOA_LIB names another build of the same sources (the host-sanitizer build of build.py)
+LIB_PATH = os.environ.get("AAQAOA_LIB") or os.path.join(HERE, "libaaqaoa.so")
 
 _lib = None
 

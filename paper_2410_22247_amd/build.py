@@ -33,14 +33,26 @@ def _clean(stderr: str) -> str:
     return "\n".join(l for l in stderr.splitlines() if "packed-fp32-ops" not in l)
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
+# Host-side sanitizer build (CPU checks of validation, planning and the orbit code): the
+# host half of every translation unit instrumented with AddressSanitizer and
+# UndefinedBehaviorSanitizer, device code untouched; the runtime is preloaded into the
+# process (libclang_rt.asan of the ROCm clang), so the link line names no sanitizer.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+LIB_HOST_SANITIZE = os.path.join(ROOT, "_build", "libaaqaoa_hostsan.so")  # outside the package: CPU checks only
+
+
+def build(verbose: bool = False, jobs: int = 0, host_sanitize: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     srcs = sources()
+    flags = FLAGS + (HOST_SANITIZE if host_sanitize else [])
+    lib = LIB_HOST_SANITIZE if host_sanitize else LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
     jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with tempfile.TemporaryDirectory(prefix="aaq_build_") as tmp:
         def compile_one(src):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
-            cmd = [hipcc] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+            cmd = [hipcc] + flags + ["-x", "hip", "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,15 +65,15 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
                 raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n{err}")
             if verbose and err.strip():
                 print(err, file=sys.stderr)
-        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for _, o, _, _ in results] + ["-o", LIB + ".tmp"]
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for _, o, _, _ in results] + ["-o", lib + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + _clean(r.stderr))
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, host_sanitize="--host-sanitize" in sys.argv))

@@ -113,3 +113,65 @@ def test_errors():
         A.aaq_edge_orbits(3, np.array([(0, 3)]))
     of, rep, size = A.aaq_edge_orbits(4, np.zeros((0, 2), dtype=np.int32))
     assert of.size == 0 and rep.size == 0
+
+
+# ------------------------------------------------------------------ closed forms at larger n
+def _partition_of(groups):
+    return {frozenset((min(u, v), max(u, v)) for u, v in grp) for grp in groups}
+
+
+def _closed_form_cases():
+    """(name, n, edges, expected partition) for families whose edge orbits are known in
+    closed form, up to 34 vertices: the automorphism group of K_n, of a star, of a cycle,
+    of K_{a,b}, of a hypercube and of a torus grid acts transitively on the edges; a path
+    has only its reversal (edge i with edge n-2-i); a wheel keeps spokes and rim apart;
+    two disjoint cycles of different lengths keep their two edge sets apart."""
+    cases = []
+    for n in (12, 20, 34):
+        es = [(u, v) for u in range(n) for v in range(u + 1, n)]
+        cases.append((f"K{n}", n, es, [es]))
+    for n in (17, 34):
+        es = [(0, v) for v in range(1, n)]
+        cases.append((f"star{n}", n, es, [es]))
+    for n in (5, 23, 34):
+        es = [(v, (v + 1) % n) for v in range(n)]
+        cases.append((f"C{n}", n, es, [es]))
+    for n in (9, 18, 34):
+        es = [(i, i + 1) for i in range(n - 1)]
+        groups = [[es[i], es[n - 2 - i]] for i in range((n - 1) // 2)]
+        if (n - 1) % 2:
+            groups.append([es[(n - 1) // 2]])
+        cases.append((f"P{n}", n, es, groups))
+    for m in (6, 33):  # hub 0 and a rim cycle of m vertices
+        spokes = [(0, v) for v in range(1, m + 1)]
+        rim = [(v, v % m + 1) for v in range(1, m + 1)]
+        cases.append((f"W{m + 1}", m + 1, spokes + rim, [spokes, rim]))
+    for a, b in ((3, 7), (17, 17)):
+        es = [(u, a + v) for u in range(a) for v in range(b)]
+        cases.append((f"K{a},{b}", a + b, es, [es]))
+    for d in (4, 5):
+        n = 1 << d
+        es = [(z, z | (1 << k)) for z in range(n) for k in range(d) if not (z >> k) & 1]
+        cases.append((f"Q{d}", n, es, [es]))
+    for m in (5, 6):  # torus C_m x C_m
+        idx = lambda i, j: (i % m) * m + (j % m)  # noqa: E731
+        es = [(idx(i, j), idx(i, j + 1)) for i in range(m) for j in range(m)] + \
+             [(idx(i, j), idx(i + 1, j)) for i in range(m) for j in range(m)]
+        cases.append((f"T{m}x{m}", m * m, es, [es]))
+    c1 = [(v, (v + 1) % 15) for v in range(15)]
+    c2 = [(15 + v, 15 + (v + 1) % 19) for v in range(19)]
+    cases.append(("C15+C19", 34, c1 + c2, [c1, c2]))
+    return cases
+
+
+@pytest.mark.parametrize("case", _closed_form_cases(), ids=lambda c: c[0])
+def test_closed_form_orbits_up_to_34_vertices(case):
+    name, n, edges, groups = case
+    rng = np.random.default_rng(len(edges))
+    perm = rng.permutation(len(edges))  # input order must not matter
+    es = np.asarray(edges, dtype=np.int32)[perm]
+    of, rep, size = A.aaq_edge_orbits(n, es)
+    assert partition(es, of) == _partition_of(groups), name
+    assert sorted(size) == sorted(len(set(map(tuple, map(sorted, grp)))) for grp in groups)
+    for o, r in enumerate(rep):
+        assert of[r] == o
