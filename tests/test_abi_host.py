@@ -124,6 +124,25 @@ def test_workspace_and_state_sizes():
     assert A.aaq_num_sets(34) == 4 and A.aaq_num_sets(33) == 4
 
 
+def test_tile_sets_for_every_size_and_tile():
+    """The planner's tile sets (qubits from 26 up spread over the later sets) are built for
+    every n up to the largest and both tile sizes without tripping its own checks, and the
+    set counts are those of the capacity rule: one full set of L qubits, the others L - 5."""
+    for prec in (A.AAQ_PREC_C64, A.AAQ_PREC_C128):
+        for tb in (12, 13):
+            for n in range(2, 35):
+                pr = prob(G.prufer_tree(n, n) if n > 2 else G.complete(2))
+                A.aaq_set_tile_bits(n, prec, True, tb)
+                try:
+                    assert A.aaq_workspace_size(pr, 2, True, prec=prec) > 0
+                finally:
+                    A.aaq_set_tile_bits(n, prec, True, 0)
+    for n in range(2, 35):
+        k = A.aaq_num_sets(n)
+        best = min(1 if n <= L else 1 + -(-(n - L) // (L - 5)) for L in (12, 13))
+        assert k == best, (n, k, best)
+
+
 def test_plan_workspace_size_host_only():
     probs = [prob(G.star(7)), prob(G.complete(9)), prob(G.prufer_tree(16, 2))]
     w = A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True)
