@@ -73,6 +73,31 @@ def test_cut_values_bit_exact_every_layout(g):
     assert np.array_equal(out.cpu().numpy(), ref_c)
 
 
+def test_cut_values_bit_exact_every_layout_large():
+    """n = 28, whose high tile sets each hold one of qubits 26 and 27 beside a run of other
+    qubits (13-bit tiles, three sets): every set, arrangement, observable and precision
+    against the oracle over all 2^28 indices (the comparison runs on the device against
+    the oracle's values copied there)."""
+    n = 28
+    g = G.prufer_tree(n, 40 + n)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    ref_c = torch.from_numpy(O.cut_values(g.n, g.edge_array())).cuda()
+    ref_h = torch.from_numpy(O.term_values(g.n, wp.terms(OBS_HRED)).astype(np.int32)).cuda()
+    ws = dev_bytes(1 << 16)
+    out = torch.empty(1 << g.n, dtype=torch.int32, device="cuda")
+    assert A.aaq_num_sets(n) == 3
+    for prec in (A.AAQ_PREC_C64, A.AAQ_PREC_C128):
+        for s in range(A.aaq_num_sets(n, prec)):
+            for arr in (0, 1):
+                for obs, ref in ((A.AAQ_OBS_HC, ref_c), (A.AAQ_OBS_HRED, ref_h)):
+                    out.fill_(-1)
+                    A.aaq_cut_values_layout(pr, obs, s, arr, prec, ws, out)
+                    assert torch.equal(out, ref), (prec, s, arr, obs)
+    del out, ref_c, ref_h
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------ energies
 ENERGY_CASES = [
     (G.Graph(1, []), 1), (G.Graph(2, [(0, 1)]), 2), (G.binary_tree(5), 3), (rand_graph(8, 0.5, 4), 2),
