@@ -117,6 +117,30 @@ def c1(args):
                            "kind": "FP64 full-state oracle, H_red energy, all 256 points, median of 5 runs"}}
 
 
+AGG_NAMES = {A.AAQ_AGG_FUSED: "fused", A.AAQ_AGG_PER_TERM: "per_term", A.AAQ_AGG_PASS_PER_TERM: "pass_per_term"}
+
+
+def _agg_modes(pr, p, g, b, reps, blocks, ref_of=None):
+    """Energy rates of H_red and H_C in the three aggregation modes (one Estimator per mode,
+    freed before the next: at n = 34 each holds a 128 GiB state buffer); with `ref_of`, the
+    relative error of each mode's energy against ref_of(obs)."""
+    out = {}
+    for agg, name in AGG_NAMES.items():
+        est = A.Estimator(pr, p, A.AAQ_OBS_HRED, A.AAQ_PREC_C64, grad=False, agg=agg)
+        m = {}
+        for oname, obs in (("H_red", A.AAQ_OBS_HRED), ("H_C", A.AAQ_OBS_HC)):
+            dt = _timed(lambda: est.energy(g, b, obs=obs, agg=agg), reps, blocks=blocks)
+            m[f"{oname}_evals_s"] = round(1.0 / dt, 3)
+            if ref_of is not None:
+                e = est.energy(g, b, obs=obs, agg=agg)[0]
+                m[f"{oname}_rel_err"] = abs(e - ref_of(obs)) / abs(ref_of(obs))
+        m["speedup"] = round(m["H_red_evals_s"] / m["H_C_evals_s"], 3)
+        out[name] = m
+        del est
+        torch.cuda.empty_cache()
+    return out
+
+
 def c2(args):
     from oracle import reduced as R
     import oracle as O
@@ -147,6 +171,8 @@ def c2(args):
                         "max_rel_err_batched": float(np.max(np.abs(out[:, 0] - ref) / np.abs(ref))),
                         "max_rel_err_plain": float(np.max(np.abs(single - ref) / np.abs(ref)))}
         r["speedup_Hred_over_HC_batched"] = round(r["H_red"]["batched_evals_s"] / r["H_C"]["batched_evals_s"], 3)
+        r["aggregation_modes_single_calls"] = _agg_modes(pr, p, gam[0], bet[0], 20, 5)
+        r["orbit_ratio_E_over_OE"] = round(wp.m / wp.orbits.count, 3)
         terms = wp.terms(A.AAQ_OBS_HRED)
         cnt = {"K16": 64, "star20": 8}.get(name, 2)
         rate_o, thr = _oracle_rate(lambda i: O.energy(wp.n, wp.edges(), terms, gam[i], bet[i]), cnt)
@@ -226,6 +252,12 @@ def c5a(args):
         res[oname] = {"s_per_eval": round(dt, 4), "max_rel_err_vs_closed_form": float(max(errs)),
                       "sweep_GBps": {c: round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1)
                                      for c, v in tm.items() if v["bytes"]}}
+    del est
+    torch.cuda.empty_cache()
+    ref_of = {obs: R.p1_energy(wp.n, wp.edges(), wp.terms(obs), gam[0, 0], bet[0, 0])
+              for obs in (A.AAQ_OBS_HC, A.AAQ_OBS_HRED)}
+    res["aggregation_modes"] = _agg_modes(pr, p, gam[0], bet[0], 1, 3, ref_of=ref_of.__getitem__)
+    res["orbit_ratio_E_over_OE"] = round(wp.m / wp.orbits.count, 3)
     return {"workload": "c5a: random tree n=34 (seed 5) p=1, complex64 energy, 2^34 amplitudes", "results": res}
 
 
