@@ -261,8 +261,13 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // butterflies and weighted by wcur = w^(gates of the mixer applied so far): that is
   // the term at the start of the mixer.  Evaluating after the butterflies keeps no
   // pre-gate values alive.
-  template <int K, uint32_t MASK, bool LAM>
+  // PSI: psi gets the gates too (false: only lambda, for a last arrangement after which
+  // psi is neither stored nor used; the terms are then formed before the gates)
+  template <int K, uint32_t MASK, bool LAM, bool PSI = true>
   __device__ __forceinline__ void mix_at(uint32_t act, R k, R w, R& wcur, R& gsum) {
+    static_assert(PSI || (NS == 2 && LAM), "only lambda's gates need psi's to be skipped");
+    // terms before the gates carry the scale of the gates applied so far
+    if constexpr (!PSI) grad_terms<K, MASK>(act, wcur, gsum);
     constexpr int B0 = G::b0(K);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
@@ -274,77 +279,82 @@ template <class R, int NS, bool EN, int LT> struct Tile {
         if (r & (1 << b)) continue;
         const int r1 = r | (1 << b);
         if constexpr (NS == 2 && LAM) bflyk(a[NS - 1][r], a[NS - 1][r1], kk);
-        bflyk(a[0][r], a[0][r1], kk);
+        if constexpr (PSI) bflyk(a[0][r], a[0][r1], kk);
       }
       wcur *= on ? w : R(1);
       // keep the scheduler from interleaving the butterflies of different qubits, which
       // holds pre- and post-gate values at once (register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
-    if constexpr (NS == 2 && LAM) {
-      // The register bits mixed here are taken two at a time where possible: for qubits
-      // b1, b2 and the four registers r0 = r, r1 = r ^ b1, r2 = r ^ b2, r3 = r ^ b1 ^ b2 the
-      // eight pair terms of both qubits add up to
-      //   Im(conj(lam0 + lam3) (psi1 + psi2)) + Im(conj(lam1 + lam2) (psi0 + psi3)),
-      // twelve operations where the two qubits' terms one by one take sixteen.  A pair with
-      // a qubit the set does not mix (uniform test) takes the single-qubit form.
-      constexpr uint32_t MB = (MASK >> B0) & ((1u << RB) - 1u);
-      R gt = R(0);
-      uint32_t left = MB;
+    if constexpr (PSI && NS == 2 && LAM) grad_terms<K, MASK>(act, wcur, gsum);
+  }
+
+  // The mixer's gradient terms of the qubits of MASK held in registers by arrangement K,
+  // weighted by wcur and added to gsum.
+  template <int K, uint32_t MASK> __device__ __forceinline__ void grad_terms(uint32_t act, R wcur, R& gsum) {
+    constexpr int B0 = G::b0(K);
+    // The register bits mixed here are taken two at a time where possible: for qubits
+    // b1, b2 and the four registers r0 = r, r1 = r ^ b1, r2 = r ^ b2, r3 = r ^ b1 ^ b2 the
+    // eight pair terms of both qubits add up to
+    //   Im(conj(lam0 + lam3) (psi1 + psi2)) + Im(conj(lam1 + lam2) (psi0 + psi3)),
+    // twelve operations where the two qubits' terms one by one take sixteen.  A pair with
+    // a qubit the set does not mix (uniform test) takes the single-qubit form.
+    constexpr uint32_t MB = (MASK >> B0) & ((1u << RB) - 1u);
+    R gt = R(0);
+    uint32_t left = MB;
 #pragma unroll
-      for (int b1 = 0; b1 < RB; ++b1) {
-        if (!((left >> b1) & 1u)) continue;
-        int b2 = -1;
+    for (int b1 = 0; b1 < RB; ++b1) {
+      if (!((left >> b1) & 1u)) continue;
+      int b2 = -1;
 #pragma unroll
-        for (int c = b1 + 1; c < RB; ++c)
-          if (b2 < 0 && ((left >> c) & 1u)) b2 = c;
-        left &= ~(1u << b1);
-        if (b2 >= 0) left &= ~(1u << b2);
-        const bool on1 = ((act >> (B0 + b1)) & 1u) != 0;
-        const bool on2 = b2 >= 0 && ((act >> (B0 + b2)) & 1u) != 0;
-        if (b2 >= 0 && on1 && on2) {
+      for (int c = b1 + 1; c < RB; ++c)
+        if (b2 < 0 && ((left >> c) & 1u)) b2 = c;
+      left &= ~(1u << b1);
+      if (b2 >= 0) left &= ~(1u << b2);
+      const bool on1 = ((act >> (B0 + b1)) & 1u) != 0;
+      const bool on2 = b2 >= 0 && ((act >> (B0 + b2)) & 1u) != 0;
+      if (b2 >= 0 && on1 && on2) {
+        R g0 = R(0), g1 = R(0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r & ((1 << b1) | (1 << b2))) continue;
+          const int r1 = r | (1 << b1), r2 = r | (1 << b2), r3 = r1 | r2;
+          const V la = mkv<R>(a[NS - 1][r].x + a[NS - 1][r3].x, a[NS - 1][r].y + a[NS - 1][r3].y);
+          const V lb = mkv<R>(a[NS - 1][r1].x + a[NS - 1][r2].x, a[NS - 1][r1].y + a[NS - 1][r2].y);
+          const V pa = mkv<R>(a[0][r1].x + a[0][r2].x, a[0][r1].y + a[0][r2].y);
+          const V pb = mkv<R>(a[0][r].x + a[0][r3].x, a[0][r].y + a[0][r3].y);
+          g0 = fmar(la.x, pa.y, g0);
+          g0 = fmar(-la.y, pa.x, g0);
+          g1 = fmar(lb.x, pb.y, g1);
+          g1 = fmar(-lb.y, pb.x, g1);
+        }
+        gt += g0 + g1;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int b = q == 0 ? b1 : b2;
+          if (b < 0) continue;
+          // sum over pairs of Im(conj(lam_r) psi_r1) + Im(conj(lam_r1) psi_r): two chains
+          // of fused multiply-adds (four per pair)
           R g0 = R(0), g1 = R(0);
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            if (r & ((1 << b1) | (1 << b2))) continue;
-            const int r1 = r | (1 << b1), r2 = r | (1 << b2), r3 = r1 | r2;
-            const V la = mkv<R>(a[NS - 1][r].x + a[NS - 1][r3].x, a[NS - 1][r].y + a[NS - 1][r3].y);
-            const V lb = mkv<R>(a[NS - 1][r1].x + a[NS - 1][r2].x, a[NS - 1][r1].y + a[NS - 1][r2].y);
-            const V pa = mkv<R>(a[0][r1].x + a[0][r2].x, a[0][r1].y + a[0][r2].y);
-            const V pb = mkv<R>(a[0][r].x + a[0][r3].x, a[0][r].y + a[0][r3].y);
-            g0 = fmar(la.x, pa.y, g0);
-            g0 = fmar(-la.y, pa.x, g0);
-            g1 = fmar(lb.x, pb.y, g1);
-            g1 = fmar(-lb.y, pb.x, g1);
+            if (r & (1 << b)) continue;
+            const int r1 = r | (1 << b);
+            const V &l0 = a[NS - 1][r], &l1 = a[NS - 1][r1], &p0 = a[0][r], &p1 = a[0][r1];
+            g0 = fmar(l0.x, p1.y, g0);
+            g0 = fmar(-l0.y, p1.x, g0);
+            g1 = fmar(l1.x, p0.y, g1);
+            g1 = fmar(-l1.y, p0.x, g1);
           }
-          gt += g0 + g1;
-        } else {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int b = q == 0 ? b1 : b2;
-            if (b < 0) continue;
-            // sum over pairs of Im(conj(lam_r) psi_r1) + Im(conj(lam_r1) psi_r): two chains
-            // of fused multiply-adds (four per pair)
-            R g0 = R(0), g1 = R(0);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-              if (r & (1 << b)) continue;
-              const int r1 = r | (1 << b);
-              const V &l0 = a[NS - 1][r], &l1 = a[NS - 1][r1], &p0 = a[0][r], &p1 = a[0][r1];
-              g0 = fmar(l0.x, p1.y, g0);
-              g0 = fmar(-l0.y, p1.x, g0);
-              g1 = fmar(l1.x, p0.y, g1);
-              g1 = fmar(-l1.y, p0.x, g1);
-            }
-            gt += ((act >> (B0 + b)) & 1u) ? g0 + g1 : R(0);
-          }
+          gt += ((act >> (B0 + b)) & 1u) ? g0 + g1 : R(0);
         }
       }
-      gsum += wcur * gt;
-      // the terms are formed here, before a following transpose: the empty volatile asm
-      // is ordered with the LDS stores, so the pre-transpose values are not kept alive
-      asm volatile("" : "+v"(gsum));
     }
+    gsum += wcur * gt;
+    // the terms are formed here, before a following transpose: the empty volatile asm
+    // is ordered with the LDS stores, so the pre-transpose values are not kept alive
+    asm volatile("" : "+v"(gsum));
   }
 
   // -------------------------------------------------------------- z of register 0
@@ -822,12 +832,13 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // skips arrangement 0.  Mixer A walks the route forward and ends at the phase
   // arrangement P, mixer B walks it back to LAST.  The qubits mixed at each stop are
   // compile-time masks (fwd_mask, bwd_mask).
-  template <int RT, int K, int PREV, bool LAM>
+  // PSI_P: psi gets the gates at the last stop P too (see mix_at)
+  template <int RT, int K, int PREV, bool LAM, bool PSI_P = true>
   __device__ __forceinline__ void fwd_steps(uint32_t act, R k, R w, R& wcur, R& gs, V* lds) {
     if constexpr (K <= P) {
       xchg<PREV, K, LAM, half_xchg(RT)>(lds);
-      mix_at<K, fwd_mask(RT, K), LAM>(act, k, w, wcur, gs);
-      fwd_steps<RT, K + 1, K, LAM>(act, k, w, wcur, gs, lds);
+      mix_at<K, fwd_mask(RT, K), LAM, (K < P || PSI_P)>(act, k, w, wcur, gs);
+      fwd_steps<RT, K + 1, K, LAM, PSI_P>(act, k, w, wcur, gs, lds);
     }
   }
   template <int RT, int K, bool LAM>
@@ -838,18 +849,22 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       bwd_steps<RT, K - 1, LAM>(act, k, w, wcur, gs, lds);
     }
   }
-  template <int RT, bool LAM> __device__ __forceinline__ void mix_fwd(uint32_t act, R k, R w, R& gs, V* lds) {
+  // PSI_LAST = false: psi is neither stored nor used after this mixer, so the gates of
+  // its last stop are applied to lambda only
+  template <int RT, bool LAM, bool PSI_LAST = true>
+  __device__ __forceinline__ void mix_fwd(uint32_t act, R k, R w, R& gs, V* lds) {
     R wcur = R(1);
     mix_at<LAST, fwd_mask(RT, LAST), LAM>(act, k, w, wcur, gs);
-    fwd_steps<RT, first_arr(RT), LAST, LAM>(act, k, w, wcur, gs, lds);
+    fwd_steps<RT, first_arr(RT), LAST, LAM, PSI_LAST>(act, k, w, wcur, gs, lds);
   }
-  template <int RT, bool LAM> __device__ __forceinline__ void mix_bwd(uint32_t act, R k, R w, R& gs, V* lds) {
+  template <int RT, bool LAM, bool PSI_LAST = true>
+  __device__ __forceinline__ void mix_bwd(uint32_t act, R k, R w, R& gs, V* lds) {
     constexpr int FIRST = first_arr(RT);
     R wcur = R(1);
     mix_at<P, bwd_mask(RT, P), LAM>(act, k, w, wcur, gs);
     bwd_steps<RT, P - 1, LAM>(act, k, w, wcur, gs, lds);
     xchg<(FIRST < P ? FIRST : P), LAST, LAM, half_xchg(RT)>(lds);
-    mix_at<LAST, bwd_mask(RT, LAST), LAM>(act, k, w, wcur, gs);
+    mix_at<LAST, bwd_mask(RT, LAST), LAM, PSI_LAST>(act, k, w, wcur, gs);
   }
 
   // Executes program `pg` on the tile with id `tile` of set S (whose route is RT), for
@@ -886,11 +901,16 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     constexpr bool LAM0 = NS == 2 && (KIND & SK_LAM_IN) != 0;
     lam_live = LAM0;
+    // SK_PSI_DEAD: psi is not stored (lambda is stored alone), so the last stop of the
+    // last mixer applies its gates to lambda only
+    constexpr bool PSI_DEAD = (KIND & SK_PSI_DEAD) != 0;
+    constexpr bool A_LAST = sk_mid(KIND) == 0 && (KIND & SK_MIXB) == 0;  // nothing after mixer A
+    static_assert(!PSI_DEAD || NS == 2, "only two-state sweeps leave psi unstored");
     ops_at<KL, LAM0, sk_pre(KIND)>(pg.pre_ops, false, S, tile_base, scp->F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
     bool at_p = false;
     if constexpr ((KIND & SK_MIXA) != 0) {
       R gs = R(0);
-      mix_fwd<RT, LAM0>(S.act, (R)scp->kA, (R)scp->wA, gs, lds_x);
+      mix_fwd<RT, LAM0, !(PSI_DEAD && A_LAST)>(S.act, (R)scp->kA, (R)scp->wA, gs, lds_x);
       if (pg.mixA_grad) acc.ba += (double)gs;
       at_p = true;
     }
@@ -903,13 +923,18 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     constexpr bool LAM1 = LAM0 || (NS == 2 && (KIND & SK_MAKE_LAM) != 0);
     if constexpr ((KIND & SK_MIXB) != 0) {
       R gs = R(0);
-      mix_bwd<RT, LAM1>(S.act, (R)scp->kB, (R)scp->wB, gs, lds_x);
+      mix_bwd<RT, LAM1, !PSI_DEAD>(S.act, (R)scp->kB, (R)scp->wB, gs, lds_x);
       if (pg.mixB_grad) acc.bb += (double)gs;
       at_p = false;
     }
-    const bool st_psi = (pg.flags & F_STORE_PSI) && cx.psi;
+    const bool st_psi = !PSI_DEAD && (pg.flags & F_STORE_PSI) && cx.psi;
     const bool st_lam = NS == 2 && LAM1 && (pg.flags & F_STORE_LAM) && cx.lam;
-    if ((st_psi || st_lam) && at_p) xchg<P, LAST, LAM1, half_xchg(RT)>(lds_x);
+    if ((st_psi || st_lam) && at_p) {
+      if constexpr (PSI_DEAD)
+        xchg1<P, LAST>(a[NS - 1], lds_x);  // lambda alone goes back to the store layout
+      else
+        xchg<P, LAST, LAM1, half_xchg(RT)>(lds_x);
+    }
     uint64_t toff = tile_base + thread_off<LAST>(S);
     // opaque to the compiler: the store addresses are formed here, not kept in
     // registers from the loads (that would hold 2 VGPRs per register and state)
@@ -1531,6 +1556,16 @@ static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t 
     case SK_B_PLAIN: return sweep_launch_kind<R, RT, LT, SK_B_PLAIN>(A, grid, blk, dyn, st);
     case SK_B_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY>(A, grid, blk, dyn, st);
     case SK_B_LAST: return sweep_launch_kind<R, RT, LT, SK_B_LAST>(A, grid, blk, dyn, st);
+    case SK_B_PLAIN_PD: return sweep_launch_kind<R, RT, LT, SK_B_PLAIN_PD>(A, grid, blk, dyn, st);
+    // on the full route (set 0, which takes the turnaround and layer boundaries only with
+    // two tile sets) the lambda-only last stop spills registers in some instantiations:
+    // those sweeps keep psi's gates there
+    case SK_TURNAROUND_PD:
+      if constexpr (RT == ROUTE_FULL) return sweep_launch_kind<R, RT, LT, SK_TURNAROUND>(A, grid, blk, dyn, st);
+      else return sweep_launch_kind<R, RT, LT, SK_TURNAROUND_PD>(A, grid, blk, dyn, st);
+    case SK_B_BOUNDARY_PD:
+      if constexpr (RT == ROUTE_FULL) return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY>(A, grid, blk, dyn, st);
+      else return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY_PD>(A, grid, blk, dyn, st);
     default: break;
   }
   if (pt)
@@ -1616,6 +1651,10 @@ static bool bsweep_launch_kind(const BatchArgs<R>& A, uint32_t kind, dim3 grid, 
     case SK_B_PLAIN: launch((k_bsweep_k<R, RT, LT, SK_B_PLAIN>), grid, blk, dyn, st, A); return true;
     case SK_B_BOUNDARY: launch((k_bsweep_k<R, RT, LT, SK_B_BOUNDARY>), grid, blk, dyn, st, A); return true;
     case SK_B_LAST: launch((k_bsweep_k<R, RT, LT, SK_B_LAST>), grid, blk, dyn, st, A); return true;
+    case SK_TURNAROUND_PD:
+      if constexpr (RT == ROUTE_FULL) launch((k_bsweep_k<R, RT, LT, SK_TURNAROUND>), grid, blk, dyn, st, A);
+      else launch((k_bsweep_k<R, RT, LT, SK_TURNAROUND_PD>), grid, blk, dyn, st, A);
+      return true;
     default: return false;
   }
 }

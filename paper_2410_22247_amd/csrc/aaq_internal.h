@@ -64,6 +64,7 @@ enum : uint32_t {
   SK_MIXA = 1u << 3,
   SK_MIXB = 1u << 4,
   SK_MAKE_LAM = 1u << 5,  // the energy step creates lambda
+  SK_PSI_DEAD = 1u << 6,  // psi is not stored after the last mixer (lambda alone is)
   SK_GENERIC = 1u << 31
 };
 constexpr uint32_t sk_pre(uint32_t kind) { return (kind >> 8) & 0xFFu; }
@@ -82,6 +83,11 @@ constexpr uint32_t SK_TURNAROUND = sk_make(SK_LOAD_PSI | SK_MIXA | SK_MIXB | SK_
 constexpr uint32_t SK_B_PLAIN = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA, 0, 0);
 constexpr uint32_t SK_B_BOUNDARY = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA | SK_MIXB, 0, OP_GRADG | OP_UNPHASE);
 constexpr uint32_t SK_B_LAST = sk_make(SK_LOAD_PSI | SK_LAM_IN | SK_MIXA, 0, OP_GRADG);
+// the turnaround and the backward sweeps when psi is not stored (the turnaround of every
+// gradient evaluation; the backward sweeps with forward-state checkpoints)
+constexpr uint32_t SK_TURNAROUND_PD = SK_TURNAROUND | SK_PSI_DEAD;
+constexpr uint32_t SK_B_PLAIN_PD = SK_B_PLAIN | SK_PSI_DEAD;
+constexpr uint32_t SK_B_BOUNDARY_PD = SK_B_BOUNDARY | SK_PSI_DEAD;
 
 // partial-sum slots written per sweep and tile
 enum : int { SLOT_E = 0, SLOT_NORM = 1, SLOT_GPRE = 2, SLOT_GMID = 3, SLOT_BA = 4, SLOT_BB = 5, SLOT_TERMS = 6 };
@@ -159,7 +165,11 @@ inline uint32_t sweep_kind(const SweepProg& s) {
   const uint32_t k = sk_make(b, s.pre_ops, s.mid_ops);
   for (uint32_t known : {SK_F_FIRST, SK_F_PLAIN, SK_F_BOUNDARY, SK_F_ENERGY, SK_F_ENERGY_TERMS, SK_TURNAROUND,
                          SK_B_PLAIN, SK_B_BOUNDARY, SK_B_LAST})
-    if (k == known) return k;
+    if (k == known) {
+      const bool dead = (s.flags & F_STORE_LAM) && !(s.flags & F_STORE_PSI);
+      if (dead && (k == SK_TURNAROUND || k == SK_B_PLAIN || k == SK_B_BOUNDARY)) return k | SK_PSI_DEAD;
+      return k;
+    }
   return SK_GENERIC;
 }
 
