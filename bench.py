@@ -36,10 +36,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kclass: str):
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def load_traffic(kclass: str, path: str = TRAFFIC_JSON):
     """HBM bytes per launch from the committed rocprofv3 counter runs, or None when
     they were taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -60,6 +62,11 @@ def kernel_class(name: str):
         if pre in name:
             ns = name.split(pre, 1)[1].split(",")[1].strip()
             return two if ns == "2" else one
+    if "aaq::k_bsweep_k<" in name:
+        # <R, route, tile bits, shape>: two states when the shape loads or creates lambda
+        # (bits 2 and 5 of the shape word)
+        kind = int(name.split("aaq::k_bsweep_k<", 1)[1].split(">", 1)[0].split(",")[3].strip().rstrip("u"))
+        return "sweep_2state" if kind & ((1 << 2) | (1 << 5)) else "sweep_1state"
     for key, cls in (("k_units", "units"), ("k_reduce", "reduce"), ("k_bsweep_out", "reduce"),
                      ("k_plan_tables", "tables"), ("k_tables", "tables"), ("k_zz_pass", "zz_pass")):
         if key in name:
@@ -78,7 +85,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def write_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 512 << 20):
+def write_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 512 << 20, out_path: str = TRAFFIC_JSON):
     """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
     dispatch) of `bench.py --copy-calibration`: each counter is scaled by the ratio of the
     algorithmic bytes of the 512 MiB calibration copy to what the counter reports for it."""
@@ -103,7 +110,7 @@ def write_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 512 << 20):
             w = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
             out["kernels"][c] = {"launches": len(d["FETCH_SIZE"]), "fetch_bytes_per_launch": f,
                                  "write_bytes_per_launch": w, "hbm_bytes_per_launch": f + w}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(out_path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
 
