@@ -308,12 +308,13 @@ void aaq_resident_destroy(aaq_resident *r);
 
 /* ---------------------------------------------------------------- half state
  * MaxCut QAOA states are invariant under flipping every bit (|+>, the cut phase and the
- * mixer all commute with the global flip; so are h and lambda = h psi), so the single-
+ * mixer all commute with the global flip; so are h and lambda = (h - c) psi), so the single-
  * instance and resident evaluations store and sweep only the amplitudes with bit n-1 = 0
  * and double every sum (the same results up to rounding order, half the state traffic
- * and half the vector work).  Used when the program has at least two tile sets, every
- * byte offset of 2^n amplitudes fits 32 bits (n <= 29 complex64, n <= 28 complex128), and
- * the call neither keeps the final state (sampling) nor passes over it per term.  On by
+ * and half the vector work).  Used when the program has at least two tile sets, the state
+ * is not of the one size whose 2^n amplitudes exceed 4 GiB while their half does not (n = 30
+ * complex64, n = 29 complex128: those keep the full state), and the call neither keeps the
+ * final state (sampling) nor passes over it per term.  On by
  * default; the switch is process-wide and takes effect at the next call (it is part of
  * the cached host plan's key).  State buffers sized by aaq_state_bytes stay valid. */
 void aaq_set_half_state(int enable);

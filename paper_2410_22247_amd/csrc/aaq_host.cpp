@@ -1018,9 +1018,12 @@ constexpr int kSampleBlockBits = 13;  // CDF blocks of 2^13 bitstrings
 
 int sample_block_bits(int n) { return std::min(n, kSampleBlockBits); }
 
+// sub-block sums: one FP64 sum per 64 bitstrings (per block when a block is smaller)
+size_t sample_sub_count(int n) { return (size_t)1 << (n - std::min(sample_block_bits(n), 6)); }
+
 size_t sample_extra_bytes(int n) {
   const size_t nb = (size_t)1 << (n - sample_block_bits(n));
-  return align_up(sizeof(double) * nb) * 2 + align_up(sizeof(double) * 2);
+  return align_up(sizeof(double) * nb) * 2 + align_up(sizeof(double) * 2) + align_up(sizeof(double) * sample_sub_count(n));
 }
 
 aaq_status run_sample(const aaq_problem* pr, int p, const double* gamma, const double* beta, aaq_precision prec,
@@ -1049,8 +1052,9 @@ aaq_status run_sample(const aaq_problem* pr, int p, const double* gamma, const d
   double* bsum = (double*)sw;
   double* cum = (double*)(sw + align_up(sizeof(double) * nb));
   double* stats = (double*)(sw + 2 * align_up(sizeof(double) * nb));
+  double* ssum = (double*)(sw + 2 * align_up(sizeof(double) * nb) + align_up(sizeof(double) * 2));
   const SwScale* fin = (const SwScale*)(ws + S.lay.scales) + S.lay.nsweep;
-  HIPCHK(launch_sample(d_state, S.n, lb, bsum, cum, &fin->F_pre, d_uniform, shots, (const GraphDev*)(ws + S.lay.graph),
+  HIPCHK(launch_sample(d_state, S.n, lb, bsum, cum, ssum, &fin->F_pre, d_uniform, shots, (const GraphDev*)(ws + S.lay.graph),
                        (const int4*)(ws + S.lay.terms), d_samples, d_cuts, stats, S.dbl, hs));
   double h[2];
   HIPCHK(hipMemcpyAsync(h, stats, sizeof(h), hipMemcpyDeviceToHost, hs));

@@ -334,25 +334,39 @@ __global__ __launch_bounds__(256) void k_zz_pass(const typename Cx<R>::V* __rest
 // ---------------------------------------------------------------- final-state sampling
 // The buffer holds sigma psi(z ^ F) at index z (uniform scale sigma, flip mask F), so the
 // probability of bitstring z is |buf[z ^ F]|^2 / sum |buf|^2.  Bitstrings are drawn by
-// inverse CDF in bitstring order: FP64 sums over blocks of 2^lb indices (index block c
-// holds bitstring block c ^ (F >> lb)), their inclusive prefix in bitstring-block order,
-// then per shot a binary search over the blocks and a wave-wide prefix scan inside the
-// chosen block.
+// inverse CDF in bitstring order, in three levels: FP64 sums over sub-blocks of 2^ls = 64
+// indices and over blocks of 2^lb indices (index block c holds bitstring block c ^ (F >> lb),
+// index sub-block s of a block holds bitstring sub-block s ^ ((F >> ls) mod 2^(lb - ls))),
+// the blocks' inclusive prefix in bitstring-block order, then per shot a binary search over
+// the blocks, a wave-wide prefix scan over the chosen block's sub-block sums and one over the
+// chosen sub-block's amplitudes.
+__host__ __device__ constexpr int samp_sub_bits(int lb) { return lb < 6 ? lb : 6; }
+
 template <class R>
 __global__ __launch_bounds__(256) void k_samp_blocksum(const typename Cx<R>::V* __restrict__ psi, int lb,
-                                                       double* __restrict__ bsum) {
-  __shared__ double red[4];
+                                                       double* __restrict__ bsum, double* __restrict__ ssum) {
+  // sub-block sums (one wave-wide sum per 64 consecutive indices), then the block sum as
+  // their sum in index order
+  __shared__ double sub[128];
   const uint64_t base = (uint64_t)blockIdx.x << lb;
-  const int B = 1 << lb;
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < B; i += 256) {
-    const typename Cx<R>::V a = psi[base + i];
-    acc += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  const int B = 1 << lb, ls = samp_sub_bits(lb), nsub = B >> ls;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wave * 64; c < B; c += 256) {
+    double pz = 0.0;
+    if (c + lane < B) {
+      const typename Cx<R>::V a = psi[base + c + lane];
+      pz = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    }
+    pz = wave_sum(pz);
+    if (lane == 0) sub[c >> ls] = pz;
   }
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x < nsub) ssum[((uint64_t)blockIdx.x << (lb - ls)) + threadIdx.x] = sub[threadIdx.x];
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int s2 = 0; s2 < nsub; ++s2) t += sub[s2];
+    bsum[blockIdx.x] = t;
+  }
 }
 
 // one workgroup: cum[b] = sum_{c <= b} bsum[c ^ fhi], in a fixed order
@@ -385,10 +399,10 @@ __global__ __launch_bounds__(1024) void k_samp_scan(const double* __restrict__ b
 // one wave per shot (four shots per workgroup)
 template <class R>
 __global__ __launch_bounds__(256) void k_sample(const typename Cx<R>::V* __restrict__ psi, int lb, uint64_t nb,
-                                                const double* __restrict__ cum, const uint64_t* __restrict__ flips,
-                                                const double* __restrict__ uniform, int shots, const GraphDev* g,
-                                                const int4* __restrict__ cost_terms, uint64_t* __restrict__ samples,
-                                                int32_t* __restrict__ cuts) {
+                                                const double* __restrict__ cum, const double* __restrict__ ssum,
+                                                const uint64_t* __restrict__ flips, const double* __restrict__ uniform,
+                                                int shots, const GraphDev* g, const int4* __restrict__ cost_terms,
+                                                uint64_t* __restrict__ samples, int32_t* __restrict__ cuts) {
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= shots) return;  // uniform over the wave
@@ -403,33 +417,58 @@ __global__ __launch_bounds__(256) void k_sample(const typename Cx<R>::V* __restr
     else lo = mid + 1;
   }
   const uint64_t b = lo;
-  const double r = t - (b ? cum[b - 1] : 0.0);
-  const int B = 1 << lb;
-  uint64_t zsel = ~0ull, zlast = b << lb;
-  double run = 0.0;
-  for (int c = 0; c < B; c += 64) {
-    const int j = c + lane;
-    double pz = 0.0;
-    if (j < B) {
-      const typename Cx<R>::V a = psi[((b << lb) | (uint64_t)j) ^ F];
-      pz = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-    }
-    double s = pz;  // inclusive prefix over the wave
+  double r = t - (b ? cum[b - 1] : 0.0);
+  // the chosen block's sub-block sums in bitstring order, two per lane (at most 128)
+  const int ls = samp_sub_bits(lb), nsub = 1 << (lb - ls);
+  const uint64_t fhi = (F >> lb) & (nb - 1);
+  const int fsub = (int)((F >> ls) & (uint64_t)(nsub - 1));
+  const double* ms = ssum + ((b ^ fhi) << (lb - ls));
+  const int s0 = 2 * lane, s1 = s0 + 1;
+  const double v0 = s0 < nsub ? ms[s0 ^ fsub] : 0.0, v1 = s1 < nsub ? ms[s1 ^ fsub] : 0.0;
+  double sc = v0 + v1;  // inclusive prefix over the wave
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double v = __shfl_up(s, o, 64);
-      if (lane >= o) s += v;
-    }
-    const uint64_t hit = __ballot(run + s > r);
-    const uint64_t nz = __ballot(pz > 0.0);
-    if (nz) zlast = (b << lb) | (uint64_t)(c + 63 - __builtin_clzll(nz));
-    if (hit) {
-      zsel = (b << lb) | (uint64_t)(c + __builtin_ctzll(hit));
-      break;
-    }
-    run += __shfl(s, 63, 64);
+  for (int o = 1; o < 64; o <<= 1) {
+    const double v = __shfl_up(sc, o, 64);
+    if (lane >= o) sc += v;
   }
-  if (zsel == ~0ull) zsel = zlast;  // rounding left the residual above the block's scanned mass
+  const uint64_t hit = __ballot(sc > r);
+  int sel;
+  bool exact = true;
+  if (hit) {
+    const int L = __builtin_ctzll(hit);
+    const double before = L ? __shfl(sc, L - 1, 64) : 0.0;
+    const double first = __shfl(v0, L, 64);
+    sel = (before + first > r) ? 2 * L : 2 * L + 1;
+    r -= (sel == 2 * L) ? before : before + first;
+  } else {
+    // rounding left the residual above the block's sub-block mass: the last sub-block
+    // with mass, and in it the last amplitude with mass
+    const uint64_t nz = __ballot(v0 > 0.0 || v1 > 0.0);
+    const int L = nz ? 63 - __builtin_clzll(nz) : 0;
+    sel = (__shfl(v1, L, 64) > 0.0) ? 2 * L + 1 : 2 * L;
+    exact = false;
+  }
+  // the chosen sub-block's amplitudes in bitstring order, one per lane
+  const int S = 1 << ls;
+  const uint64_t z0 = (b << lb) | ((uint64_t)sel << ls);
+  double pz = 0.0;
+  if (lane < S) {
+    const typename Cx<R>::V a = psi[(z0 | (uint64_t)lane) ^ F];
+    pz = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+  }
+  double se = pz;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double v = __shfl_up(se, o, 64);
+    if (lane >= o) se += v;
+  }
+  const uint64_t eh = exact ? __ballot(se > r) : 0ull;
+  const uint64_t enz = __ballot(pz > 0.0);
+  uint64_t zsel;
+  if (eh)
+    zsel = z0 | (uint64_t)__builtin_ctzll(eh);
+  else  // rounding again: the sub-block's last amplitude with mass
+    zsel = z0 | (uint64_t)(enz ? 63 - __builtin_clzll(enz) : 0);
   int cut = 0;
   if (g->weighted) {  // the weighted cut: the H_C term list holds every edge with its weight
     for (int t = 0; t < g->T; ++t) {
@@ -500,20 +539,21 @@ hipError_t launch_tables(const double* gamma, const double* beta, int p, int cma
   return hipGetLastError();
 }
 
-hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, const uint64_t* flips,
+hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, double* ssum, const uint64_t* flips,
                          const double* uniform, int shots, const GraphDev* g, const int4* cost_terms, uint64_t* samples,
                          int32_t* cuts, double* stats, bool dbl, hipStream_t st) {
+  if (lb > 13 || lb > n) return hipErrorInvalidValue;  // at most 128 sub-blocks of 64 per block
   const uint64_t nb = (uint64_t)1 << (n - lb);
   const dim3 gs((unsigned)((shots + 3) / 4));
   if (dbl) {
-    launch(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum);
+    launch(k_samp_blocksum<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double2*)psi, lb, bsum, ssum);
     launch(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
-    launch(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, flips, uniform, shots,
+    launch(k_sample<double>, gs, dim3(256), 0, st, (const double2*)psi, lb, nb, cum, ssum, flips, uniform, shots,
                        g, cost_terms, samples, cuts);
   } else {
-    launch(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum);
+    launch(k_samp_blocksum<float>, dim3((unsigned)nb), dim3(256), 0, st, (const float2*)psi, lb, bsum, ssum);
     launch(k_samp_scan, dim3(1), dim3(1024), 0, st, bsum, nb, flips, lb, cum);
-    launch(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, flips, uniform, shots, g,
+    launch(k_sample<float>, gs, dim3(256), 0, st, (const float2*)psi, lb, nb, cum, ssum, flips, uniform, shots, g,
                        cost_terms, samples, cuts);
   }
   launch(k_samp_stats, dim3(1), dim3(256), 0, st, cuts, shots, stats);

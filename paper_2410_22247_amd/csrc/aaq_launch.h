@@ -103,7 +103,7 @@ hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t
 // output rows [count][stride] in unit order (column 1, the norm, is averaged)
 // final-state sampling: block sums of |psi|^2, their prefix in bitstring order, one
 // inverse-CDF draw per uniform number (one wave per shot), cut values, best / mean cut
-hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, const uint64_t* flips,
+hipError_t launch_sample(const void* psi, int n, int lb, double* bsum, double* cum, double* ssum, const uint64_t* flips,
                          const double* uniform, int shots, const GraphDev* g, const int4* cost_terms, uint64_t* samples,
                          int32_t* cuts, double* stats, bool dbl, hipStream_t st);
 hipError_t launch_lc_bcast(const double* params, int np, double* rows, int count, hipStream_t st);
