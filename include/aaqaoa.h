@@ -423,7 +423,7 @@ void aaq_lightcone_destroy(aaq_lightcone *lc);
 
 /* ---------------------------------------------------------------- diagnostics */
 /* Per-kernel timing.  While enabled, every kernel launch of the library (outside a
- * stream capture) carries two HIP events in its dispatch on the stream it is launched
+ * stream capture, of the classes selected by aaq_timing_classes) carries two HIP events in its dispatch on the stream it is launched
  * on (the kernel's start and end; a launch of two kernels is timed from the first's
  * start to the second's end); aaq_timing_read waits for the events and returns, per
  * kernel class ("sweep_1state", "sweep_2state", "tables", "reduce", "zz_pass",
@@ -438,6 +438,12 @@ typedef struct {
 } aaq_kernel_timing;
 aaq_status aaq_timing_enable(int on);
 aaq_status aaq_timing_read(aaq_kernel_timing *out, int max, int *count, int reset);
+/* The kernel classes whose launches carry events while timing is on, as a bit mask in the
+ * order listed above (bit 0 "sweep_1state", 1 "sweep_2state", 2 "tables", 3 "reduce",
+ * 4 "zz_pass", 5 "units"); every class (63) until changed.  Launches of the other classes
+ * run without events and are not counted.  AAQ_ERR_INVALID_ARG for a negative mask or
+ * one with bits above 5 (the selection is then unchanged). */
+aaq_status aaq_timing_classes(int mask);
 
 const char *aaq_status_string(aaq_status s);
 const char *aaq_last_error_message(void);

@@ -47,7 +47,7 @@ EXPORTS = (
     "aaq_validate", "aaq_state_bytes", "aaq_workspace_size", "aaq_energy", "aaq_energy_grad", "aaq_cut_values",
     "aaq_cut_values_layout", "aaq_num_sets", "aaq_plan_default_opts", "aaq_plan_workspace_size", "aaq_plan_create",
     "aaq_plan_execute", "aaq_plan_destroy", "aaq_status_string", "aaq_last_error_message", "aaq_version",
-    "aaq_timing_enable", "aaq_timing_read", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
+    "aaq_timing_enable", "aaq_timing_read", "aaq_timing_classes", "aaq_set_tile_bits", "aaq_get_tile_bits", "aaq_autotune",
     "aaq_plan_autotune", "aaq_checkpoint_bytes", "aaq_energy_grad_checkpointed", "aaq_lightcone_info",
     "aaq_lightcone_workspace_size", "aaq_lightcone_create", "aaq_lightcone_execute", "aaq_lightcone_destroy",
     "aaq_edge_orbits", "aaq_sample_workspace_size", "aaq_sample", "aaq_resident_workspace_size",
@@ -88,6 +88,7 @@ def lib():
         "aaq_last_error_message": (ctypes.c_char_p, []),
         "aaq_version": (ctypes.c_char_p, []),
         "aaq_timing_enable": (i, [i]),
+        "aaq_timing_classes": (i, [i]),
         "aaq_timing_read": (i, [ctypes.POINTER(CKernelTiming), i, ctypes.POINTER(i), i]),
         "aaq_set_tile_bits": (i, [i, i, i, i]),
         "aaq_checkpoint_bytes": (i, [P, i, i, szp]),

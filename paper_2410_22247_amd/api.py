@@ -456,6 +456,20 @@ def aaq_timing_enable(on: bool) -> None:
     _check(_lib.lib().aaq_timing_enable(int(bool(on))))
 
 
+TIMING_CLASSES = ("sweep_1state", "sweep_2state", "tables", "reduce", "zz_pass", "units")
+
+
+def aaq_timing_classes(classes=None) -> None:
+    """Time only the named kernel classes while timing is on (None: every class)."""
+    if classes is None:
+        mask = (1 << len(TIMING_CLASSES)) - 1
+    else:
+        mask = 0
+        for c in classes:
+            mask |= 1 << TIMING_CLASSES.index(c)
+    _check(_lib.lib().aaq_timing_classes(mask))
+
+
 def aaq_timing_read(reset: bool = True) -> dict:
     """{class: {"launches", "total_ms", "bytes"}} accumulated since the last reset."""
     arr = (_lib.CKernelTiming * 16)()

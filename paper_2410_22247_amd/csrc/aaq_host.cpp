@@ -62,6 +62,7 @@ struct Pending {
 };
 std::mutex g_tmu;
 bool g_timing = false;
+uint32_t g_tclasses = (1u << KC_N) - 1;  // the classes timed while timing is on
 std::vector<Pending> g_pending;
 // timing-only events (no system-scope fence), created when timing is switched on and
 // reused, so a timed region creates none; guarded by g_tmu
@@ -84,7 +85,7 @@ struct TimedLaunch {
   hipStream_t st;
   TimedLaunch(int cls, double bytes, hipStream_t s) : on(false), st(s) {
     std::lock_guard<std::mutex> lk(g_tmu);
-    if (!g_timing) return;
+    if (!g_timing || !((g_tclasses >> cls) & 1u)) return;
     // kernels recorded into a graph carry no dispatch events: no timing while capturing
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
@@ -2142,6 +2143,13 @@ aaq_status aaq_timing_enable(int on) {
       g_evpool.push_back(e);
     }
   }
+  return AAQ_OK;
+}
+
+aaq_status aaq_timing_classes(int mask) {
+  if (mask < 0 || mask >= (1 << KC_N)) return fail(AAQ_ERR_INVALID_ARG, "timing class mask out of range");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_tclasses = (uint32_t)mask;
   return AAQ_OK;
 }
 

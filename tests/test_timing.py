@@ -17,12 +17,23 @@ from workloads import graphs as G
 from workloads.configs import OBS_HRED, make_problem
 
 C64 = A.AAQ_PREC_C64
+AAQ_ERR_INVALID_ARG = 1
 
 
 def test_timing_read_empty():
     A.aaq_timing_enable(False)
     A.aaq_timing_read(reset=True)
     assert A.aaq_timing_read(reset=True) == {}
+
+
+def test_timing_class_mask_checked():
+    lib = A._lib.lib()
+    for bad in (-1, 1 << len(A.api.TIMING_CLASSES)):
+        assert lib.aaq_timing_classes(bad) == AAQ_ERR_INVALID_ARG
+    A.aaq_timing_classes(["sweep_2state", "reduce"])
+    A.aaq_timing_classes(None)
+    with pytest.raises(ValueError):
+        A.aaq_timing_classes(["no_such_class"])
 
 
 @pytest.mark.gpu
@@ -68,6 +79,27 @@ def test_timing_counts_and_bytes(half):
     assert t["tables"]["launches"] == 1 and t["reduce"]["launches"] == 1
     for c in ("sweep_1state", "sweep_2state", "tables", "reduce"):
         assert t[c]["total_ms"] > 0, c
+
+    # one class selected: only its launches carry events, with the same counts and bytes
+    A.aaq_set_half_state(half)
+    try:
+        A.aaq_timing_classes(["sweep_2state"])
+        A.aaq_timing_read(reset=True)
+        A.aaq_timing_enable(True)
+        try:
+            r2 = est.energy_grad(gam, bet)
+            torch.cuda.synchronize()
+        finally:
+            A.aaq_timing_enable(False)
+            A.aaq_timing_classes(None)
+        t2 = A.aaq_timing_read(reset=True)
+    finally:
+        A.aaq_set_half_state(1)
+    assert list(t2) == ["sweep_2state"]
+    assert t2["sweep_2state"]["launches"] == t["sweep_2state"]["launches"]
+    assert t2["sweep_2state"]["bytes"] == t["sweep_2state"]["bytes"]
+    assert t2["sweep_2state"]["total_ms"] > 0
+    assert r2[0] == r0[0] and np.array_equal(r2[1], r0[1]) and np.array_equal(r2[2], r0[2])
 
 
 @pytest.mark.gpu
