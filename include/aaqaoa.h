@@ -184,7 +184,7 @@ aaq_status aaq_energy_grad_noalloc(const aaq_problem *prob, int p, const double 
  * same device code that the cost layer and the expectation use.
  *   d_ws   device workspace of >= 512 + 16 * T * (1 + 2 * aaq_num_sets(n, prec)) bytes
  *          (T = number of observable terms: the graph block and the term lists)
- *   d_out  device int32[2^n]; n <= 30.  Synchronises the stream. */
+ *   d_out  device int32[2^n] (16 GiB at n = 32, 64 GiB at n = 34).  Synchronises the stream. */
 aaq_status aaq_cut_values(const aaq_problem *prob, aaq_observable obs, void *d_ws, size_t ws_bytes, int32_t *d_out,
                           void *stream);
 

@@ -98,6 +98,30 @@ def cut_values(n: int, edges, weights=None) -> np.ndarray:
     return out
 
 
+def cut_values_at(z, edges, weights=None) -> np.ndarray:
+    """C(z) = sum_e w_e [z_u != z_v] at the given indices only (any shape, n <= 64), edge by
+    edge in numpy: the values a state too large for the full table is checked on."""
+    z = np.asarray(z, dtype=np.uint64)
+    e = _edges(edges)
+    w, _ = _weights(weights, e.shape[0])
+    if w is None:
+        w = np.ones(e.shape[0], dtype=np.int32)
+    out = np.zeros(z.shape, dtype=np.int64)
+    for (u, v), we in zip(e.reshape(-1, 2), w):
+        out += int(we) * (((z >> np.uint64(u)) ^ (z >> np.uint64(v))) & np.uint64(1)).astype(np.int64)
+    return out
+
+
+def term_values_at(z, terms) -> np.ndarray:
+    """h(z) = sum_t w_t [z_i != z_j] at the given indices only."""
+    z = np.asarray(z, dtype=np.uint64)
+    ti, tj, tw = _terms(terms)
+    out = np.zeros(z.shape, dtype=np.float64)
+    for i, j, w in zip(ti, tj, tw):
+        out += float(w) * (((z >> np.uint64(i)) ^ (z >> np.uint64(j))) & np.uint64(1)).astype(np.float64)
+    return out
+
+
 def term_values(n: int, terms) -> np.ndarray:
     """h(z) = sum_t w_t [z_i != z_j] for every z."""
     ti, tj, tw = _terms(terms)

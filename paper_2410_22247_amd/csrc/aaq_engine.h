@@ -391,15 +391,27 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // at their values in the flip mask F, which is uniform) and m the register bits flipped
   // relative to it: C(b ^ m) = C(b) + sum_{v in m} d_v
   //   + sum_{edges (v, w) inside m} 2 (2 [b_v != b_w] - 1),
-  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.  C(b) = sum_v [b_v] popc(adj_v & ~b):
-  // per vertex a sign-extended bit, a three-input AND and a population count.  The masks
-  // come from scalar loads; everything about the register bits is uniform (scalar).
-  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, uint64_t F, const GraphDev* g0,
-                                                        int (&cv)[NR]) const {
+  // d_v = deg v - 2 #{neighbours u with b_u != b_v}.  Everything about the register bits is
+  // uniform (scalar).  ub = tile_base ^ F, the base without this thread's bits (uniform).
+  // n <= 32: C(b) = sum_v [b_v] popc(adj_v & ~b), per vertex a sign-extended bit, a
+  // three-input AND and a population count, the masks from scalar loads.
+  // n > 32 (64-bit masks, three times the vector work per vertex): the tile's uniform part
+  // is computed once per wave with lane v taking vertex v.  Let tm be the thread bits'
+  // global positions, o the other vertices, and s this thread's values of b at tm (in
+  // thread-bit order: s = t ^ ub there).  Splitting the edges by how many ends lie in tm,
+  //   C(b) = 1/2 sum_{v in o} dd_v + sum_{v in tm} (z1_v + s_v c_v) + #{edges in tm cut by s},
+  // dd_v = #{u in o, u ~ v: ub_u != ub_v}, z1_v = #{u in o, u ~ v: ub_u = 1},
+  // c_v = #{u in o, u ~ v} - 2 z1_v; the last term is sum_{v in tm} s_v popc(ta_v & ~s),
+  // ta_v = v's neighbours in tm as thread bits.  The wave's sum comes from ballots of the
+  // bits of each lane's share, the per-vertex values from readlane.  The whole wave must
+  // make the call (every kernel calling this runs full waves to here).
+  template <int K> __device__ __forceinline__ void cuts(const SetSpec& S, uint64_t zb, uint64_t ub, uint64_t F,
+                                                        const GraphDev* g0, int (&cv)[NR]) const {
     const cptr<GraphDev> g = cst(g0);
     const int n = g->n;
-    // every index bit is below n: with n <= 32 the masks fit 32-bit registers (uniform branch)
+    constexpr int B0 = G::b0(K);
     int c0 = 0;
+    int d[RB];
     if (n <= 32) {
       const uint32_t z = (uint32_t)zb;
       const cptr<uint4> a4 = (cptr<uint4>)&g->adj32[0];
@@ -411,32 +423,78 @@ template <class R, int NS, bool EN, int LT> struct Tile {
         c0 = __popc(a.z & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v + 2, 1)) + c0;
         c0 = __popc(a.w & ~z & (uint32_t)__builtin_amdgcn_sbfe((int)z, v + 3, 1)) + c0;
       }
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const uint32_t v = S.pos[B0 + b];
+        d[b] = 0;
+        if (v != kDummy) {
+          const uint32_t bm = 0u - (uint32_t)((F >> v) & 1ull);  // the base bit of v, uniform
+          d[b] = g->deg[v] - 2 * __popc(g->adj32[v] & ((uint32_t)zb ^ bm));
+        }
+      }
     } else {
-      for (int v = 0; v < n; ++v) {
-        const uint64_t m = 0ull - ((zb >> v) & 1ull);
-        c0 += __popcll(g->adj[v] & ~zb & m);
+      static_assert(2 * kMaxN < 128, "a lane's share fits the seven ballot bits");
+      constexpr int KI = (K == LAST) ? 0 : 1;
+      const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+      const uint64_t adj = lane < (uint32_t)n ? g->adj[lane] : 0ull;
+      uint64_t tm = 0;
+      uint32_t ubt = 0, pt = 0;  // ub at tm and adj at tm, as thread bits
+#pragma unroll
+      for (int i = 0; i < kMaxRuns; ++i) {
+        const uint32_t r = S.trun[KI][i], tb = r & 0xFFu, gb = r >> 16;
+        const uint64_t mk = (1ull << ((r >> 8) & 0xFFu)) - 1ull;
+        tm |= mk << gb;
+        ubt |= (uint32_t)((ub >> gb) & mk) << tb;
+        pt |= (uint32_t)((adj >> gb) & mk) << tb;
+      }
+      const uint64_t ao = adj & ~tm;
+      const uint64_t uv = 0ull - ((ub >> lane) & 1ull);
+      const int dd = __popcll(ao & (ub ^ uv));
+      const int z1 = __popcll(ao & ub);
+      const int cc = __popcll(ao) - 2 * z1;
+      const uint32_t share = ((tm >> lane) & 1ull) ? (uint32_t)(2 * z1) : (uint32_t)dd;
+      int a2 = 0;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) a2 += __popcll(__ballot((share >> k) & 1u)) << k;
+      c0 = a2 >> 1;
+      const uint32_t s = threadIdx.x ^ ubt, ns = ~s;
+#pragma unroll
+      for (int i = 0; i < kMaxRuns; ++i) {
+        const uint32_t r = S.trun[KI][i], tb = r & 0xFFu, w = (r >> 8) & 0xFFu, gb = r >> 16;
+        for (uint32_t j = 0; j < w; ++j) {
+          const int v = (int)(gb + j);
+          const int sv = (int)((s >> (tb + j)) & 1u);
+          const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int)pt, v);
+          c0 += sv * __builtin_amdgcn_readlane(cc, v);
+          if (ta) c0 += sv * __popc(ta & ns);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const uint32_t v = S.pos[B0 + b];
+        d[b] = 0;
+        if (v != kDummy) {
+          const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int)pt, (int)v);
+          const int o = __builtin_amdgcn_readlane(dd, (int)v);
+          d[b] = g->deg[v] - 2 * (o + __popc(ta & (((ub >> v) & 1ull) ? ns : s)));
+        }
       }
     }
-    constexpr int B0 = G::b0(K);
-    int d[RB];
     uint32_t rr[RB], df[RB];
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const uint32_t v = S.pos[B0 + b];
-      d[b] = 0;
       rr[b] = 0;
       df[b] = 0;
       if (v != kDummy) {
         const uint64_t av = g->adj[v];
-        const uint64_t bm = 0ull - ((F >> v) & 1ull);  // the base bit of v, uniform
-        d[b] = g->deg[v] - 2 * (n <= 32 ? __popc(g->adj32[v] & ((uint32_t)zb ^ (uint32_t)bm))
-                                        : __popcll(av & (zb ^ bm)));
+        const uint32_t fv = (uint32_t)((F >> v) & 1ull);
 #pragma unroll
         for (int b2 = 0; b2 < RB; ++b2) {
           const uint32_t w = S.pos[B0 + b2];
           if (w != kDummy && ((av >> w) & 1u)) {
             rr[b] |= 1u << b2;
-            if (((F >> w) & 1u) != (bm & 1u)) df[b] |= 1u << b2;
+            if ((uint32_t)((F >> w) & 1ull) != fv) df[b] |= 1u << b2;
           }
         }
       }
@@ -550,7 +608,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
       if (cst(cx.g)->h_is_cut)
-        cuts<K>(S, zb, F, cx.g, hv);
+        cuts<K>(S, zb, tile_base ^ F, F, cx.g, hv);
       else
         hvals<K>(S, zb, cx.terms, hv, cst(cx.g)->n <= 32);
       double e = 0.0, nr = 0.0;
@@ -576,7 +634,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
-      cuts<K>(S, zb, F, cx.g, cv);
+      cuts<K>(S, zb, tile_base ^ F, F, cx.g, cv);
       if constexpr (NS == 2 && LAM) {
         if (ops & OP_GRADG) {
           R gs = R(0);
@@ -988,7 +1046,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     if (EN && (ops & OP_ENERGY)) {
       int hv[NR];
       if (cst(cx.g)->h_is_cut)
-        cuts<K>(S, zb, F, cx.g, hv);
+        cuts<K>(S, zb, tile_base ^ F, F, cx.g, hv);
       else
         hvals<K>(S, zb, cx.terms, hv, cst(cx.g)->n <= 32);
       double e = 0.0, nr = 0.0;
@@ -1016,7 +1074,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       if (cst(cx.g)->weighted)
         wcuts<K>(S, zb, cx.terms, cv, cst(cx.g)->n <= 32);
       else
-        cuts<K>(S, zb, F, cx.g, cv);
+        cuts<K>(S, zb, tile_base ^ F, F, cx.g, cv);
       if (NS == 2 && (ops & OP_GRADG)) {
         R gs = R(0);
 #pragma unroll
@@ -1516,7 +1574,7 @@ __global__ __launch_bounds__(1 << (LT - kRegBits)) void k_cuts(const GraphDev* g
   if (use_terms)
     tl.template hvals<KK>(S, zb, terms, v, cst(g)->n <= 32);
   else
-    tl.template cuts<KK>(S, zb, 0ull, g, v);
+    tl.template cuts<KK>(S, zb, tile_base, 0ull, g, v);
   const uint32_t t = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < G::NR; ++r) {

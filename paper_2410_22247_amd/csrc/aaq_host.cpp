@@ -1589,7 +1589,6 @@ aaq_status aaq_cut_values_layout(const aaq_problem* prob, aaq_observable obs, in
                                  aaq_precision prec, void* d_ws, size_t ws_bytes, int32_t* d_out, void* stream) {
   aaq_status s = validate_problem(prob);
   if (s) return s;
-  if (prob->n > 30) return fail(AAQ_ERR_UNSUPPORTED, "cut-value dumps are limited to n <= 30");
   if (!d_out || !d_ws) return fail(AAQ_ERR_INVALID_ARG, "d_out / d_ws is NULL");
   if (obs != AAQ_OBS_HC && obs != AAQ_OBS_HRED) return fail(AAQ_ERR_INVALID_ARG, "bad observable");
   if (prec != AAQ_PREC_C64 && prec != AAQ_PREC_C128) return fail(AAQ_ERR_INVALID_ARG, "bad precision");

@@ -98,6 +98,38 @@ def test_cut_values_bit_exact_every_layout_large():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("n", [33, 34])
+def test_cut_values_64bit_sampled(n):
+    """n > 32, where index masks take 64 bits and the tile's uniform part of C(z) is formed
+    across the wave (one lane per vertex): every set, arrangement, observable and precision
+    dumped whole (32 or 64 GiB), 2^20 seeded indices against the oracle's per-index values,
+    and the complement symmetry C(z) = C(~z) over every index on the device."""
+    g = G.prufer_tree(n, 5)
+    wp = make_problem(g)
+    pr = A.Problem.from_workload(wp)
+    rng = np.random.default_rng(100 + n)
+    idx = rng.integers(0, 1 << n, 1 << 20, dtype=np.uint64)
+    ref_c = O.cut_values_at(idx, g.edge_array())
+    ref_h = O.term_values_at(idx, wp.terms(OBS_HRED))
+    didx = torch.from_numpy(idx.astype(np.int64)).cuda()
+    ws = dev_bytes(1 << 16)
+    out = torch.empty(1 << n, dtype=torch.int32, device="cuda")
+    chunk = 1 << 28
+    N = 1 << n
+    for prec in (A.AAQ_PREC_C64, A.AAQ_PREC_C128):
+        for s in range(A.aaq_num_sets(n, prec)):
+            for arr in (0, 1):
+                for obs, ref in ((A.AAQ_OBS_HC, ref_c), (A.AAQ_OBS_HRED, ref_h)):
+                    out.fill_(-1)
+                    A.aaq_cut_values_layout(pr, obs, s, arr, prec, ws, out)
+                    got = out[didx].cpu().numpy()
+                    assert np.array_equal(got.astype(np.float64), np.asarray(ref, dtype=np.float64)), (prec, s, arr, obs)
+                    for a in range(0, N // 2, chunk):
+                        assert torch.equal(out[a:a + chunk], out[N - a - chunk:N - a].flip(0)), (prec, s, arr, obs, a)
+    del out, didx
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------ energies
 ENERGY_CASES = [
     (G.Graph(1, []), 1), (G.Graph(2, [(0, 1)]), 2), (G.binary_tree(5), 3), (rand_graph(8, 0.5, 4), 2),

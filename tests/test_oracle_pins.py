@@ -54,6 +54,31 @@ def test_cut_closed_forms():
     assert O.cut_values(12, t.edge_array()).max() == t.m  # trees are bipartite: C_max = |E|
 
 
+def test_cut_values_at_indices():
+    """The per-index cut values (for states too large for the full table) equal the full
+    table on small graphs, weighted or not, and at 34 vertices follow the closed forms of
+    K_n and the star and the complement symmetry."""
+    for g in SMALL:
+        z = np.arange(1 << g.n)
+        assert np.array_equal(O.cut_values_at(z, g.edge_array()), O.cut_values(g.n, g.edge_array()))
+    for g, w in weighted_graphs()[:4]:
+        z = np.arange(1 << g.n)
+        assert np.array_equal(O.cut_values_at(z, g.edge_array(), w), O.cut_values(g.n, g.edge_array(), w))
+    n = 34
+    rng = np.random.default_rng(11)
+    z = rng.integers(0, 1 << n, 4096, dtype=np.uint64)
+    k = np.array([bin(int(x)).count("1") for x in z])
+    assert np.array_equal(O.cut_values_at(z, G.complete(n).edge_array()), k * (n - k))
+    kl = np.array([bin(int(x) >> 1).count("1") for x in z])
+    assert np.array_equal(O.cut_values_at(z, G.star(n - 1).edge_array()), np.where(z & np.uint64(1), n - 1 - kl, kl))
+    t = G.prufer_tree(n, 5)
+    full = np.uint64((1 << n) - 1)
+    assert np.array_equal(O.cut_values_at(z, t.edge_array()), O.cut_values_at(full ^ z, t.edge_array()))
+    prob = make_problem(G.binary_tree(11))
+    zz = np.arange(1 << 11)
+    assert np.array_equal(O.term_values_at(zz, prob.terms(OBS_HRED)), O.term_values(11, prob.terms(OBS_HRED)))
+
+
 def test_term_values_weighted():
     prob = make_problem(G.binary_tree(11))
     h = O.term_values(11, prob.terms(OBS_HRED))
