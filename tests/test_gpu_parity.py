@@ -98,13 +98,16 @@ def test_cut_values_bit_exact_every_layout_large():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n", [33, 34])
-def test_cut_values_64bit_sampled(n):
+@pytest.mark.parametrize("g", [G.prufer_tree(33, 5), G.prufer_tree(34, 5), rand_graph(33, 0.3, 7)],
+                         ids=lambda g: f"{g.name or 'tree'}-n{g.n}")
+def test_cut_values_64bit_sampled(g):
     """n > 32, where index masks take 64 bits and the tile's uniform part of C(z) is formed
     across the wave (one lane per vertex): every set, arrangement, observable and precision
     dumped whole (32 or 64 GiB), 2^20 seeded indices against the oracle's per-index values,
-    and the complement symmetry C(z) = C(~z) over every index on the device."""
-    g = G.prufer_tree(n, 5)
+    and the complement symmetry C(z) = C(~z) over every index on the device.  The dense
+    graph (144 edges) puts edges among the thread-bit vertices and between them and the
+    register bits, which trees rarely do."""
+    n = g.n
     wp = make_problem(g)
     pr = A.Problem.from_workload(wp)
     rng = np.random.default_rng(100 + n)
