@@ -254,7 +254,9 @@ aaq_status aaq_plan_workspace_size(const aaq_problem *probs, int count, int p, a
                                    const aaq_plan_opts *opts, size_t *bytes);
 
 /* Validates every unit, lays out the workspace (descriptors, phase tables, per-unit
- * state buffers for n > 13) and uploads descriptors on `stream`. */
+ * state buffers for n > 13: with gradients the forward state after each of a unit's
+ * forward sweep steps, when there are at most 32 of them, and lambda; psi and lambda
+ * otherwise) and uploads descriptors on `stream`. */
 aaq_status aaq_plan_create(const aaq_problem *probs, int count, int p, aaq_observable obs, int with_grad,
                            const aaq_plan_opts *opts, void *d_ws, size_t ws_bytes, void *stream,
                            aaq_plan **out);

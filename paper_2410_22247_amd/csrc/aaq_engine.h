@@ -1400,7 +1400,7 @@ template <class R, int NS, int LT> __global__ AAQ_TILE_BOUNDS void k_units(UnitA
     const SwScale* scales = unit_scales<R>(A.ws, D);
     const bool big = D->state_off >= 0;
     V* psi = big ? reinterpret_cast<V*>(A.ws + D->state_off) : A.psi_io;
-    V* lam = big ? psi + ((size_t)1 << D->n) : nullptr;
+    V* lam = big && D->lam_off >= 0 ? reinterpret_cast<V*>(A.ws + D->lam_off) : nullptr;
     Ctx<R> cx{g, terms, tab, psi, lam, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
     cx.cen = (R)(0.5 * D->cmax);
     Tile<R, NS, true, LT> tl;
@@ -1451,6 +1451,7 @@ template <class R> struct BatchArgs {
   const UnitDesc* units;
   const SweepProg* progs;
   const int32_t* list;  // unit indices of the group
+  const int2* wgmap;    // (unit, tile) of each workgroup of a sweep step
   unsigned char* ws;
   int step;
   int tabmax;
@@ -1462,9 +1463,10 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
   __shared__ V lds_x[lds_slot(G::TILE)];
   __shared__ double red[(G::NT / 64) * 6];
   extern __shared__ unsigned char dyn_lds[];
-  const int u = A.list[blockIdx.y];
+  const int2 wm = A.wgmap[blockIdx.x];
+  const int u = __builtin_amdgcn_readfirstlane(wm.x);
   const UnitDesc* D = A.units + u;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane(wm.y);
   if (tile >= (uint32_t)D->ntiles || A.step >= D->nsweep) return;
   V* ltab0 = reinterpret_cast<V*>(dyn_lds);
   V* ltab1 = ltab0 + A.tabmax;
@@ -1481,8 +1483,9 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
     load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
   __syncthreads();
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
-  V* lam = psi + ((size_t)1 << D->n);
+  V* lam = reinterpret_cast<V*>(A.ws + D->lam_off);
   Ctx<R> cx{g, terms, tab, psi, NS == 2 ? lam : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
+  cx.N = (uint64_t)1 << D->n;  // the stride between the unit's checkpoint buffers
   cx.cen = (R)(0.5 * D->cmax);
   Tile<R, NS, EN, LT> tl;
   Acc acc;
@@ -1513,9 +1516,10 @@ __global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KI
   __shared__ V lds_x[lds_slot(sweep_half_xchg(NS, RT, KIND) ? G::TILE / 2 : G::TILE)];
   __shared__ double red[(G::NT / 64) * 6];
   extern __shared__ unsigned char dyn_lds[];
-  const int u = __builtin_amdgcn_readfirstlane(cst(A.list)[blockIdx.y]);
+  const int2 wm = cst(A.wgmap)[blockIdx.x];
+  const int u = __builtin_amdgcn_readfirstlane(wm.x);
   const cptr<UnitDesc> D = cst(A.units + u);
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane(wm.y);
   if (tile >= (uint32_t)D->ntiles || A.step >= D->nsweep) return;
   V* ltab0 = reinterpret_cast<V*>(dyn_lds);
   V* ltab1 = ltab0 + A.tabmax;
@@ -1533,7 +1537,8 @@ __global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KI
   __syncthreads();
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
   const uint64_t N = (uint64_t)1 << D->n;
-  Ctx<R> cx{g, terms, tab, psi, NS == 2 ? psi + N : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax, N,
+  Ctx<R> cx{g, terms, tab, psi, NS == 2 ? reinterpret_cast<V*>(A.ws + D->lam_off) : nullptr, (R)exp2(-0.5 * (double)D->n),
+            D->T, D->cmax, N,
             N <= ((uint64_t)1 << 32) / sizeof(V), false, (R)(0.5 * D->cmax)};
   Tile<R, NS, EN, LT> tl;
   Acc acc;
@@ -1709,17 +1714,24 @@ static bool bsweep_launch_kind(const BatchArgs<R>& A, uint32_t kind, dim3 grid, 
     case SK_B_PLAIN: launch((k_bsweep_k<R, RT, LT, SK_B_PLAIN>), grid, blk, dyn, st, A); return true;
     case SK_B_BOUNDARY: launch((k_bsweep_k<R, RT, LT, SK_B_BOUNDARY>), grid, blk, dyn, st, A); return true;
     case SK_B_LAST: launch((k_bsweep_k<R, RT, LT, SK_B_LAST>), grid, blk, dyn, st, A); return true;
+    // the lambda-only shapes of forward-state checkpoints, with the single-instance
+    // sweeps' fallbacks on the full route
     case SK_TURNAROUND_PD:
       if constexpr (RT == ROUTE_FULL) launch((k_bsweep_k<R, RT, LT, SK_TURNAROUND>), grid, blk, dyn, st, A);
       else launch((k_bsweep_k<R, RT, LT, SK_TURNAROUND_PD>), grid, blk, dyn, st, A);
+      return true;
+    case SK_B_PLAIN_PD: launch((k_bsweep_k<R, RT, LT, SK_B_PLAIN_PD>), grid, blk, dyn, st, A); return true;
+    case SK_B_BOUNDARY_PD:
+      if constexpr (RT == ROUTE_FULL) launch((k_bsweep_k<R, RT, LT, SK_B_BOUNDARY>), grid, blk, dyn, st, A);
+      else launch((k_bsweep_k<R, RT, LT, SK_B_BOUNDARY_PD>), grid, blk, dyn, st, A);
       return true;
     default: return false;
   }
 }
 
 template <class R, int LT> hipError_t bsweep_launch_impl(const LaunchBatch& L, hipStream_t st) {
-  const dim3 grid(L.max_tiles, L.nlist);
-  BatchArgs<R> A{L.units, L.progs, L.list, L.ws, L.step, L.tabmax};
+  const dim3 grid(L.wg_count);
+  BatchArgs<R> A{L.units, L.progs, L.list, L.wgmap, L.ws, L.step, L.tabmax};
   const size_t dyn = 2 * sizeof(typename Cx<R>::V) * (size_t)L.tabmax;
   if (L.kind != SK_GENERIC) {
     const bool done = L.route == ROUTE_HIGH ? bsweep_launch_kind<R, ROUTE_HIGH, LT>(A, L.kind, grid, dyn, st)

@@ -1112,8 +1112,9 @@ struct aaq_plan {
   // larger units: batched sweeps, one group per (tile size, tile-set count)
   struct Group {
     int L;
-    size_t list_off;  // device int32 list of unit indices
-    int nlist, max_tiles, nsweep;
+    size_t list_off;   // device int32 list of unit indices
+    size_t wgmap_off;  // device int2 (unit, tile) of each workgroup of the group's sweep steps
+    int nlist, max_tiles, nsweep, wg_count;
     std::vector<SweepProg> progs;  // the group's common program (for launch shapes)
     std::vector<uint8_t> routes;   // route of the set of each step
     bool weighted = false;         // some unit has edge weights (run-time sweep path)
@@ -1137,7 +1138,7 @@ constexpr int kMaxUnitTile = 13;
 constexpr int kNumCounters = 4;
 
 struct PlanLayout {
-  size_t units = 0, progs = 0, order = 0, counter = 0, lists = 0, graphs = 0, total = 0;
+  size_t units = 0, progs = 0, order = 0, counter = 0, lists = 0, graphs = 0, wgmap = 0, total = 0;
   std::vector<UnitDesc> ud;
   std::vector<SweepProg> progs_v;
   std::vector<std::pair<int, std::vector<int32_t>>> small;        // (tile bits, units)
@@ -1234,7 +1235,10 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     const std::vector<SetSpec>& sets = it->second.sets;
     D.nsets = (int)sets.size();
     for (int s = 0; s < D.nsets; ++s) D.sets[s] = sets[s];
-    progs[i] = build_progs(D.nsets, p, grad, OP_ENERGY, false);
+    // units swept as batched steps keep their forward states (checkpoints, at most
+    // kMaxCkpt of them): the backward steps then read psi and store lambda alone
+    const bool ckpt = grad && D.n > D.L && !o.single_launch && p * (D.nsets - 1) <= kMaxCkpt;
+    progs[i] = build_progs(D.nsets, p, grad, OP_ENERGY, false, ckpt);
     D.nsweep = (int)progs[i].size();
   }
   // offsets
@@ -1254,6 +1258,13 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   off = align_up(off + sizeof(int32_t) * kNumCounters);
   PL.lists = off;
   off = align_up(off + sizeof(int32_t) * count);
+  // the batched sweeps' workgroup map: (unit, tile) of every tile of every unit that runs
+  // as batched sweep steps (n above its tile size, not in the single-launch mode)
+  PL.wgmap = off;
+  size_t big_tiles = 0;
+  for (int i = 0; i < count; ++i)
+    if (PL.ud[i].n > PL.ud[i].L && !o.single_launch) big_tiles += (size_t)1 << (PL.ud[i].n - PL.ud[i].L);
+  off = align_up(off + sizeof(int2) * big_tiles);
   PL.graphs = off;
   off = align_up(off + PL.blob.size());
   for (int i = 0; i < count; ++i) {
@@ -1270,8 +1281,11 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];
     if (D.n > D.L) {
+      const size_t sbytes = amp * ((size_t)1 << D.n);
+      const int nb = prog_buffers(progs[i]);
       D.state_off = (int64_t)off;
-      off = align_up(off + amp * ((size_t)1 << D.n) * (grad ? 2 : 1));
+      D.lam_off = grad ? (int64_t)(off + sbytes * nb) : -1;
+      off = align_up(off + sbytes * (nb + (grad ? 1 : 0)));
       D.ntiles = (int32_t)(1u << (D.n - D.L));
       D.part_off = (int64_t)off;
       off = align_up(off + sizeof(double) * 6 * (size_t)D.nsweep * D.ntiles);
@@ -1281,6 +1295,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
         by_group[std::make_pair((int)D.L, D.nsets)].push_back(i);
     } else {
       D.state_off = -1;
+      D.lam_off = -1;
       D.ntiles = 1;
       D.part_off = -1;
       by_small[D.L].push_back(i);
@@ -1343,6 +1358,8 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     B.units = U.units;
     B.progs = U.progs;
     B.list = (const int32_t*)(P->ws + Gp.list_off);
+    B.wgmap = (const int2*)(P->ws + Gp.wgmap_off);
+    B.wg_count = Gp.wg_count;
     B.ws = P->ws;
     B.nlist = Gp.nlist;
     B.max_tiles = Gp.max_tiles;
@@ -1692,7 +1709,7 @@ aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_obse
       P->small.push_back(c);
       so += sizeof(int32_t) * sm.second.size();
     }
-    size_t lo = PL.lists;
+    size_t lo = PL.lists, wo = PL.wgmap;
     for (auto& gl : PL.group_units) {
       const std::vector<int32_t>& units = gl.second;
       std::memcpy(up.data() + lo, units.data(), sizeof(int32_t) * units.size());
@@ -1703,6 +1720,15 @@ aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_obse
       Gp.nlist = (int)units.size();
       Gp.max_tiles = 0;
       for (int u : units) Gp.max_tiles = std::max(Gp.max_tiles, (int)PL.ud[u].ntiles);
+      // one workgroup per tile of the group's units, no idle ones for the smaller units
+      Gp.wgmap_off = wo;
+      Gp.wg_count = 0;
+      for (int u : units) {
+        int2* m = reinterpret_cast<int2*>(up.data() + wo) + Gp.wg_count;
+        for (int t = 0; t < PL.ud[u].ntiles; ++t) m[t] = make_int2(u, t);
+        Gp.wg_count += PL.ud[u].ntiles;
+      }
+      wo += sizeof(int2) * (size_t)Gp.wg_count;
       const UnitDesc& D0 = PL.ud[units[0]];
       Gp.nsweep = D0.nsweep;
       Gp.progs.assign(PL.progs_v.begin() + D0.prog_off, PL.progs_v.begin() + D0.prog_off + D0.nsweep);

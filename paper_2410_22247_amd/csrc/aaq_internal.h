@@ -214,6 +214,7 @@ struct UnitDesc {
   int32_t row;         // row in d_params / d_out
   int32_t T, cmax;
   int64_t part_off;    // byte offset of the per-tile partial sums [nsweep][6][ntiles] (n > L units)
+  int64_t lam_off;     // byte offset of lambda, after the psi buffers (n > L units with gradients)
   int32_t ntiles;      // tiles per sweep
   int32_t L;           // tile size (log2 amplitudes) of the unit's kernels
   SetSpec sets[kMaxSets];

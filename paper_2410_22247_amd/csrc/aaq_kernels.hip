@@ -582,10 +582,10 @@ hipError_t launch_plan_tables(const LaunchUnits& L, int p, bool dbl, hipStream_t
 
 hipError_t launch_bsweep_out(const LaunchBatch& L, double* out, int out_stride, bool grad, bool dbl, hipStream_t st) {
   if (dbl) {
-    BatchArgs<double> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
+    BatchArgs<double> A{L.units, L.progs, L.list, L.wgmap, L.ws, 0, L.tabmax};
     launch(k_bsweep_out<double>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
   } else {
-    BatchArgs<float> A{L.units, L.progs, L.list, L.ws, 0, L.tabmax};
+    BatchArgs<float> A{L.units, L.progs, L.list, L.wgmap, L.ws, 0, L.tabmax};
     launch(k_bsweep_out<float>, dim3(L.nlist), dim3(256), 0, st, A, out, out_stride, (int)grad);
   }
   return hipGetLastError();

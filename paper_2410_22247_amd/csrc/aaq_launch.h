@@ -82,8 +82,9 @@ struct LaunchBatch {
   const UnitDesc* units;
   const SweepProg* progs;
   const int32_t* list;  // device list of the group's unit indices
+  const int2* wgmap;    // device (unit, tile) of each workgroup of a sweep step
   unsigned char* ws;
-  int nlist, max_tiles, step, tabmax, route;
+  int nlist, max_tiles, wg_count, step, tabmax, route;
   bool two_states, energy;
   uint32_t kind;  // the step's sweep shape (SK_*; SK_GENERIC: the run-time-flag engine)
 };
