@@ -67,6 +67,11 @@ template <class R> __device__ __forceinline__ typename Cx<R>::V mkv(R x, R y) {
   return v;
 }
 
+// the default deferred-table hook of Tile::run: nothing to load
+struct NoTabs {
+  __device__ __forceinline__ void operator()() const {}
+};
+
 // tile index of register r of thread t in an arrangement whose register bits start at B0
 template <int B0, int RB> __device__ __forceinline__ uint32_t tidx(uint32_t t, uint32_t r) {
   return (t & ((1u << B0) - 1u)) | (r << B0) | ((t >> B0) << (B0 + RB));
@@ -930,10 +935,13 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // around register updates.  The sweep runs in three stages (pre ops, mixer A + mid
   // ops, mixer B + store), each compiled for lambda live or not; lambda becomes live
   // where the energy step makes it.  Stores and buffer indices follow the program.
-  template <int RT, uint32_t KIND>
+  // late_tabs: called once the state loads are issued (a shape whose phase tables are
+  // first read at the mid position, after the first LDS exchange and its barrier, loads
+  // them there so their latency overlaps the state loads')
+  template <int RT, uint32_t KIND, class TabLoad = NoTabs>
   __device__ __forceinline__ void run(const SweepProg& pg, const SetSpec& S, const SwScale& sc, uint64_t tile,
                                       const Ctx<R>& cx, V* lds_x, const V* ltab_pre, const V* ltab_mid, Acc& acc,
-                                      double* zz_lds) {
+                                      double* zz_lds, const TabLoad& late_tabs = TabLoad{}) {
     const cptr<SwScale> scp = cst(&sc);  // uniform: scalar loads
     static_assert((KIND & SK_GENERIC) == 0, "generic sweeps take run_rt");
     static_assert(NS == ((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), "state count of the shape");
@@ -945,8 +953,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     } else {
       const uint64_t toff = tile_base + thread_off<KL>(S);
       if constexpr ((KIND & SK_LOAD_PSI) != 0) load_all<KL, RT == ROUTE_HIGH>(0, cx.psi + pg.ld_buf * cx.N, tile_base, toff, S, cx.off32, cx.nt);
-      if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
+      if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0)
         load_all<KL, RT == ROUTE_HIGH>(NS - 1, cx.lam, tile_base, toff, S, cx.off32, cx.nt);
+      late_tabs();
+      if constexpr (NS == 2 && (KIND & SK_LAM_IN) != 0) {
         if (scp->fix_lam) {
           const R fr = (R)scp->lam_fix[0], fi = (R)scp->lam_fix[1];
 #pragma unroll
@@ -1309,13 +1319,21 @@ __global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   V* ltab0 = reinterpret_cast<V*>(dyn_lds);
   V* ltab1 = ltab0 + (A.cmax + 1);
   const SwScale& sc = *A.scale;
-  if (A.prog.pre_ops & (OP_PHASE | OP_UNPHASE))
-    load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax, (A.prog.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
-  if (A.prog.mid_ops & (OP_PHASE | OP_UNPHASE))
-    load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax, (A.prog.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
-  if (PT)
-    for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
-  __syncthreads();
+  // a specialised shape with no phase before its first mixer loads its mid table once its
+  // state loads are issued (Tile::run); the others load the tables here
+  constexpr bool LATE_TAB = (KIND & SK_GENERIC) == 0 && !PT && (sk_pre(KIND) & (OP_PHASE | OP_UNPHASE)) == 0;
+  auto mid_tab = [&]() {
+    if (A.prog.mid_ops & (OP_PHASE | OP_UNPHASE))
+      load_tab<R>(ltab1, A.tab, A.prog.mid_layer, A.cmax, (A.prog.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  };
+  if constexpr (!LATE_TAB) {
+    if (A.prog.pre_ops & (OP_PHASE | OP_UNPHASE))
+      load_tab<R>(ltab0, A.tab, A.prog.pre_layer, A.cmax, (A.prog.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+    mid_tab();
+    if (PT)
+      for (int t = threadIdx.x; t < A.T; t += G::NT) zz[t] = 0.0;
+    __syncthreads();
+  }
   Ctx<R> cx{A.g, A.terms, A.tab, A.psi, A.lam, A.amp, A.T, A.cmax, A.N, A.N <= ((uint64_t)1 << 32) / sizeof(V), A.nt != 0,
             (R)(0.5 * A.cmax)};
   Tile<R, NS, EN, LT> tl;
@@ -1324,6 +1342,8 @@ __global__ AAQ_SWEEP_BOUNDS(NS, RT, KIND) void k_sweep(SweepArgs<R> A) {
   const uint32_t tile = blockIdx.x;
   if constexpr ((KIND & SK_GENERIC) != 0)
     tl.template run_rt<RT>(A.prog, A.set, sc, tile, cx, true, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
+  else if constexpr (LATE_TAB)
+    tl.template run<RT, KIND>(A.prog, A.set, sc, tile, cx, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr, mid_tab);
   else
     tl.template run<RT, KIND>(A.prog, A.set, sc, tile, cx, lds_x, ltab0, ltab1, acc, PT ? zz : nullptr);
   const uint32_t nt = gridDim.x;  // tiles of this launch (half of the set's with the half state)
@@ -1530,11 +1550,19 @@ __global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KI
   const SwScale& sc = reinterpret_cast<const SwScale*>(A.ws + D->tab_off + amp * (size_t)D->p * (D->cmax + 1))[A.step];
   const SweepProg pg = cst(A.progs)[D->prog_off + A.step];
   const SetSpec S = D->sets[pg.set];
-  if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
-    load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
-  if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
-    load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
-  __syncthreads();
+  // as in k_sweep: a shape with no phase before its first mixer loads its mid table once
+  // its state loads are issued
+  constexpr bool LATE_TAB = (sk_pre(KIND) & (OP_PHASE | OP_UNPHASE)) == 0;
+  auto mid_tab = [&]() {
+    if (pg.mid_ops & (OP_PHASE | OP_UNPHASE))
+      load_tab<R>(ltab1, tab, pg.mid_layer, D->cmax, (pg.mid_ops & OP_UNPHASE) != 0, sc.rho_mid);
+  };
+  if constexpr (!LATE_TAB) {
+    if (pg.pre_ops & (OP_PHASE | OP_UNPHASE))
+      load_tab<R>(ltab0, tab, pg.pre_layer, D->cmax, (pg.pre_ops & OP_UNPHASE) != 0, sc.rho_pre);
+    mid_tab();
+    __syncthreads();
+  }
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
   const uint64_t N = (uint64_t)1 << D->n;
   Ctx<R> cx{g, terms, tab, psi, NS == 2 ? reinterpret_cast<V*>(A.ws + D->lam_off) : nullptr, (R)exp2(-0.5 * (double)D->n),
@@ -1543,7 +1571,10 @@ __global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KI
   Tile<R, NS, EN, LT> tl;
   Acc acc;
   acc.zero();
-  tl.template run<RT, KIND>(pg, S, sc, tile, cx, lds_x, ltab0, ltab1, acc, nullptr);
+  if constexpr (LATE_TAB)
+    tl.template run<RT, KIND>(pg, S, sc, tile, cx, lds_x, ltab0, ltab1, acc, nullptr, mid_tab);
+  else
+    tl.template run<RT, KIND>(pg, S, sc, tile, cx, lds_x, ltab0, ltab1, acc, nullptr);
   scale_acc(acc, pg, sc);
   constexpr uint32_t SLOTS = sweep_slots(KIND);
   constexpr int NV = __builtin_popcount(SLOTS);
