@@ -305,10 +305,15 @@ def lc(args):
                 g, gr = np.concatenate([dg, db]), np.concatenate([dg_lc, db_lc])
                 errs_e.append(abs(e - e_lc) / abs(e_lc))
                 errs_g.append(float(np.linalg.norm(g - gr) / np.linalg.norm(gr)))
-            r[oname] = {"units": L.units, "max_cone_qubits": L.max_qubits, "cone_amplitudes": L.amplitudes,
-                        "evals_s": round(1.0 / dt, 1), "max_rel_err_energy": float(max(errs_e)),
-                        "max_rel_err_grad": float(max(errs_g))}
             L.close()
+            # the same cones with each small-unit launch on a stream of its own
+            Ls = A.LightCone(pr, p, obs, with_grad=True, small_streams=True)
+            Ls.params.copy_(torch.from_numpy(np.concatenate([gam[0], bet[0]])))
+            dts = _timed(Ls.execute, reps)
+            Ls.close()
+            r[oname] = {"units": L.units, "max_cone_qubits": L.max_qubits, "cone_amplitudes": L.amplitudes,
+                        "evals_s": round(1.0 / dt, 1), "small_streams_evals_s": round(1.0 / dts, 1),
+                        "max_rel_err_energy": float(max(errs_e)), "max_rel_err_grad": float(max(errs_g))}
         r["speedup_Hred_over_HC"] = round(r["H_red"]["evals_s"] / r["H_C"]["evals_s"], 3)
         res[name] = r
     return {"workload": "lc: light-cone x orbit evaluation (energy + adjoint gradient, complex64), device-resident "

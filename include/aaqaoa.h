@@ -224,7 +224,10 @@ aaq_status aaq_autotune(const aaq_problem *prob, int p, int with_grad, aaq_obser
  * sweep sequence in registers, one launch per tile size.  Larger units are grouped by
  * tile size and tile-set count, and each sweep step is one launch over every tile of
  * every unit of the group; the persistent small-unit launches run concurrently with
- * that chain (a second stream, a fork and a join in the captured graph).  With
+ * that chain (a second stream, a fork and a join in the captured graph; with
+ * small_streams each of them on a stream of its own).  Units with n > 13 store and sweep
+ * the half state (the spin-flip symmetry, as for the single-instance calls, when
+ * aaq_set_half_state allows it) and, with gradients, keep their forward states.  With
  * single_launch every unit runs in the persistent kernel (a large unit is swept tile by
  * tile by the one workgroup that takes it), so the whole batch is one launch after the
  * phase tables.  Replays are captured once in a HIP graph.
@@ -245,6 +248,9 @@ typedef struct {
                               amplitude bits) that is >= max(n, this); 0 = 10 (default) */
   int single_launch;       /* 1 = every unit in the persistent kernel (one launch per tile size);
                               0 = units with n > 13 as batched sweep steps (default) */
+  int small_streams;       /* 1 = each persistent small-unit launch (one per tile size) on a stream
+                              of its own, concurrent with the others; 0 = all of them on one
+                              stream beside the batched sweep steps (default) */
 } aaq_plan_opts;
 
 /* Fills opts with the defaults above. */
@@ -271,7 +277,8 @@ void aaq_plan_destroy(aaq_plan *plan);
 /* Plan autotuner: builds the plan with every candidate of tile_bits_large (12, 13; when
  * some unit has n > 13), min_tile_bits_small (10, 12, 13; when some unit has n <= 12),
  * workgroups (automatic, one and four per compute unit; when some unit has n <= 13) and
- * single_launch (0, 1; when some unit has n > 13) on top of `base` (NULL = defaults),
+ * single_launch (0, 1; when some unit has n > 13) and small_streams (0, 1; when some unit has
+ * n <= 13) on top of `base` (NULL = defaults),
  * times `reps` executions of each with HIP
  * events on `stream` (after one warm-up execution) and returns the fastest options in
  * *best and their time per execution in *best_ms (may be NULL).  Candidates whose

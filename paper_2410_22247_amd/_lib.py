@@ -40,6 +40,7 @@ class CPlanOpts(ctypes.Structure):
         ("tile_bits_large", ctypes.c_int),
         ("min_tile_bits_small", ctypes.c_int),
         ("single_launch", ctypes.c_int),
+        ("small_streams", ctypes.c_int),
     ]
 
 

@@ -1505,7 +1505,7 @@ template <class R, int NS, bool EN, int RT, int LT> __global__ AAQ_TILE_BOUNDS v
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
   V* lam = reinterpret_cast<V*>(A.ws + D->lam_off);
   Ctx<R> cx{g, terms, tab, psi, NS == 2 ? lam : nullptr, (R)exp2(-0.5 * (double)D->n), D->T, D->cmax};
-  cx.N = (uint64_t)1 << D->n;  // the stride between the unit's checkpoint buffers
+  cx.N = (uint64_t)1 << (D->n - D->half);  // stored amplitudes: the stride between checkpoint buffers
   cx.cen = (R)(0.5 * D->cmax);
   Tile<R, NS, EN, LT> tl;
   Acc acc;
@@ -1564,7 +1564,7 @@ __global__ AAQ_SWEEP_BOUNDS(((KIND & (SK_LAM_IN | SK_MAKE_LAM)) ? 2 : 1), RT, KI
     __syncthreads();
   }
   V* psi = reinterpret_cast<V*>(A.ws + D->state_off);
-  const uint64_t N = (uint64_t)1 << D->n;
+  const uint64_t N = (uint64_t)1 << (D->n - D->half);  // stored amplitudes per state
   Ctx<R> cx{g, terms, tab, psi, NS == 2 ? reinterpret_cast<V*>(A.ws + D->lam_off) : nullptr, (R)exp2(-0.5 * (double)D->n),
             D->T, D->cmax, N,
             N <= ((uint64_t)1 << 32) / sizeof(V), false, (R)(0.5 * D->cmax)};

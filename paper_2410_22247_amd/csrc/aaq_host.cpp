@@ -688,36 +688,43 @@ struct Single {
 // once per sweep, and every sum counts one of each equal pair.
 std::atomic<bool> g_half_state{true};
 
-bool half_state_ok(const Single& S, aaq_aggregation agg, bool keep_state) {
-  if (!g_half_state || S.k < 2 || agg == AAQ_AGG_PASS_PER_TERM || keep_state) return false;
+// whether the sets of an n-qubit program at tile size L can sweep the half state
+bool sets_half_ok(const std::vector<SetSpec>& sets, int n, int L, bool dbl) {
+  if (!g_half_state || sets.size() < 2) return false;
   // The sweeps address a stored state with 32-bit buffer offsets when its 2^(n-1)
   // amplitudes span at most 4 GiB; the mirrored offsets of that path are formed over the
   // full index range, so it needs 2^n amplitudes within 4 GiB.  Larger states take 64-bit
   // addresses, mirrored offsets included.  Only the size in between (2^n amplitudes above
   // 4 GiB, their half within it: n = 30 in complex64) keeps the full state.
-  const uint64_t amp = S.dbl ? 16u : 8u;
-  const bool full32 = (((uint64_t)1 << S.n) * amp) <= ((uint64_t)1 << 32);
-  const bool half64 = (((uint64_t)1 << (S.n - 1)) * amp) > ((uint64_t)1 << 32);
+  const uint64_t amp = dbl ? 16u : 8u;
+  const bool full32 = (((uint64_t)1 << n) * amp) <= ((uint64_t)1 << 32);
+  const bool half64 = (((uint64_t)1 << (n - 1)) * amp) > ((uint64_t)1 << 32);
   if (!full32 && !half64) return false;
-  const SetSpec& last = S.sets.back();
-  const int b0l = geo_b0(geo_na(S.L) - 1, S.L);
-  if (last.pos[S.L - 1] != S.n - 1 || b0l + kRegBits != S.L) return false;
-  for (size_t i = 0; i + 1 < S.sets.size(); ++i)  // bit n-1 is the top tile-id bit
-    if (!((S.sets[i].fixmask >> (S.n - 1)) & 1u)) return false;
+  const SetSpec& last = sets.back();
+  const int b0l = geo_b0(geo_na(L) - 1, L);
+  if (last.pos[L - 1] != n - 1 || b0l + kRegBits != L) return false;
+  for (size_t i = 0; i + 1 < sets.size(); ++i)  // bit n-1 is the top tile-id bit
+    if (!((sets[i].fixmask >> (n - 1)) & 1u)) return false;
   return true;
 }
+bool half_state_ok(const Single& S, aaq_aggregation agg, bool keep_state) {
+  if (S.k < 2 || agg == AAQ_AGG_PASS_PER_TERM || keep_state) return false;
+  return sets_half_ok(S.sets, S.n, S.L, S.dbl);
+}
 
-void mark_mirror(Single& S) {
-  SetSpec& last = S.sets.back();
-  const int b0l = geo_b0(geo_na(S.L) - 1, S.L);
+// the last set's mirrored registers (those whose index has bit n-1 set)
+void mark_mirror(std::vector<SetSpec>& sets, int n, int L) {
+  SetSpec& last = sets.back();
+  const int b0l = geo_b0(geo_na(L) - 1, L);
   last.mirror = 0;
   for (int r = 0; r < (1 << kRegBits); ++r)
-    if ((last.roff[r] >> (S.n - 1)) & 1u) last.mirror |= (uint16_t)(1u << r);
+    if ((last.roff[r] >> (n - 1)) & 1u) last.mirror |= (uint16_t)(1u << r);
   last.tmax = 0;
   for (int j = 0; j < b0l; ++j)
     if (last.pos[j] != kDummy) last.tmax |= (uint64_t)1 << last.pos[j];
-  last.mfull = ((uint64_t)1 << S.n) - 1;
+  last.mfull = ((uint64_t)1 << n) - 1;
 }
+void mark_mirror(Single& S) { mark_mirror(S.sets, S.n, S.L); }
 
 // grids: persistent workgroups per sweep (empty: one per tile, the upper bound used for
 // sizing); partial sums are laid out [sweep][slot][tile] with a tile-count stride.
@@ -1120,9 +1127,12 @@ struct aaq_plan {
     bool weighted = false;         // some unit has edge weights (run-time sweep path)
   };
   std::vector<Group> groups;
-  // the small-unit launches run on `aux`, forked from and joined to the caller's stream
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the small-unit launches (one per tile size) run on streams of their own, forked from
+  // and joined to the caller's stream, when more than one launch sequence exists
+  static constexpr int kMaxAux = 3;
+  hipStream_t aux[kMaxAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxAux] = {};
+  int naux = 0;
   // captured graph
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1165,6 +1175,7 @@ aaq_status check_opts(const aaq_plan_opts& o) {
     return fail(AAQ_ERR_INVALID_ARG, "min_tile_bits_small must be in 0..13");
   if (o.workgroups < 0) return fail(AAQ_ERR_INVALID_ARG, "workgroups must be >= 0");
   if (o.single_launch != 0 && o.single_launch != 1) return fail(AAQ_ERR_INVALID_ARG, "single_launch must be 0 or 1");
+  if (o.small_streams != 0 && o.small_streams != 1) return fail(AAQ_ERR_INVALID_ARG, "small_streams must be 0 or 1");
   return AAQ_OK;
 }
 
@@ -1192,6 +1203,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   struct GraphEntry {
     int64_t goff, toff;
     std::vector<SetSpec> sets;
+    bool half;  // the unit sweeps the half state (its last set's mirrored registers marked)
   };
   std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*, const int32_t*, int>, GraphEntry> gmap;
   PL.ud.assign(count, UnitDesc{});
@@ -1228,11 +1240,15 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
       PL.blob.resize(align_up(PL.blob.size() + sizeof(int4) * std::max<size_t>(t.size(), 1)));
       if (!t.empty()) std::memcpy(PL.blob.data() + toff, t.data(), sizeof(int4) * t.size());
       if (unit_terms) std::get<0>(key) = (const int32_t*)(intptr_t)(-1 - i);  // never shared
-      it = gmap.emplace(key, GraphEntry{goff, toff, sets}).first;
+      // units swept as batched steps store and sweep the half state when their sets allow
+      const bool half = pr->n > D.L && !o.single_launch && sets_half_ok(sets, pr->n, D.L, dbl);
+      if (half) mark_mirror(sets, pr->n, D.L);
+      it = gmap.emplace(key, GraphEntry{goff, toff, sets, half}).first;
     }
     D.graph_off = it->second.goff;  // relative to the graph area; fixed up below
     D.terms_off = it->second.toff;
     const std::vector<SetSpec>& sets = it->second.sets;
+    D.half = it->second.half ? 1 : 0;
     D.nsets = (int)sets.size();
     for (int s = 0; s < D.nsets; ++s) D.sets[s] = sets[s];
     // units swept as batched steps keep their forward states (checkpoints, at most
@@ -1263,7 +1279,8 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   PL.wgmap = off;
   size_t big_tiles = 0;
   for (int i = 0; i < count; ++i)
-    if (PL.ud[i].n > PL.ud[i].L && !o.single_launch) big_tiles += (size_t)1 << (PL.ud[i].n - PL.ud[i].L);
+    if (PL.ud[i].n > PL.ud[i].L && !o.single_launch)
+      big_tiles += ((size_t)1 << (PL.ud[i].n - PL.ud[i].L)) >> PL.ud[i].half;
   off = align_up(off + sizeof(int2) * big_tiles);
   PL.graphs = off;
   off = align_up(off + PL.blob.size());
@@ -1281,12 +1298,12 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
   for (int i = 0; i < count; ++i) {
     UnitDesc& D = PL.ud[i];
     if (D.n > D.L) {
-      const size_t sbytes = amp * ((size_t)1 << D.n);
+      const size_t sbytes = amp * ((size_t)1 << (D.n - D.half));  // the stored amplitudes
       const int nb = prog_buffers(progs[i]);
       D.state_off = (int64_t)off;
       D.lam_off = grad ? (int64_t)(off + sbytes * nb) : -1;
       off = align_up(off + sbytes * (nb + (grad ? 1 : 0)));
-      D.ntiles = (int32_t)(1u << (D.n - D.L));
+      D.ntiles = (int32_t)((1u << (D.n - D.L)) >> D.half);  // tiles swept per step
       D.part_off = (int64_t)off;
       off = align_up(off + sizeof(double) * 6 * (size_t)D.nsweep * D.ntiles);
       if (o.single_launch)  // swept tile by tile by one workgroup of the persistent kernel
@@ -1335,15 +1352,18 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     HIPCHK(launch_plan_tables(U, P->p, P->dbl, hs));  // every unit; also resets the counters
     tl.done();
   }
-  // the persistent small-unit kernels and the chain of batched sweep steps touch disjoint
-  // units: with both present, the small units run on the auxiliary stream, concurrently
-  const bool fork = !P->small.empty() && !P->groups.empty() && P->aux;
-  hipStream_t su = fork ? P->aux : hs;
+  // the persistent small-unit kernels (one per tile size, each with its own work counter)
+  // and the chain of batched sweep steps touch disjoint units: the small-unit launches run
+  // on one auxiliary stream beside the chain, or with small_streams each on its own
+  const bool fork = P->naux > 0;
   if (fork) {
     HIPCHK(hipEventRecord(P->ev_fork, hs));
-    HIPCHK(hipStreamWaitEvent(P->aux, P->ev_fork, 0));
+    for (int i = 0; i < P->naux; ++i) HIPCHK(hipStreamWaitEvent(P->aux[i], P->ev_fork, 0));
   }
-  for (const auto& sc : P->small) {
+  for (size_t i = 0; i < P->small.size(); ++i) {
+    const auto& sc = P->small[i];
+    const int ai = std::min((int)i, P->naux - 1);
+    hipStream_t su = fork ? P->aux[ai] : hs;
     LaunchUnits V = U;
     V.order = (const int32_t*)(P->ws + sc.order_off);
     V.counter = (int32_t*)(P->ws + P->counter_off) + sc.counter;
@@ -1352,7 +1372,8 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     HIPCHK(launch_units(V, P->grad, P->dbl, sc.L, sc.blocks, su));
     tl.done();
   }
-  if (fork) HIPCHK(hipEventRecord(P->ev_join, P->aux));
+  if (fork)
+    for (int i = 0; i < P->naux; ++i) HIPCHK(hipEventRecord(P->ev_join[i], P->aux[i]));
   for (const auto& Gp : P->groups) {
     LaunchBatch B;
     B.units = U.units;
@@ -1380,7 +1401,8 @@ aaq_status plan_launch(aaq_plan* P, const double* d_params, double* d_out, hipSt
     HIPCHK(launch_bsweep_out(B, d_out, 2 + 2 * P->p, P->grad, P->dbl, hs));
     tl.done();
   }
-  if (fork) HIPCHK(hipStreamWaitEvent(hs, P->ev_join, 0));
+  if (fork)
+    for (int i = 0; i < P->naux; ++i) HIPCHK(hipStreamWaitEvent(hs, P->ev_join[i], 0));
   return AAQ_OK;
 }
 
@@ -1653,6 +1675,7 @@ void aaq_plan_default_opts(aaq_plan_opts* o) {
   o->tile_bits_large = 0;
   o->min_tile_bits_small = 0;
   o->single_launch = 0;
+  o->small_streams = 0;
 }
 
 aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
@@ -1755,10 +1778,20 @@ aaq_status plan_create_impl(const aaq_problem* probs, int count, int p, aaq_obse
   P->progs_off = PL.progs;
   P->counter_off = PL.counter;
   for (int i = 0; i < count; ++i) P->tabmax = std::max(P->tabmax, PL.ud[i].cmax + 1);
-  if (!P->small.empty() && !P->groups.empty()) {  // fork / join of the small-unit launches
-    e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+  // fork / join of the small-unit launches (default-priority streams): one auxiliary
+  // stream beside the chain of batched sweep steps, or with small_streams one per launch
+  const int nsmall = (int)P->small.size();
+  const bool chain = !P->groups.empty();
+  if (o.small_streams && nsmall + (chain ? 1 : 0) >= 2 && nsmall <= aaq_plan::kMaxAux)
+    P->naux = nsmall;
+  else if (nsmall > 0 && chain)
+    P->naux = 1;
+  if (P->naux > 0) {
+    e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+    for (int i = 0; i < P->naux && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&P->aux[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join[i], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
       aaq_plan_destroy(P);
       return fail(AAQ_ERR_HIP, std::string("plan stream / events: ") + hipGetErrorString(e));
@@ -2105,6 +2138,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   std::vector<int> smalls = any_tiny ? std::vector<int>{10, 12, 13} : std::vector<int>{b0.min_tile_bits_small};
   std::vector<int> wgs = any_small ? std::vector<int>{0, device_cus(), 4 * device_cus()} : std::vector<int>{b0.workgroups};
   std::vector<int> singles = any_large ? std::vector<int>{0, 1} : std::vector<int>{b0.single_launch};
+  std::vector<int> streams = any_small ? std::vector<int>{0, 1} : std::vector<int>{b0.small_streams};
   hipStream_t hs = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -2116,6 +2150,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   aaq_status st = AAQ_OK;
   double bms = -1.0;
   aaq_plan_opts bo = b0;
+  for (int ss : streams)
   for (int sl : singles)
   for (int tl : larges)
     for (int ts : smalls)
@@ -2125,6 +2160,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
         o.min_tile_bits_small = ts;
         o.workgroups = wg;
         o.single_launch = sl;
+        o.small_streams = ss;
         size_t need = 0;
         if ((st = aaq_plan_workspace_size(probs, count, p, obs, with_grad, &o, &need))) goto done;
         if (need > ws_bytes) continue;  // this candidate does not fit the caller's workspace
@@ -2221,12 +2257,14 @@ void aaq_plan_destroy(aaq_plan* P) {
   if (!P) return;
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->graph) (void)hipGraphDestroy(P->graph);
-  if (P->aux) {
-    (void)hipStreamSynchronize(P->aux);
-    (void)hipStreamDestroy(P->aux);
+  for (int i = 0; i < aaq_plan::kMaxAux; ++i) {
+    if (P->aux[i]) {
+      (void)hipStreamSynchronize(P->aux[i]);
+      (void)hipStreamDestroy(P->aux[i]);
+    }
+    if (P->ev_join[i]) (void)hipEventDestroy(P->ev_join[i]);
   }
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   delete P;
 }
 

@@ -215,8 +215,10 @@ struct UnitDesc {
   int32_t T, cmax;
   int64_t part_off;    // byte offset of the per-tile partial sums [nsweep][6][ntiles] (n > L units)
   int64_t lam_off;     // byte offset of lambda, after the psi buffers (n > L units with gradients)
-  int32_t ntiles;      // tiles per sweep
+  int32_t ntiles;      // tiles per sweep (of the stored half with the half state)
   int32_t L;           // tile size (log2 amplitudes) of the unit's kernels
+  int32_t half;        // 1: the unit stores and sweeps the half state (n > L units only)
+  int32_t pad_;
   SetSpec sets[kMaxSets];
 };
 

@@ -230,7 +230,8 @@ template <class R> __global__ void k_bsweep_out(BatchArgs<R> A, double* out, int
         if (pg.mixB_grad && pg.mixB_layer == l) tot += 2.0 * slot_sum(s, SLOT_BB);
       }
     }
-    if (threadIdx.x == 0) o[oi] = tot;
+    // with the half state every sum covers one of each pair (z, ~z) of equal terms
+    if (threadIdx.x == 0) o[oi] = D->half ? 2.0 * tot : tot;
   }
 }
 

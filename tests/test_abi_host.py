@@ -146,6 +146,25 @@ def test_tile_sets_for_every_size_and_tile():
 def test_plan_workspace_size_host_only():
     probs = [prob(G.star(7)), prob(G.complete(9)), prob(G.prufer_tree(16, 2))]
     w = A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True)
-    # the n = 16 unit needs psi and lambda slices in the workspace
-    assert w > 2 * (8 << 16)
+    # the n = 16 unit (two tile sets, p = 2) keeps its p (k - 1) = 2 forward states and lambda,
+    # each over the stored half state of 2^15 amplitudes
+    assert w > 3 * (8 << 15)
+    assert A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, False) < w  # no lambda, no checkpoints
+    A.aaq_set_half_state(0)
+    try:
+        assert A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True) > 3 * (8 << 16)  # every amplitude stored
+    finally:
+        A.aaq_set_half_state(1)
     assert status_of(A.aaq_plan_workspace_size, probs, 0, A.AAQ_OBS_HRED, True) == 1
+    # plan options outside their ranges
+    for bad in ({"tile_bits_large": 11}, {"min_tile_bits_small": 14}, {"workgroups": -1}):
+        assert status_of(A.aaq_plan_workspace_size, probs, 2, A.AAQ_OBS_HRED, True, **bad) == 1
+    for field in ("small_streams", "single_launch"):
+        o = A.api._opts()
+        setattr(o, field, 2)
+        sz = ctypes.c_size_t()
+        st = _lib.lib().aaq_plan_workspace_size(A.api._problem_array(probs), len(probs), 2, A.AAQ_OBS_HRED, 1,
+                                                 ctypes.byref(o), ctypes.byref(sz))
+        assert st == 1, field
+    # the small-unit streams change the launches, not the workspace
+    assert A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True, small_streams=True) == w

@@ -454,6 +454,47 @@ def test_plan_matches_single_calls_and_oracle():
         plan.close()
 
 
+@pytest.mark.parametrize("prec", [A.AAQ_PREC_C64, A.AAQ_PREC_C128], ids=["c64", "c128"])
+@pytest.mark.parametrize("grad", [False, True], ids=["energy", "grad"])
+def test_plan_half_state_matches_full_state(prec, grad):
+    """Units above the tile size (two and three tile sets, n = 14 ... 23) store and sweep the
+    half state in a plan by default: every output equals the full-state plan's (half state
+    switched off) within the precision's tolerance, and both match the FP64 oracle."""
+    graphs = [G.random_regular(3, 14, seed=2), G.star(16), G.prufer_tree(18, 4), G.prufer_tree(21, 5),
+              rand_graph(23, 0.12, 4), G.complete(12)]
+    wps = [make_problem(g) for g in graphs]
+    units = [A.Problem.from_workload(w) for w in wps]
+    p = 2
+    rng = np.random.default_rng(41)
+    gam = rng.uniform(0, math.pi, (len(units), p))
+    bet = rng.uniform(0, math.pi / 2, (len(units), p))
+    prm = torch.from_numpy(np.concatenate([gam, bet], 1))
+    outs = {}
+    for half in (1, 0):
+        A.aaq_set_half_state(half)
+        try:
+            plan = A.Plan(units, p, OBS_HRED, with_grad=grad, use_graph=True, prec=prec)
+            plan.params.copy_(prm)
+            outs[half] = plan.execute().cpu().numpy()
+            plan.close()
+        finally:
+            A.aaq_set_half_state(1)
+    erel, grel = (EREL, GREL) if prec == A.AAQ_PREC_C64 else (1e-10, 1e-10)
+    for u, w in enumerate(wps):
+        if grad:
+            e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+        else:
+            e_ref = O.energy(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+        for half in (1, 0):
+            check_energy(outs[half][u, 0], e_ref, rel=erel)
+            assert abs(outs[half][u, 1] - 1) < (1e-5 if prec == A.AAQ_PREC_C64 else 1e-10)
+            if grad:
+                check_grad(outs[half][u, 2:], np.concatenate([dg_ref, db_ref]), rel=grel)
+        check_energy(outs[1][u, 0], outs[0][u, 0], rel=erel)
+        if grad:
+            check_grad(outs[1][u, 2:], outs[0][u, 2:], rel=grel)
+
+
 @pytest.mark.parametrize("obs", [OBS_HC, OBS_HRED], ids=["H_C", "H_red"])
 @pytest.mark.parametrize("grad", [False, True], ids=["energy", "grad"])
 def test_plan_groups_of_tile_sets(obs, grad):
@@ -484,11 +525,12 @@ def test_plan_groups_of_tile_sets(obs, grad):
     plan.close()
 
 
-@pytest.mark.parametrize("tl,ts,wg,sl", [(12, 10, 0, 0), (13, 13, 0, 0), (12, 12, 7, 0), (13, 10, 1, 0), (12, 10, 0, 1),
-                                         (13, 12, 3, 1)])
-def test_plan_tile_options_match_oracle(tl, ts, wg, sl):
-    """Tile sizes, workgroup counts and the single-launch mode (units with n > 13 swept tile
-    by tile inside the persistent kernel) against the oracle, with graph replays."""
+@pytest.mark.parametrize("tl,ts,wg,sl,ss", [(12, 10, 0, 0, 0), (13, 13, 0, 0, 0), (12, 12, 7, 0, 0), (13, 10, 1, 0, 0),
+                                            (12, 10, 0, 1, 0), (13, 12, 3, 1, 0), (12, 10, 0, 0, 1), (13, 10, 0, 1, 1)])
+def test_plan_tile_options_match_oracle(tl, ts, wg, sl, ss):
+    """Tile sizes, workgroup counts, the single-launch mode (units with n > 13 swept tile
+    by tile inside the persistent kernel) and the small-unit launches on streams of their
+    own against the oracle, with graph replays."""
     graphs = [G.prufer_tree(9, 1), G.star(11), G.complete(12), G.binary_tree(13), G.prufer_tree(16, 2),
               G.random_regular(3, 20, seed=5)]
     wps = [make_problem(g) for g in graphs]
@@ -498,7 +540,7 @@ def test_plan_tile_options_match_oracle(tl, ts, wg, sl):
     gam = rng.uniform(0, math.pi, (len(units), p))
     bet = rng.uniform(0, math.pi / 2, (len(units), p))
     plan = A.Plan(units, p, OBS_HRED, with_grad=True, tile_bits_large=tl, min_tile_bits_small=ts, workgroups=wg,
-                  single_launch=bool(sl))
+                  single_launch=bool(sl), small_streams=bool(ss))
     plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
     for rep in range(2):
         out = plan.execute().cpu().numpy()
