@@ -251,6 +251,10 @@ typedef struct {
   int small_streams;       /* 1 = each persistent small-unit launch (one per tile size) on a stream
                               of its own, concurrent with the others; 0 = all of them on one
                               stream beside the batched sweep steps (default) */
+  int max_small_n;         /* units with n <= this run in the persistent small-unit kernel, the
+                              others as batched sweep steps (13, or 12: 13-qubit units then take
+                              two 12-bit tiles); 0 = 12 when some unit has n > 13 and
+                              single_launch is 0 (the steps run anyway), else 13 (default) */
 } aaq_plan_opts;
 
 /* Fills opts with the defaults above. */
@@ -277,8 +281,9 @@ void aaq_plan_destroy(aaq_plan *plan);
 /* Plan autotuner: builds the plan with every candidate of tile_bits_large (12, 13; when
  * some unit has n > 13), min_tile_bits_small (10, 12, 13; when some unit has n <= 12),
  * workgroups (automatic, one and four per compute unit; when some unit has n <= 13) and
- * single_launch (0, 1; when some unit has n > 13) and small_streams (0, 1; when some unit has
- * n <= 13) on top of `base` (NULL = defaults),
+ * single_launch (0, 1; when some unit has n > 13), small_streams (0, 1; when some unit has
+ * n <= 13) and max_small_n (13, 12; when some unit has n = 13 and some n > 13) on top of
+ * `base` (NULL = defaults),
  * times `reps` executions of each with HIP
  * events on `stream` (after one warm-up execution) and returns the fastest options in
  * *best and their time per execution in *best_ms (may be NULL).  Candidates whose

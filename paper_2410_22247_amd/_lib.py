@@ -41,6 +41,7 @@ class CPlanOpts(ctypes.Structure):
         ("min_tile_bits_small", ctypes.c_int),
         ("single_launch", ctypes.c_int),
         ("small_streams", ctypes.c_int),
+        ("max_small_n", ctypes.c_int),
     ]
 
 

@@ -227,13 +227,14 @@ def aaq_num_sets(n: int, prec: int = AAQ_PREC_C64) -> int:
 
 
 def _opts(use_graph=True, workgroups=0, sort_units=True, prec=AAQ_PREC_C64, tile_bits_large=0,
-          min_tile_bits_small=0, single_launch=False, small_streams=False):
+          min_tile_bits_small=0, single_launch=False, small_streams=False, max_small_n=0):
     o = _lib.CPlanOpts()
     _lib.lib().aaq_plan_default_opts(ctypes.byref(o))
     o.use_graph, o.workgroups, o.sort_units, o.prec = int(use_graph), int(workgroups), int(sort_units), int(prec)
     o.tile_bits_large, o.min_tile_bits_small = int(tile_bits_large), int(min_tile_bits_small)
     o.single_launch = int(bool(single_launch))
     o.small_streams = int(bool(small_streams))
+    o.max_small_n = int(max_small_n)
     return o
 
 
@@ -241,7 +242,7 @@ def _opts_dict(o) -> dict:
     return {"use_graph": bool(o.use_graph), "workgroups": int(o.workgroups), "sort_units": bool(o.sort_units),
             "prec": int(o.prec), "tile_bits_large": int(o.tile_bits_large),
             "min_tile_bits_small": int(o.min_tile_bits_small), "single_launch": bool(o.single_launch),
-            "small_streams": bool(o.small_streams)}
+            "small_streams": bool(o.small_streams), "max_small_n": int(o.max_small_n)}
 
 
 def aaq_set_tile_bits(n: int, prec: int, with_grad: bool, tile_bits: int) -> None:

@@ -1158,6 +1158,8 @@ struct PlanLayout {
 
 // tile size of a unit under the plan options
 int unit_tile_bits(int n, const aaq_plan_opts& o) {
+  const int max_small = o.max_small_n > 0 ? o.max_small_n : kMaxUnitTile;
+  if (n > max_small && n <= kMaxUnitTile) return 12;  // more than one 12-bit tile: batched sweep steps
   if (n <= kMaxUnitTile) {
     const int lo = std::max(n, o.min_tile_bits_small > 0 ? o.min_tile_bits_small : kUnitTiles[0]);
     for (int L : kUnitTiles)
@@ -1176,6 +1178,8 @@ aaq_status check_opts(const aaq_plan_opts& o) {
   if (o.workgroups < 0) return fail(AAQ_ERR_INVALID_ARG, "workgroups must be >= 0");
   if (o.single_launch != 0 && o.single_launch != 1) return fail(AAQ_ERR_INVALID_ARG, "single_launch must be 0 or 1");
   if (o.small_streams != 0 && o.small_streams != 1) return fail(AAQ_ERR_INVALID_ARG, "small_streams must be 0 or 1");
+  if (o.max_small_n != 0 && o.max_small_n != 12 && o.max_small_n != 13)
+    return fail(AAQ_ERR_INVALID_ARG, "max_small_n must be 0, 12 or 13");
   return AAQ_OK;
 }
 
@@ -1206,6 +1210,14 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     bool half;  // the unit sweeps the half state (its last set's mirrored registers marked)
   };
   std::map<std::tuple<const int32_t*, int, int, const int32_t*, const int32_t*, const int32_t*, int>, GraphEntry> gmap;
+  // 13-qubit units join the batched sweep steps (two 12-bit tiles) when the plan runs such
+  // steps for larger units anyway, unless the options say otherwise
+  aaq_plan_opts oe = o;
+  if (oe.max_small_n == 0) {
+    bool any_large = false;
+    for (int i = 0; i < count; ++i) any_large = any_large || probs[i].n > kMaxUnitTile;
+    oe.max_small_n = (any_large && !o.single_launch) ? 12 : kMaxUnitTile;
+  }
   PL.ud.assign(count, UnitDesc{});
   PL.blob.clear();
   std::vector<std::vector<SweepProg>> progs(count);
@@ -1218,7 +1230,7 @@ aaq_status plan_layout(const aaq_problem* probs, int count, int p, aaq_observabl
     D.row = i;
     D.T = unit_terms ? (int)(*unit_terms)[i].size() : (obs == AAQ_OBS_HC) ? pr->num_edges : pr->num_orbits;
     D.cmax = total_weight(pr);
-    D.L = unit_tile_bits(pr->n, o);
+    D.L = unit_tile_bits(pr->n, oe);
     auto key = std::make_tuple(pr->edges, pr->n, pr->num_edges, pr->orbit_rep, pr->orbit_size, pr->edge_weight, (int)D.L);
     auto it = unit_terms ? gmap.end() : gmap.find(key);
     if (it == gmap.end()) {
@@ -1676,6 +1688,7 @@ void aaq_plan_default_opts(aaq_plan_opts* o) {
   o->min_tile_bits_small = 0;
   o->single_launch = 0;
   o->small_streams = 0;
+  o->max_small_n = 0;
 }
 
 aaq_status aaq_plan_workspace_size(const aaq_problem* probs, int count, int p, aaq_observable obs, int with_grad,
@@ -2128,17 +2141,19 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   aaq_plan_opts b0;
   aaq_plan_default_opts(&b0);
   if (base) b0 = *base;
-  bool any_large = false, any_small = false, any_tiny = false;
+  bool any_large = false, any_small = false, any_tiny = false, any_13 = false;
   for (int i = 0; i < count; ++i) {
     if (probs[i].n > kMaxUnitTile) any_large = true;
     else any_small = true;
     if (probs[i].n <= 12) any_tiny = true;
+    if (probs[i].n == kMaxUnitTile) any_13 = true;
   }
   std::vector<int> larges = any_large ? std::vector<int>{12, 13} : std::vector<int>{b0.tile_bits_large};
   std::vector<int> smalls = any_tiny ? std::vector<int>{10, 12, 13} : std::vector<int>{b0.min_tile_bits_small};
   std::vector<int> wgs = any_small ? std::vector<int>{0, device_cus(), 4 * device_cus()} : std::vector<int>{b0.workgroups};
   std::vector<int> singles = any_large ? std::vector<int>{0, 1} : std::vector<int>{b0.single_launch};
   std::vector<int> streams = any_small ? std::vector<int>{0, 1} : std::vector<int>{b0.small_streams};
+  std::vector<int> maxsmall = (any_13 && any_large) ? std::vector<int>{13, 12} : std::vector<int>{b0.max_small_n};
   hipStream_t hs = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
@@ -2150,6 +2165,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
   aaq_status st = AAQ_OK;
   double bms = -1.0;
   aaq_plan_opts bo = b0;
+  for (int ms : maxsmall)
   for (int ss : streams)
   for (int sl : singles)
   for (int tl : larges)
@@ -2161,6 +2177,7 @@ aaq_status aaq_plan_autotune(const aaq_problem* probs, int count, int p, aaq_obs
         o.workgroups = wg;
         o.single_launch = sl;
         o.small_streams = ss;
+        o.max_small_n = ms;
         size_t need = 0;
         if ((st = aaq_plan_workspace_size(probs, count, p, obs, with_grad, &o, &need))) goto done;
         if (need > ws_bytes) continue;  // this candidate does not fit the caller's workspace

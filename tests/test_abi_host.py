@@ -157,7 +157,7 @@ def test_plan_workspace_size_host_only():
         A.aaq_set_half_state(1)
     assert status_of(A.aaq_plan_workspace_size, probs, 0, A.AAQ_OBS_HRED, True) == 1
     # plan options outside their ranges
-    for bad in ({"tile_bits_large": 11}, {"min_tile_bits_small": 14}, {"workgroups": -1}):
+    for bad in ({"tile_bits_large": 11}, {"min_tile_bits_small": 14}, {"workgroups": -1}, {"max_small_n": 11}):
         assert status_of(A.aaq_plan_workspace_size, probs, 2, A.AAQ_OBS_HRED, True, **bad) == 1
     for field in ("small_streams", "single_launch"):
         o = A.api._opts()
@@ -168,3 +168,13 @@ def test_plan_workspace_size_host_only():
         assert st == 1, field
     # the small-unit streams change the launches, not the workspace
     assert A.aaq_plan_workspace_size(probs, 2, A.AAQ_OBS_HRED, True, small_streams=True) == w
+    # a 13-qubit unit as batched sweep steps needs its states in the workspace; beside a
+    # larger unit that is the default, alone it is not
+    p13 = [prob(G.binary_tree(13)), prob(G.prufer_tree(16, 2))]
+    w13 = A.aaq_plan_workspace_size(p13, 2, A.AAQ_OBS_HRED, True, max_small_n=13)
+    w12 = A.aaq_plan_workspace_size(p13, 2, A.AAQ_OBS_HRED, True, max_small_n=12)
+    assert w12 > w13 + 2 * (8 << 12)
+    assert A.aaq_plan_workspace_size(p13, 2, A.AAQ_OBS_HRED, True) == w12
+    alone = [prob(G.binary_tree(13))]
+    assert A.aaq_plan_workspace_size(alone, 2, A.AAQ_OBS_HRED, True) == \
+        A.aaq_plan_workspace_size(alone, 2, A.AAQ_OBS_HRED, True, max_small_n=13)

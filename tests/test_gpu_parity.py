@@ -525,12 +525,15 @@ def test_plan_groups_of_tile_sets(obs, grad):
     plan.close()
 
 
-@pytest.mark.parametrize("tl,ts,wg,sl,ss", [(12, 10, 0, 0, 0), (13, 13, 0, 0, 0), (12, 12, 7, 0, 0), (13, 10, 1, 0, 0),
-                                            (12, 10, 0, 1, 0), (13, 12, 3, 1, 0), (12, 10, 0, 0, 1), (13, 10, 0, 1, 1)])
-def test_plan_tile_options_match_oracle(tl, ts, wg, sl, ss):
+@pytest.mark.parametrize("tl,ts,wg,sl,ss,ms", [(12, 10, 0, 0, 0, 0), (13, 13, 0, 0, 0, 0), (12, 12, 7, 0, 0, 0),
+                                               (13, 10, 1, 0, 0, 0), (12, 10, 0, 1, 0, 0), (13, 12, 3, 1, 0, 0),
+                                               (12, 10, 0, 0, 1, 0), (13, 10, 0, 1, 1, 0), (12, 10, 0, 0, 0, 12),
+                                               (13, 12, 0, 0, 1, 12), (12, 10, 0, 1, 0, 12)])
+def test_plan_tile_options_match_oracle(tl, ts, wg, sl, ss, ms):
     """Tile sizes, workgroup counts, the single-launch mode (units with n > 13 swept tile
-    by tile inside the persistent kernel) and the small-unit launches on streams of their
-    own against the oracle, with graph replays."""
+    by tile inside the persistent kernel), the small-unit launches on streams of their own
+    and the 13-qubit unit as batched sweep steps over two 12-bit tiles (max_small_n = 12)
+    against the oracle, with graph replays."""
     graphs = [G.prufer_tree(9, 1), G.star(11), G.complete(12), G.binary_tree(13), G.prufer_tree(16, 2),
               G.random_regular(3, 20, seed=5)]
     wps = [make_problem(g) for g in graphs]
@@ -540,7 +543,7 @@ def test_plan_tile_options_match_oracle(tl, ts, wg, sl, ss):
     gam = rng.uniform(0, math.pi, (len(units), p))
     bet = rng.uniform(0, math.pi / 2, (len(units), p))
     plan = A.Plan(units, p, OBS_HRED, with_grad=True, tile_bits_large=tl, min_tile_bits_small=ts, workgroups=wg,
-                  single_launch=bool(sl), small_streams=bool(ss))
+                  single_launch=bool(sl), small_streams=bool(ss), max_small_n=ms)
     plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
     for rep in range(2):
         out = plan.execute().cpu().numpy()
