@@ -190,14 +190,15 @@ def c4(args):
     probs, p, gam, bet = C.config4()
     prs = [A.Problem.from_workload(w) for w in probs]
     prm = np.concatenate([gam, bet], 1)
-    plan = A.Plan.autotuned(prs, p, A.AAQ_OBS_HRED, True, params=prm, reps=3)
+    # every candidate timed over 20 replays (a replay takes about 0.3 ms)
+    plan = A.Plan.autotuned(prs, p, A.AAQ_OBS_HRED, True, params=prm, reps=20)
     plan.params.copy_(torch.from_numpy(prm))
-    dt = _timed(plan.execute, 5)
+    dt = _timed(plan.execute, 20)
     out = plan.execute().cpu().numpy()
     tuned = plan.tuned_opts
     plan.close()
     rate = len(prs) / dt
-    default_rate, _ = _plan_rate(prs, p, A.AAQ_OBS_HRED, True, gam, bet, reps=5)
+    default_rate, _ = _plan_rate(prs, p, A.AAQ_OBS_HRED, True, gam, bet, reps=20)
     single_rate, out_single = _plan_rate(prs, p, A.AAQ_OBS_HRED, True, gam, bet, reps=3, single_launch=True)
     # plain: one aaq_energy_grad call per graph
     ests = {}
