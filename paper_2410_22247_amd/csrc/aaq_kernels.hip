@@ -197,42 +197,57 @@ __device__ void stage_and_build_scales(ScaleStage& S, const SweepProg* progs, in
 }
 
 
+// Each wave sums one (sweep, slot) partial of the unit over its tiles (lanes stride the
+// tiles, then a fixed butterfly), with no workgroup barrier per sum; thread 0 then adds the
+// pair sums into the outputs in (sweep, slot) order, the order of the sweeps for every
+// output, so the result does not depend on scheduling.
 template <class R> __global__ void k_bsweep_out(BatchArgs<R> A, double* out, int out_stride, int grad) {
-  __shared__ double red[4];
+  constexpr int kChunk = 64;  // (sweep, slot) pairs per round
+  __shared__ double ps[kChunk];
+  __shared__ double tot[2 + 2 * kMaxP];
   const int u = A.list[blockIdx.x];
   const UnitDesc* D = A.units + u;
-  const int p = D->p, nt = D->ntiles;
+  const int p = D->p, nt = D->ntiles, nout = 2 + 2 * p;
   double* o = out + (size_t)D->row * out_stride;
   const double* part = reinterpret_cast<const double*>(A.ws + D->part_off);
-  auto slot_sum = [&](int s, int slot) -> double {
-    double v = 0.0;
-    for (int t = threadIdx.x; t < nt; t += blockDim.x) v += part[((size_t)s * 6 + slot) * nt + t];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    const double r = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
-    return r;
+  const SweepProg* progs = A.progs + D->prog_off;
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) tot[i] = 0.0;
+  // the output a sweep's slot adds to (-1: the sweep does not fill that slot)
+  auto target = [&](const SweepProg& pg, int slot) -> int {
+    switch (slot) {
+      case SLOT_E:
+      case SLOT_NORM: return ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) ? slot : -1;
+      case SLOT_GPRE: return (grad && (pg.pre_ops & OP_GRADG)) ? 2 + pg.pre_layer : -1;
+      case SLOT_GMID: return (grad && (pg.mid_ops & OP_GRADG)) ? 2 + pg.mid_layer : -1;
+      case SLOT_BA: return (grad && pg.mixA_grad) ? 2 + p + pg.mixA_layer : -1;
+      default: return (grad && pg.mixB_grad) ? 2 + p + pg.mixB_layer : -1;
+    }
   };
-  for (int oi = 0; oi < 2 + 2 * p; ++oi) {
-    double tot = 0.0;
-    for (int s = 0; s < D->nsweep; ++s) {
-      const SweepProg pg = A.progs[D->prog_off + s];
-      if (oi < 2) {
-        if ((pg.pre_ops | pg.mid_ops) & OP_ENERGY) tot += slot_sum(s, oi);
-      } else if (grad && oi < 2 + p) {
-        const int l = oi - 2;
-        if ((pg.pre_ops & OP_GRADG) && pg.pre_layer == l) tot += 2.0 * slot_sum(s, SLOT_GPRE);
-        if ((pg.mid_ops & OP_GRADG) && pg.mid_layer == l) tot += 2.0 * slot_sum(s, SLOT_GMID);
-      } else if (grad) {
-        const int l = oi - 2 - p;
-        if (pg.mixA_grad && pg.mixA_layer == l) tot += 2.0 * slot_sum(s, SLOT_BA);
-        if (pg.mixB_grad && pg.mixB_layer == l) tot += 2.0 * slot_sum(s, SLOT_BB);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int npairs = 6 * D->nsweep;
+  for (int c0 = 0; c0 < npairs; c0 += kChunk) {
+    for (int q = wave; q < kChunk && c0 + q < npairs; q += nw) {
+      const int s = (c0 + q) / 6, slot = (c0 + q) % 6;
+      double v = 0.0;
+      if (target(progs[s], slot) >= 0) {
+        for (int t = lane; t < nt; t += 64) v += part[((size_t)s * 6 + slot) * nt + t];
+        v = wave_sum(v);
+      }
+      if (lane == 0) ps[q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < kChunk && c0 + q < npairs; ++q) {
+        const int s = (c0 + q) / 6, slot = (c0 + q) % 6;
+        const int oi = target(progs[s], slot);
+        if (oi >= 0) tot[oi] += (slot >= SLOT_GPRE ? 2.0 : 1.0) * ps[q];
       }
     }
-    // with the half state every sum covers one of each pair (z, ~z) of equal terms
-    if (threadIdx.x == 0) o[oi] = D->half ? 2.0 * tot : tot;
+    __syncthreads();
   }
+  // with the half state every sum covers one of each pair (z, ~z) of equal terms
+  const double hs = D->half ? 2.0 : 1.0;
+  for (int i = threadIdx.x; i < nout; i += blockDim.x) o[i] = hs * tot[i];
 }
 
 
