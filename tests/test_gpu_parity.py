@@ -495,6 +495,30 @@ def test_plan_half_state_matches_full_state(prec, grad):
             check_grad(outs[1][u, 2:], outs[0][u, 2:], rel=grel)
 
 
+@pytest.mark.parametrize("p", [8, 40], ids=["p8-checkpoints", "p40-uncompute"])
+def test_plan_depth_checkpoints_and_uncompute(p):
+    """Plan units above the tile size keep their forward states while there are at most 32
+    of them (p = 8, two tile sets: 8 checkpoints) and otherwise uncompute psi in the
+    backward steps (p = 40: 40 would be needed), both in the half state: energy, norm and
+    gradient against the FP64 oracle."""
+    graphs = [G.prufer_tree(16, 7), G.random_regular(3, 14, seed=9), G.prufer_tree(11, 2)]
+    wps = [make_problem(g) for g in graphs]
+    units = [A.Problem.from_workload(w) for w in wps]
+    assert A.aaq_num_sets(16) == 2
+    rng = np.random.default_rng(p)
+    gam = rng.uniform(0, 0.3, (len(units), p))
+    bet = rng.uniform(0, 0.3, (len(units), p))
+    plan = A.Plan(units, p, OBS_HRED, with_grad=True, use_graph=True)
+    plan.params.copy_(torch.from_numpy(np.concatenate([gam, bet], 1)))
+    out = plan.execute().cpu().numpy()
+    plan.close()
+    for u, w in enumerate(wps):
+        e_ref, dg_ref, db_ref = O.energy_grad(w.n, w.edges(), w.terms(OBS_HRED), gam[u], bet[u])
+        check_energy(out[u, 0], e_ref)
+        assert abs(out[u, 1] - 1) < 1e-5
+        check_grad(out[u, 2:], np.concatenate([dg_ref, db_ref]))
+
+
 @pytest.mark.parametrize("obs", [OBS_HC, OBS_HRED], ids=["H_C", "H_red"])
 @pytest.mark.parametrize("grad", [False, True], ids=["energy", "grad"])
 def test_plan_groups_of_tile_sets(obs, grad):
