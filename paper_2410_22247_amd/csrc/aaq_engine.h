@@ -600,7 +600,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
   // energy step created lambda.
   // COPS: the ops at this position, a compile-time mask (the program's own ops are
   // passed for reference only).
-  template <int K, bool LAM, uint32_t COPS>
+  // W: integer edge weights, the cut from the set's cost-term lists (compile-time)
+  template <int K, bool LAM, uint32_t COPS, bool W = false>
   __device__ __forceinline__ void ops_at(uint8_t /*ops_rt*/, bool make_lam, const SetSpec& S, uint64_t tile_base,
                                          uint64_t F, const Ctx<R>& cx, const V* ltab, double& gacc, Acc& acc,
                                          double* zz_lds) {
@@ -639,7 +640,10 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     }
     if (ops & (OP_GRADG | OP_PHASE | OP_UNPHASE)) {
       int cv[NR];
-      cuts<K>(S, zb, tile_base ^ F, F, cx.g, cv);
+      if constexpr (W)
+        wcuts<K>(S, zb, cx.terms, cv, cst(cx.g)->n <= 32);
+      else
+        cuts<K>(S, zb, tile_base ^ F, F, cx.g, cv);
       if constexpr (NS == 2 && LAM) {
         if (ops & OP_GRADG) {
           R gs = R(0);
@@ -974,7 +978,8 @@ template <class R, int NS, bool EN, int LT> struct Tile {
     constexpr bool PSI_DEAD = (KIND & SK_PSI_DEAD) != 0;
     constexpr bool A_LAST = sk_mid(KIND) == 0 && (KIND & SK_MIXB) == 0;  // nothing after mixer A
     static_assert(!PSI_DEAD || NS == 2, "only two-state sweeps leave psi unstored");
-    ops_at<KL, LAM0, sk_pre(KIND)>(pg.pre_ops, false, S, tile_base, scp->F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
+    constexpr bool W = (KIND & SK_WEIGHTED) != 0;
+    ops_at<KL, LAM0, sk_pre(KIND), W>(pg.pre_ops, false, S, tile_base, scp->F_pre, cx, ltab_pre, acc.gpre, acc, zz_lds);
     bool at_p = false;
     if constexpr ((KIND & SK_MIXA) != 0) {
       R gs = R(0);
@@ -986,7 +991,7 @@ template <class R, int NS, bool EN, int LT> struct Tile {
       xchg<LAST, P, LAM0, half_xchg(RT)>(lds_x);
       at_p = true;
     }
-    ops_at<P, LAM0, sk_mid(KIND)>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, scp->F_mid, cx, ltab_mid,
+    ops_at<P, LAM0, sk_mid(KIND), W>(pg.mid_ops, (KIND & SK_MAKE_LAM) != 0, S, tile_base, scp->F_mid, cx, ltab_mid,
                                   acc.gmid, acc, zz_lds);
     constexpr bool LAM1 = LAM0 || (NS == 2 && (KIND & SK_MAKE_LAM) != 0);
     if constexpr ((KIND & SK_MIXB) != 0) {
@@ -1635,32 +1640,49 @@ static void sweep_launch_kind(const SweepArgs<R>& A, dim3 grid, dim3 blk, size_t
   launch((k_sweep<R, NS, PT, EN, RT, LT, KIND>), grid, blk, dyn, st, A);
 }
 
+// the specialised shape of a sweep (WB: SK_WEIGHTED for the weighted copies, which leave
+// the per-term shape to the run-time path); false when none applies
+template <class R, int RT, int LT, uint32_t WB>
+static bool sweep_launch_shape(uint32_t kind, const SweepArgs<R>& A, dim3 grid, dim3 blk, size_t dyn, hipStream_t st) {
+  switch (kind) {
+    case SK_F_FIRST: sweep_launch_kind<R, RT, LT, SK_F_FIRST | WB>(A, grid, blk, dyn, st); return true;
+    case SK_F_PLAIN: sweep_launch_kind<R, RT, LT, SK_F_PLAIN | WB>(A, grid, blk, dyn, st); return true;
+    case SK_F_BOUNDARY: sweep_launch_kind<R, RT, LT, SK_F_BOUNDARY | WB>(A, grid, blk, dyn, st); return true;
+    case SK_F_ENERGY: sweep_launch_kind<R, RT, LT, SK_F_ENERGY | WB>(A, grid, blk, dyn, st); return true;
+    case SK_F_ENERGY_TERMS:
+      if constexpr (WB != 0) return false;
+      else sweep_launch_kind<R, RT, LT, SK_F_ENERGY_TERMS>(A, grid, blk, dyn, st);
+      return true;
+    case SK_TURNAROUND: sweep_launch_kind<R, RT, LT, SK_TURNAROUND | WB>(A, grid, blk, dyn, st); return true;
+    case SK_B_PLAIN: sweep_launch_kind<R, RT, LT, SK_B_PLAIN | WB>(A, grid, blk, dyn, st); return true;
+    case SK_B_BOUNDARY: sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY | WB>(A, grid, blk, dyn, st); return true;
+    case SK_B_LAST: sweep_launch_kind<R, RT, LT, SK_B_LAST | WB>(A, grid, blk, dyn, st); return true;
+    case SK_B_PLAIN_PD: sweep_launch_kind<R, RT, LT, SK_B_PLAIN_PD | WB>(A, grid, blk, dyn, st); return true;
+    // on the full route (set 0, which takes the turnaround and layer boundaries only with
+    // two tile sets) the lambda-only last stop spills registers in some instantiations:
+    // those sweeps keep psi's gates there
+    case SK_TURNAROUND_PD:
+      if constexpr (RT == ROUTE_FULL) sweep_launch_kind<R, RT, LT, SK_TURNAROUND | WB>(A, grid, blk, dyn, st);
+      else sweep_launch_kind<R, RT, LT, SK_TURNAROUND_PD | WB>(A, grid, blk, dyn, st);
+      return true;
+    case SK_B_BOUNDARY_PD:
+      if constexpr (RT == ROUTE_FULL) sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY | WB>(A, grid, blk, dyn, st);
+      else sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY_PD | WB>(A, grid, blk, dyn, st);
+      return true;
+    default: return false;
+  }
+}
+
 template <class R, int RT, int LT>
 static void sweep_launch_rt(const SweepArgs<R>& A, const LaunchSweep& L, size_t dyn, hipStream_t st) {
   const bool pt = ((L.prog.pre_ops | L.prog.mid_ops) & OP_PERTERM) != 0;
   const bool en = ((L.prog.pre_ops | L.prog.mid_ops) & OP_ENERGY) != 0;
   const dim3 grid(L.set.ntiles >> (L.half ? 1 : 0)), blk(Geo<R, LT>::NT);
-  switch (L.generic ? SK_GENERIC : sweep_kind(L.prog)) {
-    case SK_F_FIRST: return sweep_launch_kind<R, RT, LT, SK_F_FIRST>(A, grid, blk, dyn, st);
-    case SK_F_PLAIN: return sweep_launch_kind<R, RT, LT, SK_F_PLAIN>(A, grid, blk, dyn, st);
-    case SK_F_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_F_BOUNDARY>(A, grid, blk, dyn, st);
-    case SK_F_ENERGY: return sweep_launch_kind<R, RT, LT, SK_F_ENERGY>(A, grid, blk, dyn, st);
-    case SK_F_ENERGY_TERMS: return sweep_launch_kind<R, RT, LT, SK_F_ENERGY_TERMS>(A, grid, blk, dyn, st);
-    case SK_TURNAROUND: return sweep_launch_kind<R, RT, LT, SK_TURNAROUND>(A, grid, blk, dyn, st);
-    case SK_B_PLAIN: return sweep_launch_kind<R, RT, LT, SK_B_PLAIN>(A, grid, blk, dyn, st);
-    case SK_B_BOUNDARY: return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY>(A, grid, blk, dyn, st);
-    case SK_B_LAST: return sweep_launch_kind<R, RT, LT, SK_B_LAST>(A, grid, blk, dyn, st);
-    case SK_B_PLAIN_PD: return sweep_launch_kind<R, RT, LT, SK_B_PLAIN_PD>(A, grid, blk, dyn, st);
-    // on the full route (set 0, which takes the turnaround and layer boundaries only with
-    // two tile sets) the lambda-only last stop spills registers in some instantiations:
-    // those sweeps keep psi's gates there
-    case SK_TURNAROUND_PD:
-      if constexpr (RT == ROUTE_FULL) return sweep_launch_kind<R, RT, LT, SK_TURNAROUND>(A, grid, blk, dyn, st);
-      else return sweep_launch_kind<R, RT, LT, SK_TURNAROUND_PD>(A, grid, blk, dyn, st);
-    case SK_B_BOUNDARY_PD:
-      if constexpr (RT == ROUTE_FULL) return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY>(A, grid, blk, dyn, st);
-      else return sweep_launch_kind<R, RT, LT, SK_B_BOUNDARY_PD>(A, grid, blk, dyn, st);
-    default: break;
+  if (!L.generic) {
+    const uint32_t kind = sweep_kind(L.prog);
+    if (L.weighted ? sweep_launch_shape<R, RT, LT, SK_WEIGHTED>(kind, A, grid, blk, dyn, st)
+                   : sweep_launch_shape<R, RT, LT, 0u>(kind, A, grid, blk, dyn, st))
+      return;
   }
   if (pt)
     launch((k_sweep<R, 1, true, true, RT, LT, SK_GENERIC>), grid, blk, dyn, st, A);

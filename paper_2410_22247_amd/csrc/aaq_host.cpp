@@ -936,7 +936,7 @@ aaq_status launch_eval(const Single& S, bool grad, void* d_state, void* d_lam, u
     A.set = S.sets[S.progs[sw].set];
     A.prog = S.progs[sw];
     A.two_states = needs_two_states(S.progs[sw]);
-    A.generic = weighted;
+    A.weighted = weighted;  // the weighted copies of the specialised shapes
     A.half = S.half;
     // non-temporal loads unless the whole evaluation is one state that fits the 256 MB
     // last-level cache (in-place energy sweeps then reuse it from sweep to sweep)

@@ -65,6 +65,7 @@ enum : uint32_t {
   SK_MIXB = 1u << 4,
   SK_MAKE_LAM = 1u << 5,  // the energy step creates lambda
   SK_PSI_DEAD = 1u << 6,  // psi is not stored after the last mixer (lambda alone is)
+  SK_WEIGHTED = 1u << 7,  // integer edge weights: the cut from the set's cost-term lists
   SK_GENERIC = 1u << 31
 };
 constexpr uint32_t sk_pre(uint32_t kind) { return (kind >> 8) & 0xFFu; }

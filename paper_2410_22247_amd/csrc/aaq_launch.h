@@ -59,7 +59,8 @@ struct LaunchSweep {
   SetSpec set;
   SweepProg prog;
   bool two_states;
-  bool generic = false;  // take every step from the program at run time (weighted instances)
+  bool generic = false;   // take every step from the program at run time
+  bool weighted = false;  // integer edge weights (the specialised shapes' weighted copies)
   bool half = false;     // half state: the grid covers the tiles below ntiles / 2
   bool nt = true;        // non-temporal state loads
 };
