@@ -93,8 +93,10 @@ enum { AAQ_PREC_C64 = 0, AAQ_PREC_C128 = 1 };
  *               weight-preserving automorphisms (aaq_edge_orbits with the same weights);
  *               with edge_orbit given, equal weights inside every orbit are checked.
  *               H_C's terms carry w_ij, H_red's the orbit size times the
- *               representative's weight.  Weighted instances run the sweeps whose steps
- *               are taken from the sweep program at run time. */
+ *               representative's weight.  Single-instance evaluations of weighted
+ *               instances run weighted copies of the specialised sweeps (the cut taken
+ *               from per-set cost-term lists); weighted plan units and light cones run
+ *               the sweeps whose steps are taken from the sweep program at run time. */
 #define AAQ_MAX_COST 561
 typedef struct {
   int32_t n;

@@ -665,7 +665,7 @@ constexpr int kZZBlocks = 1024;
 struct Single {
   int n, p, T, cmax, L, k, nbuf;
   bool dbl, grad;
-  bool weighted = false;  // integer edge weights: the sweeps take the run-time path
+  bool weighted = false;  // integer edge weights: the sweeps cut from the per-set cost-term lists
   bool half = false;      // half state (spin-flip symmetry): 2^(n-1) stored amplitudes
   aaq_aggregation agg;
   std::vector<SetSpec> sets;
